@@ -1,0 +1,156 @@
+"""Throughput of the colour-gradient + reaction-limited evaporation step on one MI355X.
+
+Default workload: D3Q19 256^3 periodic box, spherical drop R = 64 (tanh width 2),
+unit density ratio, tau = 1, sigma = 4A/9 with A = 5e-4, beta = 0.7, phi = 1e-5,
+Gamma = 0.305, Sbar = 3; populations in FP32 shifted storage.  A step is one full time
+step (sink, sites, moments, gradient, collision, perturbation, recolouring, streaming).
+
+Prints one JSON line: MLUPS (whole job), ms/step, the roofline of the step kernel
+(algorithmic bytes per launch / average launch time measured with HIP events on the
+stream the library launches on), FP64 and FP16S legs, and the FP64 CPU oracle timed on a
+bounded sample of the same workload (cpu_baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
+
+
+def algorithmic_bytes_per_node(Q, precision, walls=False, phi_field=False):
+    """Populations read once and written once (2 components x Q), the site mask byte read
+    and written, the flux field read when bound, the solid flag read when walls exist."""
+    elem = {"fp64": 8, "fp32s": 4, "fp16s": 2}[precision]
+    return 2 * Q * 2 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
+
+
+def run_leg(workload, precision, steps, warmup, kernel="auto"):
+    import torch
+    from paper_2412_14859_amd import cgevap
+    w = workload
+    p = w["params"]
+    sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                            phi_field=w["phi_field"], precision=precision, kernel=kernel)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ker_ms, ker_steps = sim.timing()
+    sim.set_timing(False)
+    obs = sim.observables()
+    N = 1
+    for s in p["shape"]:
+        N *= s
+    bpn = algorithmic_bytes_per_node(p["Q"], precision, w["solid"] is not None,
+                                     w["phi_field"] is not None)
+    per_launch_ms = ker_ms / max(ker_steps, 1)
+    res = {
+        "precision": precision,
+        "kernel": sim.kernel_name(),
+        "mlups": N * steps / wall / 1e6,
+        "ms_per_step": wall * 1e3 / steps,
+        "kernel_ms_per_step": per_launch_ms,
+        "bytes_per_node": bpn,
+        "achieved_gbs": bpn * N / (per_launch_ms * 1e-3) / 1e9,
+        "v_mass": obs["v_mass"],
+        "site_steps": obs["site_steps"],
+        "n_negative": obs["n_negative"],
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(seconds_hint=15.0):
+    """The FP64 oracle (single thread) on a bounded sample of the workload: the same drop
+    scaled to 64^3 (R = 16), a fixed number of steps."""
+    from oracle.oracle import Oracle  # cpu_baseline leg only
+    from paper_2412_14859_amd import inputs
+    w = inputs.workload("sphere3d", shape=(64, 64, 64), radius=16.0)
+    o = Oracle(w["params"])
+    o.init_equilibrium(w["rho_r"], w["rho_b"])
+    o.step(1)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds_hint:
+        o.step(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": 64 ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"D3Q19 64^3 drop R=16 (the 256^3 workload scaled 1/4), {steps} steps, "
+                      "FP64, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp32s", choices=["fp64", "fp32s", "fp16s"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused"])
+    ap.add_argument("--size", type=int, default=256, help="edge of the cubic box")
+    ap.add_argument("--no-legs", action="store_true", help="skip the FP64 and FP16S legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the slab-halo design is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_14859_amd import inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.size
+    w = inputs.workload("sphere3d", shape=(n, n, n), radius=64.0 * n / 256)
+    main_leg = run_leg(w, args.precision, args.steps, args.warmup, args.kernel)
+    legs = {}
+    if not args.no_legs:
+        for prec in ("fp64", "fp16s"):
+            if prec != args.precision:
+                legs[prec] = run_leg(w, prec, max(args.steps // 2, 10), args.warmup, args.kernel)
+    N = n ** 3
+    achieved = main_leg["achieved_gbs"]
+    out = {
+        "metric": "MLUPS (D3Q19 CG + reaction-limited evaporation step)",
+        "value": round(main_leg["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_leg["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32s": "f32", "fp64": "f64", "fp16s": "f16-storage/f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 {n}^3 periodic, spherical drop R={64 * n // 256}, "
+                               "unit density ratio, tau=1, A=5e-4, beta=0.7, phi=1e-5, "
+                               "Gamma=0.305, Sbar=3",
+                   "nodes": N, "precision": args.precision, "kernel": main_leg["kernel"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "kernel": main_leg["kernel"],
+                     "kernel_ms_per_launch": round(main_leg["kernel_ms_per_step"], 4),
+                     "bytes_per_node": main_leg["bytes_per_node"]},
+        "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                 for k, v in legs.items()},
+    }
+    if not args.no_cpu:
+        cb = cpu_baseline()
+        out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v)
+                               for k, v in cb.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

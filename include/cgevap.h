@@ -1,0 +1,177 @@
+/*
+ * cgevap.h -- C-ABI of libcgevap.so: the time step of the two-component colour-gradient
+ * lattice Boltzmann model with the reaction-limited evaporation sink of
+ * Nath, Aouane & Harting, arXiv:2412.14859, on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a cge_status (0 = CGE_OK, < 0 = error) and never aborts or
+ *     throws.  After an error, cge_last_error(ctx) holds a message (valid until the next
+ *     call on that context).  Parameter errors are detected on the host before any device
+ *     work, so they are testable without a GPU.
+ *   - Large buffers are caller-owned DEVICE pointers (e.g. torch tensors on the GPU);
+ *     the library allocates only its own scratch (phase-field work array, reduction
+ *     partials) at cge_create and frees it at cge_destroy.
+ *   - All device work is enqueued on the HIP stream given at cge_create, in order.
+ *     Entry points that return host data (cge_observables, cge_timing) synchronise that
+ *     stream; all others are asynchronous.
+ *   - Node index n = x + nx*(y + ny*z); scalar fields are [nz][ny][nx], vector fields
+ *     [D][nz][ny][nx], exported populations [2][Q][nz][ny][nx] with component 0 = red
+ *     (the evaporating fluid) and component 1 = blue.  All axes are periodic; walls and
+ *     obstacles are solid nodes given by the flags array.
+ *   - Lattice directions (D2Q9):  0; +x; -x; +y; -y; (1,1); (-1,-1); (1,-1); (-1,1).
+ *     (D3Q19): 0; +x; -x; +y; -y; +z; -z; then the xy, xz and yz diagonals, each in the
+ *     order (+,+), (-,-), (+,-), (-,+).
+ */
+#ifndef CGEVAP_H
+#define CGEVAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CGE_OK = 0,
+    CGE_EINVAL = -1,       /* invalid argument or parameter                       */
+    CGE_ENOMEM = -2,       /* device allocation of library scratch failed          */
+    CGE_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed           */
+    CGE_ESTATE = -4,       /* call out of order (e.g. step before cge_bind)        */
+    CGE_EUNSUPPORTED = -5, /* valid but not supported combination                  */
+    CGE_ENUMERIC = -6      /* non-finite values found in the state                 */
+} cge_status;
+
+typedef enum { CGE_D2Q9 = 9, CGE_D3Q19 = 19 } cge_lattice;
+
+/* Population storage.  FP64: doubles, FP64 arithmetic.  FP32S: floats holding shifted
+ * values (see cge_bind), FP32 arithmetic.  FP16S: half-precision storage of the same
+ * shifted values with FP32 arithmetic and stochastic rounding on store. */
+typedef enum { CGE_FP64 = 0, CGE_FP32S = 1, CGE_FP16S = 2 } cge_precision;
+
+/* Evaporation-site rule.  GRAD_GT: ||F_{n-1}(x)|| > gamma with the colour gradient of the
+ * previous step (Sec. II.B, site criterion and the remark after the method summary).
+ * PHASE_LT: |rho^N(x)| < gamma from the current pre-sink phase field (a local variant). */
+typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1 } cge_site_rule;
+
+/* Step implementation.  AUTO picks the fastest supported one. */
+typedef enum { CGE_KERNEL_AUTO = 0, CGE_KERNEL_TWOPASS = 1, CGE_KERNEL_FUSED = 2 } cge_kernel;
+
+typedef struct {
+    int lattice;            /* cge_lattice                                               */
+    int nx, ny, nz;         /* nodes per axis, >= 1 (>= 3 on every axis longer than 1);  */
+                            /* nz == 1 for D2Q9                                          */
+    int precision;          /* cge_precision                                             */
+    double rho_in[2];       /* bulk densities of red and blue; define alpha_k (Sec. II.A) */
+    double tau[2];          /* relaxation times, > 1/2 (Sec. II.A)                        */
+    double sigma;           /* surface tension in the perturbation operator (Eq. perturb) */
+    double beta;            /* recolouring parameter in [0, 1] (Eq. recolor)              */
+    double phi;             /* uniform mass flux when no flux field is bound (Sec. II.B)  */
+    double sbar;            /* layer factor Sbar >= 1 (Eq. relation)                      */
+    double gamma;           /* site threshold Gamma (site criterion)                      */
+    int site_rule;          /* cge_site_rule                                              */
+    int kernel;             /* cge_kernel                                                 */
+    unsigned long long seed; /* stochastic-rounding stream (FP16S only)                   */
+} cge_params;
+
+/* Observables of the current state (post-streaming, pre-sink), reduced in FP64 in a fixed
+ * order over fluid nodes. */
+typedef struct {
+    long long step;         /* steps taken since the last init / counter reset            */
+    long long n_sites;      /* sites the next step will use                               */
+    long long v_half;       /* #nodes with rho_r > max(rho_r)/2 (interface, Sec. III)     */
+    long long n_negative;   /* #negative populations (either component)                   */
+    long long site_steps;   /* cumulative number of (site, step) sink applications        */
+    double mass_r, mass_b;  /* total red and blue mass                                    */
+    double sink_total;      /* cumulative mass moved red -> blue by the sink              */
+    double v_mass;          /* mass_r / rho_in[0]                                         */
+    double perim_sites;     /* n_sites / sbar: interface measure seen by the sink         */
+    double perim_grad;      /* (1/2) sum ||grad rho^N||: interface measure of rho^N       */
+    double max_u;           /* max |u|                                                    */
+    double p_in, p_out;     /* mean EOS pressure over rho^N > 0.9 and < -0.9 (Eq. EOS)    */
+    double max_rho_r;       /* max rho_r                                                  */
+} cge_obs;
+
+typedef struct cge_ctx cge_ctx;
+
+/* Validate parameters, allocate the library scratch on the current HIP device, and attach
+ * the HIP stream (hipStream_t passed as void*, NULL = default stream).
+ * Errors: CGE_EINVAL (bad parameters; *out untouched), CGE_ENOMEM, CGE_EDEVICE. */
+cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out);
+
+/* Bytes of one population buffer: 2*Q*nx*ny*nz elements of 8 (FP64), 4 (FP32S) or
+ * 2 (FP16S) bytes.  Returns 0 for invalid parameters. */
+size_t cge_population_bytes(const cge_params* params);
+
+/* Attach caller-owned device buffers (they must stay valid while the context uses them).
+ *   pop_a, pop_b : two population buffers of cge_population_bytes() each (ping-pong).
+ *                  Their content is an internal encoding: per direction i the colour-blind
+ *                  deviation f_i^r + f_i^b - rho_in[1] t_i(alpha_b) and the colour
+ *                  difference f_i^r - f_i^b of the post-collision values, stored so that
+ *                  streaming is a pull.  Use cge_set/get_populations to convert.
+ *   carry        : nx*ny*nz bytes; 1 where the next step evaporates (site mask).  It may be
+ *                  overwritten between steps to impose a site set for the next step.
+ *   flags        : nullable, nx*ny*nz bytes, nonzero = solid node (halfway bounce-back,
+ *                  neutral wetting).  Not changed by the library.
+ *   phi_field    : nullable, nx*ny*nz per-node fluxes phi(x) (double for FP64, float for
+ *                  FP32S/FP16S); replaces params.phi (sink s = phi(x)/sbar per step).
+ * Errors: CGE_EINVAL for a NULL ctx/pop_a/pop_b/carry or pop_a == pop_b. */
+cge_status cge_bind(cge_ctx* ctx, void* pop_a, void* pop_b, unsigned char* carry,
+                    const unsigned char* flags, const void* phi_field);
+
+/* Equilibrium initial state from device FP64 fields rho_r, rho_b ([N]) and u ([D][N],
+ * nullable = rest):  f_i^k = rho_k [t_i(alpha_k) + W_i (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
+ * (Eq. feq per component).  Also sets the site mask from the gradient of the initial
+ * phase field and zeroes the step and sink counters.  Requires cge_bind. */
+cge_status cge_init_equilibrium(cge_ctx* ctx, const double* rho_r, const double* rho_b,
+                                const double* u);
+
+/* Load / export the state as device FP64 populations [2][Q][N] (post-streaming, pre-sink,
+ * plain f^r and f^b).  Solid nodes export zeros and are ignored on load.  Loading does not
+ * touch the site mask or counters (see cge_reset_sites, cge_set_counters). */
+cge_status cge_set_populations(cge_ctx* ctx, const double* f);
+cge_status cge_get_populations(cge_ctx* ctx, double* f);
+
+/* Recompute the site mask from the current state (gradient of its phase field). */
+cge_status cge_reset_sites(cge_ctx* ctx);
+
+/* Restore the step counter and the FP64 sink bookkeeping (checkpoint resume). */
+cge_status cge_set_counters(cge_ctx* ctx, long long step, long long site_steps,
+                            double sink_total);
+
+/* Advance nsteps >= 0 time steps (method summary of Sec. II.B: sink rate, sites, mass
+ * exchange, moments, collision, perturbation, recolouring, streaming). */
+cge_status cge_step(cge_ctx* ctx, long long nsteps);
+
+/* Reduce the observables of the current state into *out (host).  Synchronises the stream. */
+cge_status cge_observables(cge_ctx* ctx, cge_obs* out);
+
+/* Per-node FP64 fields of the current state into device arrays (each nullable):
+ * rho_r, rho_b, rhoN ([N]) and u ([D][N]).  Solid nodes get 0 (rhoN: wetting value). */
+cge_status cge_fields(cge_ctx* ctx, double* rho_r, double* rho_b, double* u, double* rhoN);
+
+/* Kernel timing: when on, HIP events bracket every launch of the step kernel(s) on the
+ * context's stream.  cge_timing synchronises and returns the summed milliseconds and the
+ * number of timed steps since timing was switched on. */
+cge_status cge_set_timing(cge_ctx* ctx, int on);
+cge_status cge_timing(cge_ctx* ctx, double* total_ms, long long* steps);
+
+/* Name of the step kernel the context launches (static string). */
+const char* cge_kernel_name(const cge_ctx* ctx);
+
+/* Lattice tables of the library (host): W, A, B, C (Q doubles each, t_i(a) = A_i + B_i a,
+ * C_i the perturbation constants), c (3Q ints), opp (Q ints), zeta.  Any pointer may be NULL. */
+cge_status cge_lattice_tables(int lattice, double* W, double* A, double* B, double* C, int* c,
+                              int* opp, double* zeta);
+
+/* Plain device-to-device copy of nbytes with a streaming kernel on hip_stream (bandwidth
+ * reference for the roofline).  Pointers must be 16-byte aligned. */
+cge_status cge_copy_probe(void* dst, const void* src, size_t nbytes, void* hip_stream);
+
+const char* cge_last_error(const cge_ctx* ctx);
+void cge_destroy(cge_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGEVAP_H */

@@ -1,0 +1,252 @@
+"""Python binding of libcgevap.so (C-ABI in include/cgevap.h): argument marshalling only.
+
+Every step of the path runs in the HIP kernels of the library; torch provides device
+memory and the stream.  Importing this module does not need a GPU; creating a simulation
+does, and fails loudly when the HIP library is missing or no GPU is visible.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcgevap.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+PRECISIONS = {"fp64": 0, "fp32s": 1, "fp16s": 2}
+KERNELS = {"auto": 0, "twopass": 1, "fused": 2}
+SITE_RULES = {"grad": 0, "phase": 1}
+ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
+
+# every symbol the header declares
+EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
+           "cge_set_populations", "cge_get_populations", "cge_reset_sites", "cge_set_counters",
+           "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
+           "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
+           "cge_destroy"]
+
+
+class CgeParams(C.Structure):
+    _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("precision", C.c_int), ("rho_in", C.c_double * 2), ("tau", C.c_double * 2),
+                ("sigma", C.c_double), ("beta", C.c_double), ("phi", C.c_double),
+                ("sbar", C.c_double), ("gamma", C.c_double), ("site_rule", C.c_int),
+                ("kernel", C.c_int), ("seed", C.c_ulonglong)]
+
+
+class CgeObs(C.Structure):
+    _fields_ = [("step", C.c_longlong), ("n_sites", C.c_longlong), ("v_half", C.c_longlong),
+                ("n_negative", C.c_longlong), ("site_steps", C.c_longlong),
+                ("mass_r", C.c_double), ("mass_b", C.c_double), ("sink_total", C.c_double),
+                ("v_mass", C.c_double), ("perim_sites", C.c_double), ("perim_grad", C.c_double),
+                ("max_u", C.c_double), ("p_in", C.c_double), ("p_out", C.c_double),
+                ("max_rho_r", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class CgeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libcgevap status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libcgevap.so (built in-tree by __graft_entry__.build() or build.py)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run "
+                               "python -c 'import __graft_entry__; __graft_entry__.build()'")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, P = C.c_void_p, C.POINTER(C.c_double), C.POINTER
+        L.cge_create.argtypes = [P(CgeParams), vp, P(vp)]
+        L.cge_population_bytes.argtypes = [P(CgeParams)]
+        L.cge_population_bytes.restype = C.c_size_t
+        L.cge_bind.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.cge_init_equilibrium.argtypes = [vp, vp, vp, vp]
+        L.cge_set_populations.argtypes = [vp, vp]
+        L.cge_get_populations.argtypes = [vp, vp]
+        L.cge_reset_sites.argtypes = [vp]
+        L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
+        L.cge_step.argtypes = [vp, C.c_longlong]
+        L.cge_observables.argtypes = [vp, P(CgeObs)]
+        L.cge_fields.argtypes = [vp, vp, vp, vp, vp]
+        L.cge_set_timing.argtypes = [vp, C.c_int]
+        L.cge_timing.argtypes = [vp, dp, P(C.c_longlong)]
+        L.cge_kernel_name.argtypes = [vp]
+        L.cge_kernel_name.restype = C.c_char_p
+        L.cge_lattice_tables.argtypes = [C.c_int, dp, dp, dp, dp, P(C.c_int), P(C.c_int), dp]
+        L.cge_copy_probe.argtypes = [vp, vp, C.c_size_t, vp]
+        L.cge_last_error.argtypes = [vp]
+        L.cge_last_error.restype = C.c_char_p
+        L.cge_destroy.argtypes = [vp]
+        L.cge_destroy.restype = None
+        for name in EXPORTS:
+            getattr(L, name).restype = getattr(L, name).restype or C.c_int
+        _lib = L
+    return _lib
+
+
+def make_params(params, precision="fp64", kernel="auto", seed=0):
+    """cge_params from a workload parameter dict (keys as in inputs.workload)."""
+    Q = int(params["Q"])
+    nz, ny, nx = params["shape"]
+    p = CgeParams()
+    p.lattice, p.nx, p.ny, p.nz = Q, nx, ny, nz
+    p.precision = PRECISIONS[precision]
+    p.rho_in[0], p.rho_in[1] = params.get("rho_in", (1.0, 1.0))
+    p.tau[0], p.tau[1] = params.get("tau", (1.0, 1.0))
+    p.sigma = params["sigma"]
+    p.beta = params["beta"]
+    p.phi = params.get("phi", 0.0)
+    p.sbar = params.get("sbar", 3.0)
+    p.gamma = params["gamma"]
+    p.site_rule = SITE_RULES[params.get("site_rule", "grad")]
+    p.kernel = KERNELS[kernel]
+    p.seed = seed
+    return p
+
+
+def lattice_tables(Q):
+    W, A, B, Cc = (np.zeros(Q) for _ in range(4))
+    c = np.zeros(3 * Q, np.int32)
+    opp = np.zeros(Q, np.int32)
+    zeta = C.c_double()
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    ip = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))  # noqa: E731
+    st = lib().cge_lattice_tables(Q, dp(W), dp(A), dp(B), dp(Cc), ip(c), ip(opp), C.byref(zeta))
+    if st != OK:
+        raise CgeError(st, f"no lattice with Q={Q}")
+    return {"W": W, "A": A, "B": B, "C": Cc, "c": c.reshape(Q, 3), "opp": opp, "zeta": zeta.value}
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Simulation:
+    """One simulation on one GPU.  Buffers are torch tensors on `device`; all work is
+    enqueued on torch's current stream of that device at construction time."""
+
+    def __init__(self, params, rho_r, rho_b, u=None, solid=None, phi_field=None,
+                 precision="fp64", kernel="auto", seed=0, device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP path needs an MI355X")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = dict(params)
+        self.precision = precision
+        self.Q = int(params["Q"])
+        self.D = 2 if self.Q == 9 else 3
+        self.shape = tuple(params["shape"])
+        self.N = int(np.prod(self.shape))
+        L = lib()
+        cp = make_params(params, precision, kernel, seed)
+        nbytes = L.cge_population_bytes(C.byref(cp))
+        if nbytes == 0:
+            raise CgeError(EINVAL, "invalid parameters")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            ctx = C.c_void_p()
+            st = L.cge_create(C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+            if st != OK:
+                raise CgeError(st, "cge_create failed")
+            self._ctx = ctx
+            dev = self.device
+            self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+            self.carry = torch.zeros(self.shape, dtype=torch.uint8, device=dev)
+            self.flags = None if solid is None else torch.as_tensor(
+                np.ascontiguousarray(solid, np.uint8), device=dev)
+            pdt = torch.float64 if precision == "fp64" else torch.float32
+            self.phi_field = None if phi_field is None else torch.as_tensor(
+                np.ascontiguousarray(phi_field), device=dev).to(pdt).contiguous()
+            self._check(L.cge_bind(self._ctx, _ptr(self.pop[0]), _ptr(self.pop[1]),
+                                   _ptr(self.carry), _ptr(self.flags), _ptr(self.phi_field)))
+            self.init_equilibrium(rho_r, rho_b, u)
+
+    # ----------------------------------------------------------------------------- plumbing
+    def _check(self, st):
+        if st != OK:
+            msg = lib().cge_last_error(self._ctx).decode()
+            raise CgeError(st, msg)
+
+    def _dev64(self, a):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, np.float64) if isinstance(a, np.ndarray)
+                                 else a, device=self.device)
+        return t.to(self.torch.float64).contiguous()
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self.torch.cuda.synchronize(self.device)
+            lib().cge_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ----------------------------------------------------------------------------- C-ABI calls
+    def init_equilibrium(self, rho_r, rho_b, u=None):
+        rr, rb = self._dev64(rho_r), self._dev64(rho_b)
+        uu = None if u is None else self._dev64(u)
+        self._check(lib().cge_init_equilibrium(self._ctx, _ptr(rr), _ptr(rb), _ptr(uu)))
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def step(self, n=1):
+        self._check(lib().cge_step(self._ctx, int(n)))
+
+    def observables(self):
+        o = CgeObs()
+        self._check(lib().cge_observables(self._ctx, C.byref(o)))
+        return o.as_dict()
+
+    def populations(self):
+        f = self.torch.empty((2, self.Q) + self.shape, dtype=self.torch.float64,
+                             device=self.device)
+        self._check(lib().cge_get_populations(self._ctx, _ptr(f)))
+        return f
+
+    def set_populations(self, f):
+        t = self._dev64(f)
+        assert t.numel() == 2 * self.Q * self.N
+        self._check(lib().cge_set_populations(self._ctx, _ptr(t)))
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def reset_sites(self):
+        self._check(lib().cge_reset_sites(self._ctx))
+
+    def set_counters(self, step=0, site_steps=0, sink_total=0.0):
+        self._check(lib().cge_set_counters(self._ctx, step, site_steps, sink_total))
+
+    def fields(self):
+        t = self.torch
+        rr, rb, rn = (t.empty(self.shape, dtype=t.float64, device=self.device) for _ in range(3))
+        u = t.empty((self.D,) + self.shape, dtype=t.float64, device=self.device)
+        self._check(lib().cge_fields(self._ctx, _ptr(rr), _ptr(rb), _ptr(u), _ptr(rn)))
+        return {"rho_r": rr, "rho_b": rb, "u": u, "rhoN": rn}
+
+    def set_timing(self, on):
+        self._check(lib().cge_set_timing(self._ctx, 1 if on else 0))
+
+    def timing(self):
+        ms, n = C.c_double(), C.c_longlong()
+        self._check(lib().cge_timing(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def kernel_name(self):
+        return lib().cge_kernel_name(self._ctx).decode()
+
+
+def copy_probe(dst, src, nbytes, stream):
+    """Launch the library's streaming copy kernel (bandwidth reference)."""
+    st = lib().cge_copy_probe(_ptr(dst), _ptr(src), int(nbytes), C.c_void_p(stream.cuda_stream))
+    if st != OK:
+        raise CgeError(st, "copy probe failed")

@@ -1,0 +1,373 @@
+// C-ABI entry points of libcgevap.so (declared in include/cgevap.h): parameter validation,
+// scratch management, step sequencing, timing, and the copy bandwidth probe.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+#include "node.hpp"
+
+namespace cge {
+
+cge_status fail(cge_ctx* c, cge_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+cge_status check(cge_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return CGE_OK;
+    return fail(c, CGE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// alpha_k of the generalized colour-gradient model (Sec. II.A): the least dense component
+// takes W_0, the others 1 - (1 - W_0)/gamma_k with gamma_k = rho_k / rho_min.
+static void alphas(const cge_params& p, double w0, double a[2]) {
+    const double rmin = p.rho_in[0] < p.rho_in[1] ? p.rho_in[0] : p.rho_in[1];
+    for (int k = 0; k < 2; ++k)
+        a[k] = p.rho_in[k] == rmin ? w0 : 1.0 - (1.0 - w0) / (p.rho_in[k] / rmin);
+}
+
+template <typename M>
+Phys<M> phys(const cge_ctx* c) {
+    const double w0 = c->Q == 9 ? Lat<9>::w0 : Lat<19>::w0;
+    double a[2];
+    alphas(c->p, w0, a);
+    Phys<M> P;
+    P.rho_ref = M(c->p.rho_in[1]);
+    P.alpha_ref = M(a[1]);
+    P.alpha_r = M(a[0]);
+    P.alpha_b = M(a[1]);
+    P.omega_r = M(1.0 / c->p.tau[0]);
+    P.omega_b = M(1.0 / c->p.tau[1]);
+    P.sigma = M(c->p.sigma);
+    P.beta = M(c->p.beta);
+    P.gamma = M(c->p.gamma);
+    P.phi = M(c->p.phi);
+    P.inv_sbar = M(1.0 / c->p.sbar);
+    P.site_rule = c->p.site_rule;
+    return P;
+}
+template Phys<float> phys<float>(const cge_ctx*);
+template Phys<double> phys<double>(const cge_ctx*);
+
+void timing_begin(cge_ctx* c) {
+    if (!c->timing) return;
+    if (c->ev_used + 2 > c->ev.size()) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            c->ev.push_back(e);
+        }
+    }
+    (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+}
+
+static void timing_fold(cge_ctx* c) {
+    if (c->ev_used == 0) return;
+    (void)hipEventSynchronize(c->ev[c->ev_used - 1]);
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]) == hipSuccess) c->timed_ms += ms;
+    }
+    c->ev_used = 0;
+}
+
+void timing_end(cge_ctx* c) {
+    if (!c->timing || c->ev_used + 2 > c->ev.size()) return;
+    (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
+    c->ev_used += 2;
+    c->timed_steps += 1;
+    if (c->ev_used >= 2048) timing_fold(c);
+}
+
+__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                              long long n16) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_zero(unsigned long long* __restrict__ p, long long n) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// zero n 8-byte words with a kernel (no memset node, so the call is safe under capture)
+static hipError_t zero_words(void* p, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       static_cast<unsigned long long*>(p), n);
+    return hipGetLastError();
+}
+
+cge_status copy_probe(void* dst, const void* src, size_t nbytes, hipStream_t s) {
+    const long long n16 = (long long)(nbytes / 16);
+    if (n16 > 0)
+        hipLaunchKernelGGL(k_copy, dim3(8192), dim3(256), 0, s, static_cast<const uint4*>(src),
+                           static_cast<uint4*>(dst), n16);
+    return hipGetLastError() == hipSuccess ? CGE_OK : CGE_EDEVICE;
+}
+
+}  // namespace cge
+
+using namespace cge;
+
+static bool is_fin(double v) { return std::isfinite(v); }
+
+static const char* validate(const cge_params* p) {
+    if (!p) return "params is NULL";
+    if (p->lattice != CGE_D2Q9 && p->lattice != CGE_D3Q19) return "lattice must be 9 or 19";
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return "nx, ny, nz must be >= 1";
+    if (p->ny > 65535 || p->nz > 65535) return "ny and nz must be <= 65535";
+    if (p->lattice == CGE_D2Q9 && p->nz != 1) return "D2Q9 needs nz == 1";
+    if (p->precision < CGE_FP64 || p->precision > CGE_FP16S) return "unknown precision";
+    for (int k = 0; k < 2; ++k) {
+        if (!(is_fin(p->rho_in[k]) && p->rho_in[k] > 0.0)) return "rho_in must be > 0";
+        if (!(is_fin(p->tau[k]) && p->tau[k] > 0.5)) return "tau must be > 1/2";
+    }
+    if (!(is_fin(p->sigma) && p->sigma >= 0.0)) return "sigma must be >= 0";
+    if (!(is_fin(p->beta) && p->beta >= 0.0 && p->beta <= 1.0)) return "beta must be in [0, 1]";
+    if (!is_fin(p->phi)) return "phi must be finite";
+    if (!(is_fin(p->sbar) && p->sbar >= 1.0)) return "sbar must be >= 1";
+    if (!is_fin(p->gamma)) return "gamma must be finite";
+    if (p->site_rule != CGE_SITE_GRAD_GT && p->site_rule != CGE_SITE_PHASE_LT)
+        return "unknown site rule";
+    if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_FUSED) return "unknown kernel";
+    return nullptr;
+}
+
+static size_t elem_bytes(int precision) {
+    return precision == CGE_FP64 ? 8 : (precision == CGE_FP32S ? 4 : 2);
+}
+
+extern "C" {
+
+size_t cge_population_bytes(const cge_params* p) {
+    if (validate(p)) return 0;
+    return 2ull * p->lattice * (size_t)p->nx * p->ny * p->nz * elem_bytes(p->precision);
+}
+
+cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out) {
+    if (!out) return CGE_EINVAL;
+    if (validate(params)) return CGE_EINVAL;
+    cge_ctx* c = new (std::nothrow) cge_ctx();
+    if (!c) return CGE_ENOMEM;
+    c->p = *params;
+    c->Q = params->lattice;
+    c->g = Geo{params->nx, params->ny, params->nz,
+               (long long)params->nx * params->ny * params->nz};
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return CGE_EDEVICE;
+    }
+    if (params->kernel == CGE_KERNEL_FUSED && !fused_supported(c)) {
+        delete c;
+        return CGE_EUNSUPPORTED;
+    }
+    c->kernel = (params->kernel == CGE_KERNEL_TWOPASS || !fused_supported(c)) ? CGE_KERNEL_TWOPASS
+                                                                                : CGE_KERNEL_FUSED;
+    const size_t mbytes = params->precision == CGE_FP64 ? 8 : 4;
+    c->acc_len = twopass_blocks(c);
+    if (fused_supported(c) && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
+    c->obs_blocks = twopass_blocks(c);
+    bool ok = hipMalloc(&c->rhoN, c->g.N * mbytes) == hipSuccess &&
+              hipMalloc(&c->acc_sink, c->acc_len * sizeof(double)) == hipSuccess &&
+              hipMalloc(&c->acc_sites, c->acc_len * sizeof(long long)) == hipSuccess &&
+              hipMalloc(&c->obs_part, (CGE_NOBS * c->obs_blocks + c->g.N) * sizeof(double)) ==
+                  hipSuccess &&
+              hipMalloc(&c->obs_res, (CGE_NOBS + 2) * sizeof(double)) == hipSuccess;
+    if (!ok) {
+        cge_destroy(c);
+        return CGE_ENOMEM;
+    }
+    ok = zero_words(c->acc_sink, c->acc_len, c->stream) == hipSuccess &&
+         zero_words(c->acc_sites, c->acc_len, c->stream) == hipSuccess;
+    if (!ok) {
+        cge_destroy(c);
+        return CGE_EDEVICE;
+    }
+    *out = c;
+    return CGE_OK;
+}
+
+cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
+                    const unsigned char* flags, const void* phi_field) {
+    if (!c) return CGE_EINVAL;
+    if (!pop_a || !pop_b || !carry) return fail(c, CGE_EINVAL, "pop_a, pop_b, carry required");
+    if (pop_a == pop_b) return fail(c, CGE_EINVAL, "pop_a and pop_b must differ");
+    c->pop[0] = pop_a;
+    c->pop[1] = pop_b;
+    c->cur = 0;
+    c->carry = carry;
+    c->flags = flags;
+    c->phi_field = phi_field;
+    c->bound = true;
+    return CGE_OK;
+}
+
+static cge_status zero_counters(cge_ctx* c) {
+    c->step = 0;
+    c->sites_offset = 0;
+    c->sink_offset = 0.0;
+    if (zero_words(c->acc_sink, c->acc_len, c->stream) != hipSuccess ||
+        zero_words(c->acc_sites, c->acc_len, c->stream) != hipSuccess)
+        return fail(c, CGE_EDEVICE, "clearing the sink accumulators failed");
+    return CGE_OK;
+}
+
+cge_status cge_init_equilibrium(cge_ctx* c, const double* rho_r, const double* rho_b,
+                                const double* u) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (!rho_r || !rho_b) return fail(c, CGE_EINVAL, "rho_r and rho_b required");
+    if (cge_status s = init_equilibrium(c, rho_r, rho_b, u)) return s;
+    if (cge_status s = reset_sites(c)) return s;
+    return zero_counters(c);
+}
+
+cge_status cge_set_populations(cge_ctx* c, const double* f) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (!f) return fail(c, CGE_EINVAL, "f is NULL");
+    return set_populations(c, f);
+}
+
+cge_status cge_get_populations(cge_ctx* c, double* f) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (!f) return fail(c, CGE_EINVAL, "f is NULL");
+    return get_populations(c, f);
+}
+
+cge_status cge_reset_sites(cge_ctx* c) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    return reset_sites(c);
+}
+
+cge_status cge_set_counters(cge_ctx* c, long long step, long long site_steps, double sink_total) {
+    if (!c) return CGE_EINVAL;
+    if (step < 0 || site_steps < 0 || !is_fin(sink_total))
+        return fail(c, CGE_EINVAL, "counters must be non-negative and finite");
+    if (cge_status s = zero_counters(c)) return s;
+    c->step = step;
+    c->sites_offset = site_steps;
+    c->sink_offset = sink_total;
+    return CGE_OK;
+}
+
+cge_status cge_step(cge_ctx* c, long long nsteps) {
+    if (!c) return CGE_EINVAL;
+    if (nsteps < 0) return fail(c, CGE_EINVAL, "nsteps must be >= 0");
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (nsteps == 0) return CGE_OK;
+    return c->kernel == CGE_KERNEL_FUSED ? fused_steps(c, nsteps) : twopass_steps(c, nsteps);
+}
+
+cge_status cge_observables(cge_ctx* c, cge_obs* out) {
+    if (!c) return CGE_EINVAL;
+    if (!out) return fail(c, CGE_EINVAL, "out is NULL");
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (cge_status s = observables(c)) return s;
+    double r[CGE_NOBS + 2];
+    if (cge_status s = check(c, hipMemcpyAsync(r, c->obs_res, sizeof(r), hipMemcpyDeviceToHost,
+                                               c->stream), "observable copy"))
+        return s;
+    if (cge_status s = check(c, hipStreamSynchronize(c->stream), "stream sync")) return s;
+    // indices follow the partial layout of the observable kernels
+    out->step = c->step;
+    out->mass_r = r[0];
+    out->mass_b = r[1];
+    out->n_negative = (long long)r[2];
+    out->p_in = r[4] > 0 ? r[3] / r[4] : 0.0;
+    out->p_out = r[6] > 0 ? r[5] / r[6] : 0.0;
+    out->n_sites = (long long)r[7];
+    out->max_u = r[8];
+    out->max_rho_r = r[9];
+    out->perim_grad = r[10];
+    out->v_half = (long long)r[11];
+    out->sink_total = c->sink_offset + r[CGE_NOBS];
+    out->site_steps = c->sites_offset + (long long)r[CGE_NOBS + 1];
+    out->v_mass = out->mass_r / c->p.rho_in[0];
+    out->perim_sites = (double)out->n_sites / c->p.sbar;
+    if (!is_fin(out->mass_r) || !is_fin(out->mass_b) || !is_fin(out->max_u))
+        return fail(c, CGE_ENUMERIC, "non-finite values in the state");
+    return CGE_OK;
+}
+
+cge_status cge_fields(cge_ctx* c, double* rho_r, double* rho_b, double* u, double* rhoN) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    return fields(c, rho_r, rho_b, u, rhoN);
+}
+
+cge_status cge_set_timing(cge_ctx* c, int on) {
+    if (!c) return CGE_EINVAL;
+    if (on && !c->timing) {
+        c->timed_ms = 0.0;
+        c->timed_steps = 0;
+        c->ev_used = 0;
+    }
+    if (!on) timing_fold(c);
+    c->timing = on != 0;
+    return CGE_OK;
+}
+
+cge_status cge_timing(cge_ctx* c, double* total_ms, long long* steps) {
+    if (!c || !total_ms || !steps) return fail(c, CGE_EINVAL, "NULL argument");
+    timing_fold(c);
+    *total_ms = c->timed_ms;
+    *steps = c->timed_steps;
+    return CGE_OK;
+}
+
+const char* cge_kernel_name(const cge_ctx* c) {
+    if (!c) return "";
+    return c->kernel == CGE_KERNEL_FUSED ? "k_fused" : "k_collide";
+}
+
+cge_status cge_lattice_tables(int lattice, double* W, double* A, double* B, double* C, int* cv,
+                              int* opp, double* zeta) {
+    if (lattice != 9 && lattice != 19) return CGE_EINVAL;
+    for (int i = 0; i < lattice; ++i) {
+        if (lattice == 9) {
+            if (W) W[i] = weight<9>(i);
+            if (A) A[i] = restA<9>(i);
+            if (B) B[i] = restB<9>(i);
+            if (C) C[i] = pertC<9>(i);
+            if (cv) { cv[3 * i] = Lat<9>::cx[i]; cv[3 * i + 1] = Lat<9>::cy[i]; cv[3 * i + 2] = Lat<9>::cz[i]; }
+            if (opp) opp[i] = Lat<9>::opp[i];
+        } else {
+            if (W) W[i] = weight<19>(i);
+            if (A) A[i] = restA<19>(i);
+            if (B) B[i] = restB<19>(i);
+            if (C) C[i] = pertC<19>(i);
+            if (cv) { cv[3 * i] = Lat<19>::cx[i]; cv[3 * i + 1] = Lat<19>::cy[i]; cv[3 * i + 2] = Lat<19>::cz[i]; }
+            if (opp) opp[i] = Lat<19>::opp[i];
+        }
+    }
+    if (zeta) *zeta = lattice == 9 ? Lat<9>::zeta : Lat<19>::zeta;
+    return CGE_OK;
+}
+
+cge_status cge_copy_probe(void* dst, const void* src, size_t nbytes, void* hip_stream) {
+    if (!dst || !src) return CGE_EINVAL;
+    if (((uintptr_t)dst | (uintptr_t)src) & 15) return CGE_EINVAL;
+    return copy_probe(dst, src, nbytes, static_cast<hipStream_t>(hip_stream));
+}
+
+const char* cge_last_error(const cge_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+void cge_destroy(cge_ctx* c) {
+    if (!c) return;
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    (void)hipFree(c->rhoN);
+    (void)hipFree(c->acc_sink);
+    (void)hipFree(c->acc_sites);
+    (void)hipFree(c->obs_part);
+    (void)hipFree(c->obs_res);
+    delete c;
+}
+
+}  // extern "C"

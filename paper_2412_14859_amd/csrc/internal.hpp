@@ -1,0 +1,125 @@
+// Host-side context and the launchers shared by the translation units of libcgevap.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/cgevap.h"
+#include "lattice.hpp"
+
+// Number of FP64 observables reduced per block (see observe.hip).
+#define CGE_NOBS 12
+
+struct cge_ctx {
+    cge_params p{};
+    int Q = 0;
+    cge::Geo g{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int kernel = CGE_KERNEL_TWOPASS;  // resolved step implementation
+    // caller-owned buffers
+    void* pop[2] = {nullptr, nullptr};
+    int cur = 0;  // pop[cur] holds the current state
+    unsigned char* carry = nullptr;
+    const unsigned char* flags = nullptr;
+    const void* phi_field = nullptr;
+    bool bound = false;
+    // library scratch
+    void* rhoN = nullptr;           // N elements of the arithmetic type
+    double* acc_sink = nullptr;     // per-block cumulative sink (FP64)
+    long long* acc_sites = nullptr; // per-block cumulative site count
+    long long acc_len = 0;
+    double* obs_part = nullptr;     // [CGE_NOBS][obs_blocks]
+    long long obs_blocks = 0;
+    double* obs_res = nullptr;      // [CGE_NOBS + 2] final values (device)
+    // counters
+    long long step = 0;
+    long long sites_offset = 0;
+    double sink_offset = 0.0;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    long long timed_steps = 0;
+    double timed_ms = 0.0;
+    std::string err;
+};
+
+namespace cge {
+
+cge_status fail(cge_ctx* c, cge_status s, const std::string& msg);
+cge_status check(cge_ctx* c, hipError_t e, const char* what);
+
+// step implementations: launch `nsteps` steps, swapping c->cur
+cge_status twopass_steps(cge_ctx* c, long long nsteps);
+cge_status fused_steps(cge_ctx* c, long long nsteps);
+bool fused_supported(const cge_ctx* c);
+long long twopass_blocks(const cge_ctx* c);
+long long fused_blocks(const cge_ctx* c);
+
+// site mask from the current state's phase field (no sink)
+cge_status reset_sites(cge_ctx* c);
+template <typename R>
+cge_status wet_field(cge_ctx* c, R* rhoN);
+
+// state conversion
+cge_status init_equilibrium(cge_ctx* c, const double* rr, const double* rb, const double* u);
+cge_status set_populations(cge_ctx* c, const double* f);
+cge_status get_populations(cge_ctx* c, double* f);
+cge_status fields(cge_ctx* c, double* rr, double* rb, double* u, double* rhoN);
+
+// observables into c->obs_res (device), then copied to host by the caller
+cge_status observables(cge_ctx* c);
+
+cge_status copy_probe(void* dst, const void* src, size_t nbytes, hipStream_t s);
+
+// timing helpers around step-kernel launches
+void timing_begin(cge_ctx* c);
+void timing_end(cge_ctx* c);
+
+// launch shape of the one-thread-per-node kernels: (bx, 1, 1) blocks, bx a multiple of 64
+inline dim3 node_block(const Geo& g) {
+    const int bx = ((g.nx + 63) / 64) * 64;
+    return dim3(bx < 256 ? bx : 256, 1, 1);
+}
+inline dim3 node_grid(const Geo& g) {
+    const dim3 b = node_block(g);
+    return dim3((g.nx + b.x - 1) / b.x, g.ny, g.nz);
+}
+
+// physical constants in arithmetic type M
+template <typename M>
+Phys<M> phys(const cge_ctx* c);
+
+}  // namespace cge
+
+// Dispatch a template FN<Q, S, M, WALLS>(args...) on lattice, precision and walls.
+#define CGE_DISPATCH(c, FN, ...)                                                            \
+    do {                                                                                    \
+        const bool w_ = (c)->flags != nullptr;                                              \
+        const int key_ = (c)->Q * 10 + (c)->p.precision;                                    \
+        switch (key_) {                                                                     \
+            case 90:                                                                        \
+                return w_ ? FN<9, double, double, true>(__VA_ARGS__)                        \
+                          : FN<9, double, double, false>(__VA_ARGS__);                      \
+            case 91:                                                                        \
+                return w_ ? FN<9, float, float, true>(__VA_ARGS__)                          \
+                          : FN<9, float, float, false>(__VA_ARGS__);                        \
+            case 92:                                                                        \
+                return w_ ? FN<9, _Float16, float, true>(__VA_ARGS__)                       \
+                          : FN<9, _Float16, float, false>(__VA_ARGS__);                     \
+            case 190:                                                                       \
+                return w_ ? FN<19, double, double, true>(__VA_ARGS__)                       \
+                          : FN<19, double, double, false>(__VA_ARGS__);                     \
+            case 191:                                                                       \
+                return w_ ? FN<19, float, float, true>(__VA_ARGS__)                         \
+                          : FN<19, float, float, false>(__VA_ARGS__);                       \
+            case 192:                                                                       \
+                return w_ ? FN<19, _Float16, float, true>(__VA_ARGS__)                      \
+                          : FN<19, _Float16, float, false>(__VA_ARGS__);                    \
+            default:                                                                        \
+                return cge::fail((c), CGE_EUNSUPPORTED, "unsupported lattice/precision");   \
+        }                                                                                   \
+    } while (0)

@@ -1,0 +1,87 @@
+// Lattice constants of the HIP path (D2Q9, D3Q19) and the per-run physical constants.
+//
+// Rest weights of the alpha-equilibrium (Eq. feq): t_i(a) = A_i + B_i a with A_0 = 0,
+// B_0 = 1 and A_i = -B_i = W_i / (1 - W_0) for i >= 1, so that t_i(W_0) = W_i and
+// zeta (1 - W_0) = c_s^2 (Appendix A).  Perturbation constants (Eq. perturb):
+// C_0 = c_s^2 - (1 - W_0), C_i = W_i for i >= 1, which give sum_i C_i = c_s^2 and
+// sum_i C_i c_ia c_ib = c_s^2 delta_ab.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cge {
+
+template <int Q>
+struct Lat;
+
+template <>
+struct Lat<9> {
+    static constexpr int D = 2;
+    static constexpr int cx[9] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+    static constexpr int cy[9] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+    static constexpr int cz[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+    static constexpr double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+    static constexpr double zeta = 3.0 / 5.0;
+};
+
+template <>
+struct Lat<19> {
+    static constexpr int D = 3;
+    static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+    static constexpr double w0 = 1.0 / 3.0, w1 = 1.0 / 18.0, w2 = 1.0 / 36.0;
+    static constexpr double zeta = 1.0 / 2.0;
+};
+
+template <int Q>
+__host__ __device__ constexpr int norm2(int i) {
+    return Lat<Q>::cx[i] * Lat<Q>::cx[i] + Lat<Q>::cy[i] * Lat<Q>::cy[i] +
+           Lat<Q>::cz[i] * Lat<Q>::cz[i];
+}
+template <int Q>
+__host__ __device__ constexpr double weight(int i) {
+    return norm2<Q>(i) == 0 ? Lat<Q>::w0 : (norm2<Q>(i) == 1 ? Lat<Q>::w1 : Lat<Q>::w2);
+}
+template <int Q>
+__host__ __device__ constexpr double restA(int i) {
+    return i == 0 ? 0.0 : weight<Q>(i) / (1.0 - Lat<Q>::w0);
+}
+template <int Q>
+__host__ __device__ constexpr double restB(int i) {
+    return i == 0 ? 1.0 : -restA<Q>(i);
+}
+template <int Q>
+__host__ __device__ constexpr double pertC(int i) {
+    return i == 0 ? 1.0 / 3.0 - (1.0 - Lat<Q>::w0) : weight<Q>(i);
+}
+// 1/|c_i| (0 for the rest direction, whose cos(theta) is taken as 0)
+template <int Q>
+__host__ __device__ constexpr double inv_len(int i) {
+    return norm2<Q>(i) == 0 ? 0.0 : (norm2<Q>(i) == 1 ? 1.0 : 0.70710678118654752440);
+}
+
+// Physical constants of one run in the arithmetic type M.
+template <typename M>
+struct Phys {
+    M rho_ref;        // codec shift: rho_ref * t_i(alpha_ref) is subtracted from f_i
+    M alpha_ref;
+    M alpha_r, alpha_b;
+    M omega_r, omega_b;  // 1/tau_k
+    M sigma, beta;
+    M gamma;
+    M phi;            // uniform flux
+    M inv_sbar;
+    int site_rule;    // 0 grad, 1 phase
+};
+
+struct Geo {
+    int nx, ny, nz;
+    long long N;
+};
+
+}  // namespace cge

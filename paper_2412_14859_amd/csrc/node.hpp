@@ -1,0 +1,240 @@
+// Per-node device arithmetic of the colour-gradient step (HIP path).
+//
+// Population encoding (all precisions): per direction i the library stores
+//   ft_i = f_i^r + f_i^b - rho_ref t_i(alpha_ref)   (colour-blind deviation)
+//   dd_i = f_i^r - f_i^b                             (colour difference)
+// of the post-collision values; streaming is a pull.  Streaming is linear, so (ft, dd)
+// stream exactly as (f^r, f^b).  The sink (Eq. exchange) leaves ft untouched and lowers
+// dd_0 by 2s; rho = rho_ref + sum ft, rho_r - rho_b = sum dd.  Collision and perturbation
+// act on the colour-blind population only; recolouring (Eq. recolor) then gives
+//   dd_i* = rho^N f_i'' + 2 beta (rho_r rho_b / rho^2) cos(theta_i) rho t_i(abar),
+// with rho_r/rho = (1 + rho^N)/2 and rho_r rho_b / rho^2 = (1 - rho^N^2)/4.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace cge {
+
+template <typename M, typename S>
+__device__ __forceinline__ M ld(const S* p) {
+    return static_cast<M>(*p);
+}
+
+// splitmix64 finaliser (Steele, Lea, Flood 2014): counter-based random bits
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Round v to half precision stochastically: the neighbour above |v| is taken with
+// probability proportional to the distance from the one below, so the rounding is
+// unbiased in expectation (needed for per-step sinks far below one half-precision ulp).
+__device__ __forceinline__ _Float16 sr_half(float v, uint32_t r) {
+    const _Float16 h = static_cast<_Float16>(v);
+    const float b = static_cast<float>(h);
+    if (b == v || !(fabsf(v) < 65504.0f)) return h;
+    const uint16_t hb = __builtin_bit_cast(uint16_t, h);
+    const bool h_is_hi = fabsf(b) > fabsf(v);
+    const uint16_t ob = h_is_hi ? (uint16_t)(hb - 1) : (uint16_t)(hb + 1);
+    const _Float16 o = __builtin_bit_cast(_Float16, ob);
+    const float of = static_cast<float>(o);
+    const float lo = h_is_hi ? fabsf(of) : fabsf(b);
+    const float hi = h_is_hi ? fabsf(b) : fabsf(of);
+    const float p = (fabsf(v) - lo) / (hi - lo);
+    const float u = static_cast<float>(r >> 8) * 5.9604644775390625e-8f;  // 2^-24
+    const bool up = u < p;
+    return up == h_is_hi ? h : o;
+}
+
+// store with the storage type's rounding: nearest for double/float, stochastic for half
+template <typename S, typename M>
+__device__ __forceinline__ void st(S* p, M v, uint64_t key) {
+    *p = static_cast<S>(v);
+}
+template <>
+__device__ __forceinline__ void st<_Float16, float>(_Float16* p, float v, uint64_t key) {
+    *p = sr_half(v, static_cast<uint32_t>(mix64(key) >> 32));
+}
+
+// neighbour coordinates with periodic wrap
+struct Nb {
+    int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ __forceinline__ Nb wrap(const Geo& g, int x, int y, int z) {
+    Nb b;
+    b.xm = x == 0 ? g.nx - 1 : x - 1;
+    b.xp = x == g.nx - 1 ? 0 : x + 1;
+    b.ym = y == 0 ? g.ny - 1 : y - 1;
+    b.yp = y == g.ny - 1 ? 0 : y + 1;
+    b.zm = z == 0 ? g.nz - 1 : z - 1;
+    b.zp = z == g.nz - 1 ? 0 : z + 1;
+    return b;
+}
+
+__device__ __forceinline__ long long lin(const Geo& g, int x, int y, int z) {
+    return (long long)x + (long long)g.nx * ((long long)y + (long long)g.ny * z);
+}
+
+// one thread per node on a (ceil(nx/bx), ny, nz) grid of (bx, 1, 1) blocks
+constexpr int kTPBX = 256;
+
+__device__ __forceinline__ bool node_xyz(const Geo& g, int& x, int& y, int& z, long long& n) {
+    x = blockIdx.x * blockDim.x + threadIdx.x;
+    y = blockIdx.y;
+    z = blockIdx.z;
+    n = lin(g, x, y, z);
+    return x < g.nx;
+}
+
+// node at x + s*c_i (s = +1 or -1)
+template <int Q, int SGN>
+__device__ __forceinline__ long long shifted(const Geo& g, const Nb& b, int x, int y, int z, int i) {
+    const int cx = SGN * Lat<Q>::cx[i], cy = SGN * Lat<Q>::cy[i], cz = SGN * Lat<Q>::cz[i];
+    const int sx = cx == 1 ? b.xp : (cx == -1 ? b.xm : x);
+    const int sy = cy == 1 ? b.yp : (cy == -1 ? b.ym : y);
+    const int sz = cz == 1 ? b.zp : (cz == -1 ? b.zm : z);
+    return lin(g, sx, sy, sz);
+}
+
+// Streaming as a pull (Eq. Stream): f_i(x) = f_i*(x - c_i); from a solid x - c_i the
+// halfway bounce-back returns f_opp(i)*(x).
+template <int Q, bool WALLS, typename S, typename M>
+__device__ __forceinline__ void pull(const S* __restrict__ src, const uint8_t* __restrict__ flags,
+                                     const Geo& g, const Nb& b, int x, int y, int z, long long n,
+                                     M (&ft)[Q], M (&dd)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        long long sn = shifted<Q, -1>(g, b, x, y, z, i);
+        int di = i;
+        if (WALLS && i != 0 && flags[sn]) {
+            sn = n;
+            di = Lat<Q>::opp[i];
+        }
+        ft[i] = ld<M>(src + (long long)di * g.N + sn);
+        dd[i] = ld<M>(src + (long long)(Q + di) * g.N + sn);
+    }
+}
+
+template <int Q, typename M>
+__device__ __forceinline__ void moments(const M (&ft)[Q], const M (&dd)[Q], M& drho, M& dsum,
+                                        M (&j)[3]) {
+    drho = M(0);
+    dsum = M(0);
+    j[0] = j[1] = j[2] = M(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        drho += ft[i];
+        dsum += dd[i];
+        if (Lat<Q>::cx[i]) j[0] += Lat<Q>::cx[i] * ft[i];
+        if (Lat<Q>::cy[i]) j[1] += Lat<Q>::cy[i] * ft[i];
+        if (Lat<Q>::cz[i]) j[2] += Lat<Q>::cz[i] * ft[i];
+    }
+}
+
+// Site decision and sink for one node (site criterion; Eqs. relation, exchange).
+// Returns the sink s applied (0 if not a site).  dsum is pre-sink on entry.
+template <typename M>
+__device__ __forceinline__ M site_sink(const Phys<M>& P, const uint8_t* __restrict__ carry,
+                                       const void* __restrict__ phi_field, long long n, M rho,
+                                       M dsum) {
+    bool m;
+    if (P.site_rule == 0) m = carry[n] != 0;
+    else m = fabs(dsum / rho) < P.gamma;
+    if (!m) return M(0);
+    const M phi = phi_field ? static_cast<const M*>(phi_field)[n] : P.phi;
+    return phi * P.inv_sbar;
+}
+
+// Colour gradient by the compact isotropic stencil: F = (1/c_s^2) sum_i W_i rho^N(x+c_i) c_i
+template <int Q, typename M, typename R>
+__device__ __forceinline__ void gradient(const R* __restrict__ rhoN, const Geo& g, const Nb& b,
+                                         int x, int y, int z, M (&F)[3]) {
+    F[0] = F[1] = F[2] = M(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const M v = M(weight<Q>(i)) * static_cast<M>(rhoN[shifted<Q, 1>(g, b, x, y, z, i)]);
+        if (Lat<Q>::cx[i]) F[0] += Lat<Q>::cx[i] * v;
+        if (Lat<Q>::cy[i]) F[1] += Lat<Q>::cy[i] * v;
+        if (Lat<Q>::cz[i]) F[2] += Lat<Q>::cz[i] * v;
+    }
+    F[0] *= M(3);
+    F[1] *= M(3);
+    F[2] *= M(3);
+}
+
+// BGK collision with harmonic tau and alpha-equilibrium (Eqs. collision, feq), perturbation
+// (Eq. perturb) and recolouring (Eq. recolor), in place on the encoded populations.
+// Inputs are post-sink.  Returns ||F||.
+template <int Q, typename M>
+__device__ __forceinline__ M collide(M (&ft)[Q], M (&dd)[Q], M rho, M rhoN, const M (&u)[3],
+                                     const M (&F)[3], const Phys<M>& P) {
+    const M pr = M(0.5) * (M(1) + rhoN);  // rho_r / rho
+    const M pb = M(0.5) * (M(1) - rhoN);  // rho_b / rho
+    const M omega = pr * P.omega_r + pb * P.omega_b;
+    const M abar = pr * P.alpha_r + pb * P.alpha_b;
+    const M drho = rho - P.rho_ref;
+    // rho t_i(abar) - rho_ref t_i(alpha_ref) = A_i drho + B_i (rho abar - rho_ref alpha_ref)
+    const M dB = rho * (abar - P.alpha_ref) + drho * P.alpha_ref;
+    const M uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const M F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    const bool hg = F2 > M(1e-24);
+    const M Fn = hg ? sqrt(F2) : M(0);
+    const M invFn = hg ? M(1) / Fn : M(0);
+    const M kp = M(2.25) * P.sigma * omega;                         // (9/4) sigma / tau
+    const M sep = M(0.5) * P.beta * (M(1) - rhoN * rhoN) * rho;      // 2 beta rho_r rho_b / rho
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const M A = M(restA<Q>(i)), B = M(restB<Q>(i)), W = M(weight<Q>(i));
+        const M cu = M(Lat<Q>::cx[i]) * u[0] + M(Lat<Q>::cy[i]) * u[1] + M(Lat<Q>::cz[i]) * u[2];
+        const M feq = A * drho + B * dB + W * rho * (M(3) * cu + M(4.5) * cu * cu - M(1.5) * uu);
+        M f1 = ft[i] - omega * (ft[i] - feq);
+        const M Fc = M(Lat<Q>::cx[i]) * F[0] + M(Lat<Q>::cy[i]) * F[1] + M(Lat<Q>::cz[i]) * F[2];
+        f1 += kp * (W * Fc * Fc * invFn - M(pertC<Q>(i)) * Fn);
+        const M full = f1 + P.rho_ref * (A + B * P.alpha_ref);
+        const M cosv = Fc * invFn * M(inv_len<Q>(i));
+        dd[i] = rhoN * full + sep * cosv * (A + B * abar);
+        ft[i] = f1;
+    }
+    return Fn;
+}
+
+// ---------------------------------------------------------------- block reductions (FP64)
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum (or max for the flagged entries) of NV values over the block, fixed order; result in
+// out[] of thread 0.  tid = linear thread index, nthreads = block size (multiple of 64).
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV], int tid,
+                                             int nthreads, double (&out)[NV]) {
+    __shared__ double sh[NV][16];
+    const int lane = tid & 63, wave = tid >> 6, nw = nthreads >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double r = is_max[k] ? wave_max(v[k]) : wave_sum(v[k]);
+        if (lane == 0) sh[k][wave] = r;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = sh[k][0];
+            for (int w = 1; w < nw; ++w) s = is_max[k] ? fmax(s, sh[k][w]) : s + sh[k][w];
+            out[k] = s;
+        }
+    }
+}
+
+}  // namespace cge

@@ -1,0 +1,196 @@
+// Observables of the current state, reduced in FP64 in a fixed order:
+//   pass A (per node): masses, negative-population count, max |u|, EOS pressure sums over
+//          the two bulk phases (Eq. EOS), max rho_r, site count; rho^N into scratch
+//   wetting of solid nodes
+//   pass B (per node): (1/2)||grad rho^N|| (interface measure), after max rho_r is known:
+//          count of rho_r > max/2 (interface position rule of Sec. III)
+//   final: one block sums the per-block partials and the per-block sink accumulators.
+#include "internal.hpp"
+#include "node.hpp"
+
+namespace cge {
+
+enum {
+    O_MASS_R = 0,
+    O_MASS_B,
+    O_NNEG,
+    O_PIN,
+    O_NIN,
+    O_POUT,
+    O_NOUT,
+    O_NSITES,
+    O_MAXU,
+    O_MAXRR,
+    O_PERIM,
+    O_VHALF
+};
+static_assert(O_VHALF + 1 == CGE_NOBS, "observable count");
+
+template <int Q, typename S, bool WALLS>
+__device__ __forceinline__ void decode_node(const S* __restrict__ src, const uint8_t* __restrict__ flags,
+                                            const Geo& g, int x, int y, int z, long long n,
+                                            const Phys<double>& P, double& rr, double& rb,
+                                            double (&j)[3], int& nneg) {
+    const Nb b = wrap(g, x, y, z);
+    double ft[Q], dd[Q];
+    pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
+    rr = rb = 0.0;
+    j[0] = j[1] = j[2] = 0.0;
+    nneg = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double full = ft[i] + P.rho_ref * (restA<Q>(i) + restB<Q>(i) * P.alpha_ref);
+        const double a = 0.5 * (full + dd[i]), c = 0.5 * (full - dd[i]);
+        rr += a;
+        rb += c;
+        nneg += (a < 0.0) + (c < 0.0);
+        j[0] += Lat<Q>::cx[i] * (a + c);
+        j[1] += Lat<Q>::cy[i] * (a + c);
+        j[2] += Lat<Q>::cz[i] * (a + c);
+    }
+}
+
+__device__ __forceinline__ long long block_id() {
+    return blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+}
+
+template <int Q, typename S, bool WALLS>
+__global__ __launch_bounds__(kTPBX) void k_obs_a(const S* __restrict__ src,
+                                                 const uint8_t* __restrict__ flags,
+                                                 const uint8_t* __restrict__ carry,
+                                                 double* __restrict__ rhoN,
+                                                 double* __restrict__ part, long long nblk, Geo g,
+                                                 Phys<double> P, double zeta) {
+    int x, y, z;
+    long long n;
+    const bool valid = node_xyz(g, x, y, z, n);
+    double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (valid && !(WALLS && flags[n])) {
+        double rr, rb, j[3];
+        int nneg;
+        decode_node<Q, S, WALLS>(src, flags, g, x, y, z, n, P, rr, rb, j, nneg);
+        const double rho = rr + rb;
+        const double rN = (rr - rb) / rho;
+        rhoN[n] = rN;
+        const double p = rr * zeta * (1.0 - P.alpha_r) + rb * zeta * (1.0 - P.alpha_b);
+        v[O_MASS_R] = rr;
+        v[O_MASS_B] = rb;
+        v[O_NNEG] = nneg;
+        if (rN > 0.9) { v[O_PIN] = p; v[O_NIN] = 1.0; }
+        if (rN < -0.9) { v[O_POUT] = p; v[O_NOUT] = 1.0; }
+        const bool site = P.site_rule == 0 ? carry[n] != 0 : fabs(rN) < P.gamma;
+        v[O_NSITES] = site ? 1.0 : 0.0;
+        v[O_MAXU] = sqrt(j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / rho;
+        v[O_MAXRR] = rr;
+    }
+    const bool is_max[10] = {false, false, false, false, false, false, false, false, true, true};
+    double out[10];
+    block_reduce<10>(v, is_max, threadIdx.x, blockDim.x, out);
+    if (threadIdx.x == 0) {
+        const long long bid = block_id();
+        for (int k = 0; k < 10; ++k) part[k * nblk + bid] = out[k];
+    }
+}
+
+template <int Q, typename S, bool WALLS>
+__global__ __launch_bounds__(kTPBX) void k_obs_b(const S* __restrict__ src,
+                                                 const uint8_t* __restrict__ flags,
+                                                 const double* __restrict__ rhoN,
+                                                 const double* __restrict__ res,
+                                                 double* __restrict__ part, long long nblk, Geo g,
+                                                 Phys<double> P) {
+    int x, y, z;
+    long long n;
+    const bool valid = node_xyz(g, x, y, z, n);
+    double v[2] = {0.0, 0.0};
+    if (valid && !(WALLS && flags[n])) {
+        const Nb b = wrap(g, x, y, z);
+        double F[3];
+        gradient<Q>(rhoN, g, b, x, y, z, F);
+        v[0] = 0.5 * sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]);
+        double rr, rb, j[3];
+        int nneg;
+        decode_node<Q, S, WALLS>(src, flags, g, x, y, z, n, P, rr, rb, j, nneg);
+        v[1] = rr > 0.5 * res[O_MAXRR] ? 1.0 : 0.0;
+    }
+    const bool is_max[2] = {false, false};
+    double out[2];
+    block_reduce<2>(v, is_max, threadIdx.x, blockDim.x, out);
+    if (threadIdx.x == 0) {
+        const long long bid = block_id();
+        part[O_PERIM * nblk + bid] = out[0];
+        part[O_VHALF * nblk + bid] = out[1];
+    }
+}
+
+// Sum (max) of the per-block partials k0..k1-1 in block order; one block of 256 threads.
+// res[CGE_NOBS] and res[CGE_NOBS+1] receive the sink and site accumulators.
+__global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ part, long long nblk,
+                                                   int k0, int k1, const double* __restrict__ acc_sink,
+                                                   const long long* __restrict__ acc_sites,
+                                                   long long nacc, double* __restrict__ res) {
+    __shared__ double sh[256];
+    for (int k = k0; k < k1; ++k) {
+        const bool is_max = (k == O_MAXU || k == O_MAXRR);
+        double s = is_max ? 0.0 : 0.0;
+        for (long long b = threadIdx.x; b < nblk; b += blockDim.x) {
+            const double v = part[k * nblk + b];
+            s = is_max ? fmax(s, v) : s + v;
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = sh[0];
+            for (int i = 1; i < (int)blockDim.x; ++i) t = is_max ? fmax(t, sh[i]) : t + sh[i];
+            res[k] = t;
+        }
+        __syncthreads();
+    }
+    if (acc_sink) {
+        double s = 0.0, c = 0.0;
+        for (long long b = threadIdx.x; b < nacc; b += blockDim.x) {
+            s += acc_sink[b];
+            c += static_cast<double>(acc_sites[b]);
+        }
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < (int)blockDim.x; ++i) t += sh[i];
+            res[CGE_NOBS] = t;
+        }
+        __syncthreads();
+        sh[threadIdx.x] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int i = 0; i < (int)blockDim.x; ++i) t += sh[i];
+            res[CGE_NOBS + 1] = t;
+        }
+    }
+}
+
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status obs_impl(cge_ctx* c) {
+    const Phys<double> P = phys<double>(c);
+    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+    const long long nblk = (long long)gr.x * gr.y * gr.z;
+    double* rhoN = c->obs_part + (long long)CGE_NOBS * nblk;  // N doubles after the partials
+    hipLaunchKernelGGL((k_obs_a<Q, S, WALLS>), gr, bl, 0, c->stream,
+                       static_cast<const S*>(c->pop[c->cur]), c->flags, c->carry, rhoN, c->obs_part,
+                       nblk, c->g, P, Lat<Q>::zeta);
+    if (WALLS)
+        if (cge_status s = wet_field<double>(c, rhoN)) return s;
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, c->stream, c->obs_part, nblk, 0, 10,
+                       (const double*)nullptr, (const long long*)nullptr, 0LL, c->obs_res);
+    hipLaunchKernelGGL((k_obs_b<Q, S, WALLS>), gr, bl, 0, c->stream,
+                       static_cast<const S*>(c->pop[c->cur]), c->flags, rhoN, c->obs_res,
+                       c->obs_part, nblk, c->g, P);
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, c->stream, c->obs_part, nblk, O_PERIM,
+                       CGE_NOBS, c->acc_sink, c->acc_sites, c->acc_len, c->obs_res);
+    return check(c, hipGetLastError(), "observable kernels");
+}
+
+cge_status observables(cge_ctx* c) { CGE_DISPATCH(c, obs_impl, c); }
+
+}  // namespace cge

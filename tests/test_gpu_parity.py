@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the same seeded
+inputs.  Tolerances: populations <= 1e-12 (FP64) and <= 1e-5 (FP32S, frozen site masks)
+relative to t_i(alpha_k) rho_k^in; site masks identical in FP64; drop volume within 0.1 %.
+Sizes span several blocks and a ragged tail in x (nx = 70 with 64-wide blocks)."""
+import numpy as np
+import pytest
+
+from tests.helpers import case, e_pop, gpu_for, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (workload, shape, overrides)
+    "d2q9_phase": ("drop2d", (1, 40, 70), dict(radius=12.0, phi=1e-3)),
+    "d2q9_grad": ("drop2d", (1, 40, 70), dict(radius=12.0, phi=1e-3, site_rule="grad",
+                                              gamma=0.305)),
+    "d2q9_walls_field": ("flat2d", (1, 40, 70), dict(phi=1e-3)),
+    "d2q9_adjoint_field": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3)),
+    "d3q19_grad": ("sphere3d", (14, 16, 70), dict(radius=5.0, phi=1e-3)),
+    "d3q19_walls_ratio": ("sessile3d", (14, 18, 70), dict(radius=6.0, phi=1e-3)),
+}
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_matches_oracle_step_by_step(name):
+    wl, shape, over = CASES[name]
+    w = case(wl, shape, **over)
+    Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
+    _flush(f"[parity fp64] {name} shape={shape}")
+    ora = oracle_for(w)
+    sim = gpu_for(w, "fp64")
+    # initial state and site mask
+    assert e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in, w["solid"]) < 1e-14
+    if w["params"]["site_rule"] == "grad":
+        assert np.array_equal(sim.carry.cpu().numpy(), (ora.fmag() > w["params"]["gamma"]))
+    for step in range(1, 13):
+        sim.step(1)
+        ora.step(1)
+        e = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in, w["solid"])
+        assert e < 1e-12, (step, e)
+        if w["params"]["site_rule"] == "grad":
+            mask_ora = (ora.fmag() > w["params"]["gamma"]).astype(np.uint8)
+            assert np.array_equal(sim.carry.cpu().numpy(), mask_ora), step
+    og, oo = sim.observables(), ora.observables()
+    for k in ("n_sites", "v_half", "n_negative", "site_steps"):
+        assert og[k] == oo[k], k
+    for k in ("mass_r", "mass_b", "sink_total", "perim_grad", "max_u", "p_in", "p_out",
+              "max_rho_r", "v_mass"):
+        assert abs(og[k] - oo[k]) <= 1e-12 * max(1.0, abs(oo[k])), (k, og[k], oo[k])
+    assert og["site_steps"] > 0
+    fl = sim.fields()
+    fo = ora.fields()
+    for k in ("rho_r", "rho_b", "rhoN"):
+        assert np.abs(fl[k].cpu().numpy() - fo[k]).max() < 1e-12, k
+    assert np.abs(fl["u"].cpu().numpy() - fo["u"]).max() < 1e-13
+    sim.close()
+
+
+@pytest.mark.parametrize("name", ["d2q9_grad", "d2q9_walls_field", "d3q19_grad",
+                                  "d3q19_walls_ratio"])
+@pytest.mark.parametrize("precision", ["fp32s"])
+def test_fp32_frozen_mask_within_1e5(name, precision):
+    """FP32 shifted storage against the FP64 oracle with the oracle's site sets imposed
+    (a site decision within rounding of Gamma may legitimately flip in FP32)."""
+    wl, shape, over = CASES[name]
+    w = case(wl, shape, **over)
+    Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
+    _flush(f"[parity {precision} frozen] {name}")
+    ora = oracle_for(w)
+    sim = gpu_for(w, precision)
+    import torch
+    worst = 0.0
+    for step in range(1, 61):
+        mask = (ora.fmag() > w["params"]["gamma"]).astype(np.uint8)
+        sim.carry.copy_(torch.as_tensor(mask, device=sim.carry.device))
+        sim.step(1)
+        ora.step(1, masks=mask[None])
+        if step in (1, 10, 60):
+            e = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in, w["solid"])
+            worst = max(worst, e)
+            assert e < 1e-5, (step, e)
+    _flush(f"  worst e_pop = {worst:.3e}")
+    sim.close()
+
+
+def test_fp64_full_drop2d_2000_steps():
+    """The 128^2 D2Q9 drop (|rho^N| < 0.5 site rule, phi = 1e-5) in full, FP64."""
+    w = case("drop2d", None)
+    _flush("[parity fp64] drop2d 128x128 2000 steps")
+    ora = oracle_for(w)
+    sim = gpu_for(w, "fp64")
+    for n in (1, 99, 1900):
+        sim.step(n)
+        ora.step(n)
+    e = e_pop(sim.populations().cpu().numpy(), ora.populations(), 9, (1.0, 1.0))
+    og, oo = sim.observables(), ora.observables()
+    _flush(f"  e_pop = {e:.3e}  v_mass gpu {og['v_mass']:.10f} oracle {oo['v_mass']:.10f}")
+    assert e < 1e-12
+    assert og["site_steps"] == oo["site_steps"]
+    assert abs(og["v_mass"] - oo["v_mass"]) < 1e-12 * oo["v_mass"]
+    sim.close()
+
+
+def test_fp32_drop2d_volume_and_frozen_error():
+    """FP32 shifted storage on the 128^2 drop: free run volume within 0.1 % of the oracle's
+    over 2000 steps; frozen-mask population error <= 1e-5 at steps 1, 100, 2000."""
+    import torch
+    w = case("drop2d", None)
+    _flush("[parity fp32s] drop2d 128x128 2000 steps")
+    ora = oracle_for(w)
+    masks = []
+    v_ora = []
+    for n in range(2000):
+        masks.append(ora.step(1, log_masks=True)[0])
+        if n + 1 in (1, 100, 500, 1000, 2000):
+            v_ora.append(ora.observables()["v_mass"])
+    f_ora_end = ora.populations()
+    # free run
+    sim = gpu_for(w, "fp32s")
+    v_gpu = []
+    done = 0
+    for n in (1, 100, 500, 1000, 2000):
+        sim.step(n - done)
+        done = n
+        v_gpu.append(sim.observables()["v_mass"])
+    rel = max(abs(a - b) / b for a, b in zip(v_gpu, v_ora))
+    _flush(f"  free-run volume rel. error {rel:.3e}")
+    assert rel < 1e-3
+    sim.close()
+    # frozen masks: the GPU takes the oracle's site sets through the carried mask
+    p = dict(w["params"], site_rule="grad")
+    w2 = dict(w, params=p)
+    sim = gpu_for(w2, "fp32s")
+    ora2 = oracle_for(w)
+    errs = {}
+    for n in range(1, 2001):
+        sim.carry.copy_(torch.as_tensor(masks[n - 1], device=sim.carry.device))
+        sim.step(1)
+        if n in (1, 100):
+            ora2.step(n - (1 if n == 100 else 0))
+            errs[n] = e_pop(sim.populations().cpu().numpy(), ora2.populations(), 9, (1.0, 1.0))
+    errs[2000] = e_pop(sim.populations().cpu().numpy(), f_ora_end, 9, (1.0, 1.0))
+    _flush(f"  frozen-mask e_pop {errs}")
+    assert max(errs.values()) < 1e-5
+    sim.close()
+
+
+def test_determinism_and_resume_bitwise():
+    import torch
+    w = case("sphere3d", (12, 16, 70), radius=5.0, phi=1e-3)
+    _flush("[determinism/resume] d3q19 12x16x70")
+    runs = []
+    for _ in range(2):
+        sim = gpu_for(w, "fp32s")
+        sim.step(15)
+        runs.append((sim.populations().cpu(), sim.observables()))
+        sim.close()
+    assert torch.equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
+    # checkpoint after 7 steps, resume in a fresh context
+    sim = gpu_for(w, "fp32s")
+    sim.step(7)
+    ck = (sim.populations().clone(), sim.carry.clone(), sim.observables())
+    sim.step(8)
+    ref = (sim.populations().cpu(), sim.observables())
+    sim.close()
+    sim2 = gpu_for(w, "fp32s")
+    sim2.set_populations(ck[0])
+    sim2.carry.copy_(ck[1])
+    sim2.set_counters(ck[2]["step"], ck[2]["site_steps"], ck[2]["sink_total"])
+    sim2.step(8)
+    got = (sim2.populations().cpu(), sim2.observables())
+    # FP32 state round-trips exactly through the FP64 export
+    assert torch.equal(got[0], ref[0])
+    for k in ("mass_r", "mass_b", "n_sites", "site_steps", "step"):
+        assert got[1][k] == ref[1][k], k
+    assert abs(got[1]["sink_total"] - ref[1]["sink_total"]) <= 1e-15 * ref[1]["sink_total"]
+    sim2.close()
+
+
+def test_edge_cases_no_sites_all_sites_and_tiny_domains():
+    _flush("[edge cases]")
+    # Gamma above every gradient: no sites, each component conserved
+    w = case("drop2d", (1, 20, 30), radius=6.0, phi=1e-3, site_rule="grad", gamma=10.0)
+    sim = gpu_for(w, "fp64")
+    a = sim.observables()
+    sim.step(5)
+    b = sim.observables()
+    assert b["site_steps"] == 0 and abs(a["mass_r"] - b["mass_r"]) < 1e-12
+    sim.close()
+    # Gamma below zero: every fluid node is a site every step
+    w = case("drop2d", (1, 20, 30), radius=6.0, phi=1e-4, site_rule="grad", gamma=-1.0)
+    sim = gpu_for(w, "fp64")
+    ora = oracle_for(w)
+    sim.step(4)
+    ora.step(4)
+    assert sim.observables()["site_steps"] == 4 * 600
+    assert e_pop(sim.populations().cpu().numpy(), ora.populations(), 9, (1.0, 1.0)) < 1e-12
+    sim.close()
+    # degenerate domains: one node wide in x, 1x1x1 in 3D
+    for shape, wl in (((1, 16, 1), "drop2d"), ((1, 1, 1), "sphere3d"), ((3, 1, 5), "sphere3d")):
+        w = case(wl, shape, radius=3.0, phi=1e-3, site_rule="grad", gamma=0.305)
+        sim = gpu_for(w, "fp64")
+        ora = oracle_for(w)
+        sim.step(3)
+        ora.step(3)
+        Q = w["params"]["Q"]
+        assert e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, (1.0, 1.0)) < 1e-12
+        sim.close()
