@@ -29,6 +29,39 @@ def algorithmic_bytes_per_node(Q, precision, walls=False, phi_field=False):
     return 2 * Q * 2 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
 
 
+STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fused", "fused")}
+
+
+def sources_sha():
+    """Hash of the HIP sources, to tell whether a stored counter summary still applies."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2412_14859_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, n, precision):
+    """HBM bytes per step measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (copy-calibrated)
+    for this kernel and workload, if the summary under profiles/ was taken on the current
+    sources; else None."""
+    tag = STEP_KERNELS[kernel][1]
+    path = os.path.join(ROOT, "profiles", f"{tag}_d3q19_{n}cube_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ": " in line and not line.startswith(" "):
+                k, v = line.split(": ", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != sources_sha():
+        return None
+    return float(kv["step_traffic_bytes"])
+
+
 def run_leg(workload, precision, steps, warmup, kernel="auto"):
     import torch
     from paper_2412_14859_amd import cgevap
@@ -68,6 +101,27 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
     del sim
     torch.cuda.empty_cache()
     return res
+
+
+def copy_probe_gbs(nbytes=1 << 30, reps=5):
+    """Achievable HBM bandwidth: the library's streaming copy kernel over nbytes, timed with
+    events on torch's current stream (the stream the probe is launched on); read + write."""
+    import torch
+    from paper_2412_14859_amd import cgevap
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    cgevap.copy_probe(dst, src, nbytes, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        cgevap.copy_probe(dst, src, nbytes, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
 def cpu_baseline(seconds_hint=15.0):
@@ -111,6 +165,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     n = args.size
     w = inputs.workload("sphere3d", shape=(n, n, n), radius=64.0 * n / 256)
+    copy_gbs, copy_ms = copy_probe_gbs()
     main_leg = run_leg(w, args.precision, args.steps, args.warmup, args.kernel)
     legs = {}
     if not args.no_legs:
@@ -119,6 +174,9 @@ def main():
                 legs[prec] = run_leg(w, prec, max(args.steps // 2, 10), args.warmup, args.kernel)
     N = n ** 3
     achieved = main_leg["achieved_gbs"]
+    step_ms = main_leg["kernel_ms_per_step"]
+    tb = stored_traffic(main_leg["kernel"], n, args.precision)
+    traffic = None if tb is None else round(tb / (step_ms * 1e-3) / 1e9, 1)
     out = {
         "metric": "MLUPS (D3Q19 CG + reaction-limited evaporation step)",
         "value": round(main_leg["mlups"], 1),
@@ -130,18 +188,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32s": "f32", "fp64": "f64", "fp16s": "f16-storage/f32"}[args.precision],
+        "dtype": {"fp32s": "f64", "fp64": "f64", "fp16s": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"D3Q19 {n}^3 periodic, spherical drop R={64 * n // 256}, "
                                "unit density ratio, tau=1, A=5e-4, beta=0.7, phi=1e-5, "
                                "Gamma=0.305, Sbar=3",
-                   "nodes": N, "precision": args.precision, "kernel": main_leg["kernel"]},
+                   "nodes": N, "storage": {"fp32s": "fp32 shifted", "fp64": "fp64",
+                                           "fp16s": "fp16 shifted, stochastic rounding"}[args.precision],
+                   "kernel": main_leg["kernel"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": main_leg["kernel"],
-                     "kernel_ms_per_launch": round(main_leg["kernel_ms_per_step"], 4),
-                     "bytes_per_node": main_leg["bytes_per_node"]},
+                     "traffic": traffic,
+                     "traffic_bytes_per_step": tb,
+                     "kernel": STEP_KERNELS[main_leg["kernel"]][0],
+                     "kernel_ms_per_step": round(main_leg["kernel_ms_per_step"], 4),
+                     "bytes_per_node": main_leg["bytes_per_node"],
+                     "copy_probe_gbs": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4)},
         "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in legs.items()},
     }

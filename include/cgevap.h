@@ -44,8 +44,10 @@ typedef enum {
 typedef enum { CGE_D2Q9 = 9, CGE_D3Q19 = 19 } cge_lattice;
 
 /* Population storage.  FP64: doubles, FP64 arithmetic.  FP32S: floats holding shifted
- * values (see cge_bind), FP32 arithmetic.  FP16S: half-precision storage of the same
- * shifted values with FP32 arithmetic and stochastic rounding on store. */
+ * values (see cge_bind), FP64 arithmetic in registers (the step is bandwidth-bound, and
+ * FP32 arithmetic on near-uniform, quasi-steady fields repeats the same rounding at every
+ * node every step, which drifts the component masses).  FP16S: half-precision storage of
+ * the same shifted values with FP32 arithmetic and stochastic rounding on store. */
 typedef enum { CGE_FP64 = 0, CGE_FP32S = 1, CGE_FP16S = 2 } cge_precision;
 
 /* Evaporation-site rule.  GRAD_GT: ||F_{n-1}(x)|| > gamma with the colour gradient of the
@@ -58,8 +60,7 @@ typedef enum { CGE_KERNEL_AUTO = 0, CGE_KERNEL_TWOPASS = 1, CGE_KERNEL_FUSED = 2
 
 typedef struct {
     int lattice;            /* cge_lattice                                               */
-    int nx, ny, nz;         /* nodes per axis, >= 1 (>= 3 on every axis longer than 1);  */
-                            /* nz == 1 for D2Q9                                          */
+    int nx, ny, nz;         /* nodes per axis, >= 1 (ny, nz <= 65535); nz == 1 for D2Q9  */
     int precision;          /* cge_precision                                             */
     double rho_in[2];       /* bulk densities of red and blue; define alpha_k (Sec. II.A) */
     double tau[2];          /* relaxation times, > 1/2 (Sec. II.A)                        */
@@ -79,7 +80,8 @@ typedef struct {
     long long step;         /* steps taken since the last init / counter reset            */
     long long n_sites;      /* sites the next step will use                               */
     long long v_half;       /* #nodes with rho_r > max(rho_r)/2 (interface, Sec. III)     */
-    long long n_negative;   /* #negative populations (either component)                   */
+    long long n_negative;   /* #populations f_i^k < -1e-6 rho_k^in t_i(alpha_k) (negative */
+                            /* beyond rounding noise; the sink can drive f_0^r below 0)   */
     long long site_steps;   /* cumulative number of (site, step) sink applications        */
     double mass_r, mass_b;  /* total red and blue mass                                    */
     double sink_total;      /* cumulative mass moved red -> blue by the sink              */
@@ -130,6 +132,14 @@ cge_status cge_init_equilibrium(cge_ctx* ctx, const double* rho_r, const double*
  * touch the site mask or counters (see cge_reset_sites, cge_set_counters). */
 cge_status cge_set_populations(cge_ctx* ctx, const double* f);
 cge_status cge_get_populations(cge_ctx* ctx, double* f);
+
+/* Raw snapshot of the state in the library's own encoding (bitwise exact round trip): the
+ * current population buffer followed by the site mask, cge_state_bytes() bytes of device
+ * memory at dst / src.  Counters are not included (see cge_set_counters).  Used for
+ * checkpoint / resume and by the adjoint's recomputation segments. */
+size_t cge_state_bytes(const cge_params* params);
+cge_status cge_save_state(cge_ctx* ctx, void* dst);
+cge_status cge_load_state(cge_ctx* ctx, const void* src);
 
 /* Recompute the site mask from the current state (gradient of its phase field). */
 cge_status cge_reset_sites(cge_ctx* ctx);

@@ -29,7 +29,10 @@
  *     C_i = W_i (i >= 1), C_0 = c_s^2 - (1 - W_0): sum C_i = c_s^2 and
  *     sum C_i c_ia c_ib = c_s^2 delta_ab, which fixes the interfacial stress to sigma.
  *   - D2Q9 is built with the same constructions (the paper uses D3Q19 only).
- *   - ||F||^2 <= 1e-24: perturbation and cos(theta) are taken as 0; cos(theta_0) = 0.
+ *   - The angle theta_i between F and c_i is undefined at F = 0.  cos(theta_i) is taken as 0
+ *     where ||F|| <= 1e-5 (far from interfaces, and at points where F vanishes by symmetry,
+ *     where its direction is rounding noise); cos(theta_0) = 0 for the rest direction.  The
+ *     perturbation is continuous at F = 0 (it vanishes with ||F||) and is applied for F != 0.
  *   - Step 0 uses the gradient of the initial phase field as the "previous" gradient.
  *   - Site criterion is strict (>).  An alternative local rule |rho^N_pre| < Gamma
  *     (site_rule = 1) uses the current pre-sink phase field.
@@ -426,7 +429,8 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
         colour_gradient(s, n, Fv);
         double F2 = Fv[0] * Fv[0] + Fv[1] * Fv[1] + Fv[2] * Fv[2];
         double Fn = sqrt(F2);
-        int has_grad = F2 > 1e-24;
+        int has_grad = F2 > 0.0;
+        int has_dir = Fn > 1e-5;
 
         for (int i = 0; i < Q; ++i) {
             double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
@@ -439,7 +443,7 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
             if (has_grad) {
                 double Fc = Fv[0] * L->c[i][0] + Fv[1] * L->c[i][1] + Fv[2] * L->c[i][2];
                 fc += 2.25 * (s->p.sigma / tau) * Fn * (L->W[i] * Fc * Fc / F2 - L->C[i]);
-                if (i != 0) {
+                if (i != 0 && has_dir) {
                     double cn = sqrt((double)(L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] +
                                               L->c[i][2] * L->c[i][2]));
                     cosv = Fc / (Fn * cn);
@@ -526,8 +530,9 @@ int ora_observables(ora_ctx* s, ora_obs* o) {
             double a = F(s, 0, i)[n], b = F(s, 1, i)[n];
             rr += a;
             rb += b;
-            if (a < 0.0) o->n_negative++;
-            if (b < 0.0) o->n_negative++;
+            /* negative beyond rounding noise: below -1e-6 of the bulk equilibrium value */
+            if (a < -1e-6 * s->p.rho_in[0] * rest_weight(&s->L, i, s->alpha[0])) o->n_negative++;
+            if (b < -1e-6 * s->p.rho_in[1] * rest_weight(&s->L, i, s->alpha[1])) o->n_negative++;
             for (int d = 0; d < 3; ++d) j[d] += (a + b) * s->L.c[i][d];
         }
         double rho = rr + rb;

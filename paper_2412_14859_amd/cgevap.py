@@ -20,7 +20,8 @@ ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 
 # every symbol the header declares
 EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
-           "cge_set_populations", "cge_get_populations", "cge_reset_sites", "cge_set_counters",
+           "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
+           "cge_load_state", "cge_reset_sites", "cge_set_counters",
            "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
@@ -71,6 +72,10 @@ def lib():
         L.cge_init_equilibrium.argtypes = [vp, vp, vp, vp]
         L.cge_set_populations.argtypes = [vp, vp]
         L.cge_get_populations.argtypes = [vp, vp]
+        L.cge_state_bytes.argtypes = [P(CgeParams)]
+        L.cge_state_bytes.restype = C.c_size_t
+        L.cge_save_state.argtypes = [vp, vp]
+        L.cge_load_state.argtypes = [vp, vp]
         L.cge_reset_sites.argtypes = [vp]
         L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
         L.cge_step.argtypes = [vp, C.c_longlong]
@@ -219,6 +224,18 @@ class Simulation:
         assert t.numel() == 2 * self.Q * self.N
         self._check(lib().cge_set_populations(self._ctx, _ptr(t)))
         self.torch.cuda.current_stream(self.device).synchronize()
+
+    def save_state(self, out=None):
+        """Raw snapshot (encoded populations + site mask) as a uint8 device tensor."""
+        if out is None:
+            cp = make_params(self.params, self.precision)
+            out = self.torch.empty(lib().cge_state_bytes(C.byref(cp)), dtype=self.torch.uint8,
+                                   device=self.device)
+        self._check(lib().cge_save_state(self._ctx, _ptr(out)))
+        return out
+
+    def load_state(self, snap):
+        self._check(lib().cge_load_state(self._ctx, _ptr(snap)))
 
     def reset_sites(self):
         self._check(lib().cge_reset_sites(self._ctx))

@@ -37,6 +37,8 @@ Phys<M> phys(const cge_ctx* c) {
     P.alpha_ref = M(a[1]);
     P.alpha_r = M(a[0]);
     P.alpha_b = M(a[1]);
+    P.rho_in_r = M(c->p.rho_in[0]);
+    P.rho_in_b = M(c->p.rho_in[1]);
     P.omega_r = M(1.0 / c->p.tau[0]);
     P.omega_b = M(1.0 / c->p.tau[1]);
     P.sigma = M(c->p.sigma);
@@ -167,7 +169,7 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     }
     c->kernel = (params->kernel == CGE_KERNEL_TWOPASS || !fused_supported(c)) ? CGE_KERNEL_TWOPASS
                                                                                 : CGE_KERNEL_FUSED;
-    const size_t mbytes = params->precision == CGE_FP64 ? 8 : 4;
+    const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type
     c->acc_len = twopass_blocks(c);
     if (fused_supported(c) && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
     c->obs_blocks = twopass_blocks(c);
@@ -238,6 +240,35 @@ cge_status cge_get_populations(cge_ctx* c, double* f) {
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (!f) return fail(c, CGE_EINVAL, "f is NULL");
     return get_populations(c, f);
+}
+
+size_t cge_state_bytes(const cge_params* p) {
+    const size_t pb = cge_population_bytes(p);
+    return pb ? pb + (size_t)p->nx * p->ny * p->nz : 0;
+}
+
+cge_status cge_save_state(cge_ctx* c, void* dst) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (!dst) return fail(c, CGE_EINVAL, "dst is NULL");
+    const size_t pb = cge_population_bytes(&c->p);
+    if (cge_status s = check(c, hipMemcpyAsync(dst, c->pop[c->cur], pb, hipMemcpyDeviceToDevice,
+                                               c->stream), "state save"))
+        return s;
+    return check(c, hipMemcpyAsync(static_cast<char*>(dst) + pb, c->carry, (size_t)c->g.N,
+                                   hipMemcpyDeviceToDevice, c->stream), "state save");
+}
+
+cge_status cge_load_state(cge_ctx* c, const void* src) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (!src) return fail(c, CGE_EINVAL, "src is NULL");
+    const size_t pb = cge_population_bytes(&c->p);
+    if (cge_status s = check(c, hipMemcpyAsync(c->pop[c->cur], src, pb, hipMemcpyDeviceToDevice,
+                                               c->stream), "state load"))
+        return s;
+    return check(c, hipMemcpyAsync(c->carry, static_cast<const char*>(src) + pb, (size_t)c->g.N,
+                                   hipMemcpyDeviceToDevice, c->stream), "state load");
 }
 
 cge_status cge_reset_sites(cge_ctx* c) {

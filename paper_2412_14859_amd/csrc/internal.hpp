@@ -105,8 +105,8 @@ Phys<M> phys(const cge_ctx* c);
                 return w_ ? FN<9, double, double, true>(__VA_ARGS__)                        \
                           : FN<9, double, double, false>(__VA_ARGS__);                      \
             case 91:                                                                        \
-                return w_ ? FN<9, float, float, true>(__VA_ARGS__)                          \
-                          : FN<9, float, float, false>(__VA_ARGS__);                        \
+                return w_ ? FN<9, float, double, true>(__VA_ARGS__)                          \
+                          : FN<9, float, double, false>(__VA_ARGS__);                        \
             case 92:                                                                        \
                 return w_ ? FN<9, _Float16, float, true>(__VA_ARGS__)                       \
                           : FN<9, _Float16, float, false>(__VA_ARGS__);                     \
@@ -114,8 +114,8 @@ Phys<M> phys(const cge_ctx* c);
                 return w_ ? FN<19, double, double, true>(__VA_ARGS__)                       \
                           : FN<19, double, double, false>(__VA_ARGS__);                     \
             case 191:                                                                       \
-                return w_ ? FN<19, float, float, true>(__VA_ARGS__)                         \
-                          : FN<19, float, float, false>(__VA_ARGS__);                       \
+                return w_ ? FN<19, float, double, true>(__VA_ARGS__)                         \
+                          : FN<19, float, double, false>(__VA_ARGS__);                       \
             case 192:                                                                       \
                 return w_ ? FN<19, _Float16, float, true>(__VA_ARGS__)                      \
                           : FN<19, _Float16, float, false>(__VA_ARGS__);                    \

@@ -71,6 +71,7 @@ struct Phys {
     M rho_ref;        // codec shift: rho_ref * t_i(alpha_ref) is subtracted from f_i
     M alpha_ref;
     M alpha_r, alpha_b;
+    M rho_in_r, rho_in_b;  // bulk densities of the two components
     M omega_r, omega_b;  // 1/tau_k
     M sigma, beta;
     M gamma;

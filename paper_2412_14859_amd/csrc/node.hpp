@@ -11,6 +11,8 @@
 // with rho_r/rho = (1 + rho^N)/2 and rho_r rho_b / rho^2 = (1 - rho^N^2)/4.
 #pragma once
 
+#include <type_traits>
+
 #include "lattice.hpp"
 
 namespace cge {
@@ -136,7 +138,11 @@ __device__ __forceinline__ void moments(const M (&ft)[Q], const M (&dd)[Q], M& d
 
 // Site decision and sink for one node (site criterion; Eqs. relation, exchange).
 // Returns the sink s applied (0 if not a site).  dsum is pre-sink on entry.
-template <typename M>
+// The flux field is stored in double next to FP64 populations and in float otherwise.
+template <typename S>
+using PhiT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
+
+template <typename S, typename M>
 __device__ __forceinline__ M site_sink(const Phys<M>& P, const uint8_t* __restrict__ carry,
                                        const void* __restrict__ phi_field, long long n, M rho,
                                        M dsum) {
@@ -144,7 +150,7 @@ __device__ __forceinline__ M site_sink(const Phys<M>& P, const uint8_t* __restri
     if (P.site_rule == 0) m = carry[n] != 0;
     else m = fabs(dsum / rho) < P.gamma;
     if (!m) return M(0);
-    const M phi = phi_field ? static_cast<const M*>(phi_field)[n] : P.phi;
+    const M phi = phi_field ? static_cast<M>(static_cast<const PhiT<S>*>(phi_field)[n]) : P.phi;
     return phi * P.inv_sbar;
 }
 
@@ -167,20 +173,19 @@ __device__ __forceinline__ void gradient(const R* __restrict__ rhoN, const Geo& 
 
 // BGK collision with harmonic tau and alpha-equilibrium (Eqs. collision, feq), perturbation
 // (Eq. perturb) and recolouring (Eq. recolor), in place on the encoded populations.
-// Inputs are post-sink.  Returns ||F||.
+// Inputs are post-sink; drho = rho - rho_ref = sum_i ft_i.  Returns ||F||.
 template <int Q, typename M>
-__device__ __forceinline__ M collide(M (&ft)[Q], M (&dd)[Q], M rho, M rhoN, const M (&u)[3],
-                                     const M (&F)[3], const Phys<M>& P) {
+__device__ __forceinline__ M collide(M (&ft)[Q], M (&dd)[Q], M drho, M rho, M rhoN,
+                                     const M (&u)[3], const M (&F)[3], const Phys<M>& P) {
     const M pr = M(0.5) * (M(1) + rhoN);  // rho_r / rho
     const M pb = M(0.5) * (M(1) - rhoN);  // rho_b / rho
     const M omega = pr * P.omega_r + pb * P.omega_b;
     const M abar = pr * P.alpha_r + pb * P.alpha_b;
-    const M drho = rho - P.rho_ref;
     // rho t_i(abar) - rho_ref t_i(alpha_ref) = A_i drho + B_i (rho abar - rho_ref alpha_ref)
     const M dB = rho * (abar - P.alpha_ref) + drho * P.alpha_ref;
     const M uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const M F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-    const bool hg = F2 > M(1e-24);
+    const bool hg = F2 > M(0);
     const M Fn = hg ? sqrt(F2) : M(0);
     const M invFn = hg ? M(1) / Fn : M(0);
     const M kp = M(2.25) * P.sigma * omega;                         // (9/4) sigma / tau
@@ -194,7 +199,7 @@ __device__ __forceinline__ M collide(M (&ft)[Q], M (&dd)[Q], M rho, M rhoN, cons
         const M Fc = M(Lat<Q>::cx[i]) * F[0] + M(Lat<Q>::cy[i]) * F[1] + M(Lat<Q>::cz[i]) * F[2];
         f1 += kp * (W * Fc * Fc * invFn - M(pertC<Q>(i)) * Fn);
         const M full = f1 + P.rho_ref * (A + B * P.alpha_ref);
-        const M cosv = Fc * invFn * M(inv_len<Q>(i));
+        const M cosv = Fn > M(1e-5) ? Fc * invFn * M(inv_len<Q>(i)) : M(0);
         dd[i] = rhoN * full + sep * cosv * (A + B * abar);
         ft[i] = f1;
     }

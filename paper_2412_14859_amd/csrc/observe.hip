@@ -43,7 +43,9 @@ __device__ __forceinline__ void decode_node(const S* __restrict__ src, const uin
         const double a = 0.5 * (full + dd[i]), c = 0.5 * (full - dd[i]);
         rr += a;
         rb += c;
-        nneg += (a < 0.0) + (c < 0.0);
+        // negative beyond rounding noise: below -1e-6 of the bulk equilibrium value
+        nneg += (a < -1e-6 * P.rho_in_r * (restA<Q>(i) + restB<Q>(i) * P.alpha_r)) +
+                (c < -1e-6 * P.rho_in_b * (restA<Q>(i) + restB<Q>(i) * P.alpha_b));
         j[0] += Lat<Q>::cx[i] * (a + c);
         j[1] += Lat<Q>::cy[i] * (a + c);
         j[2] += Lat<Q>::cz[i] * (a + c);

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kTPBX) void k_phase(const S* __restrict__ src,
     pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
     moments<Q>(ft, dd, drho, dsum, j);
     const M rho = P.rho_ref + drho;
-    if (apply_sink) dsum -= M(2) * site_sink(P, carry, phi_field, n, rho, dsum);
+    if (apply_sink) dsum -= M(2) * site_sink<S>(P, carry, phi_field, n, rho, dsum);
     rhoN[n] = dsum / rho;
 }
 
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
         moments<Q>(ft, dd, drho, dsum, j);
         const M rho = P.rho_ref + drho;
-        const M s = site_sink(P, carry, phi_field, n, rho, dsum);
+        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum);
         dd[0] -= M(2) * s;
         dsum -= M(2) * s;
         if (s != M(0)) {
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         const M rN = dsum * inv_rho;
         M F[3];
         gradient<Q>(rhoN, g, b, x, y, z, F);
-        const M Fn = collide<Q>(ft, dd, rho, rN, u, F, P);
+        const M Fn = collide<Q>(ft, dd, drho, rho, rN, u, F, P);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N + (uint64_t)n;
