@@ -29,7 +29,8 @@ def algorithmic_bytes_per_node(Q, precision, walls=False, phi_field=False):
     return 2 * Q * 2 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
 
 
-STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fused", "fused")}
+STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fused", "fused"),
+                "k_finish": ("k_moments+k_finish", "split")}
 
 
 def sources_sha():
@@ -150,7 +151,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32s", choices=["fp64", "fp32s", "fp16s"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused", "split"])
     ap.add_argument("--size", type=int, default=256, help="edge of the cubic box")
     ap.add_argument("--no-legs", action="store_true", help="skip the FP64 and FP16S legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

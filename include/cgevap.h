@@ -55,8 +55,22 @@ typedef enum { CGE_FP64 = 0, CGE_FP32S = 1, CGE_FP16S = 2 } cge_precision;
  * PHASE_LT: |rho^N(x)| < gamma from the current pre-sink phase field (a local variant). */
 typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1 } cge_site_rule;
 
-/* Step implementation.  AUTO picks the fastest supported one. */
-typedef enum { CGE_KERNEL_AUTO = 0, CGE_KERNEL_TWOPASS = 1, CGE_KERNEL_FUSED = 2 } cge_kernel;
+/* Step implementation.
+ *   TWOPASS: any lattice, geometry and relaxation times; writes the post-sink phase field to
+ *            library scratch and pulls the populations twice.
+ *   FUSED:   single pass, D3Q19 without solid nodes (CGE_EUNSUPPORTED at cge_create for
+ *            D2Q9, at cge_bind with flags); recomputes the phase field of each tile's halo.
+ *   SPLIT:   unit relaxation times (tau[0] == tau[1] == 1, else CGE_EUNSUPPORTED at
+ *            cge_create), any lattice and geometry; the first pass writes the post-sink
+ *            moments, the second finishes the step from them without re-reading populations.
+ *   AUTO:    SPLIT where supported, else FUSED where supported, else TWOPASS.
+ * All give the same results up to rounding. */
+typedef enum {
+    CGE_KERNEL_AUTO = 0,
+    CGE_KERNEL_TWOPASS = 1,
+    CGE_KERNEL_FUSED = 2,
+    CGE_KERNEL_SPLIT = 3
+} cge_kernel;
 
 typedef struct {
     int lattice;            /* cge_lattice                                               */

@@ -29,10 +29,12 @@
  *     C_i = W_i (i >= 1), C_0 = c_s^2 - (1 - W_0): sum C_i = c_s^2 and
  *     sum C_i c_ia c_ib = c_s^2 delta_ab, which fixes the interfacial stress to sigma.
  *   - D2Q9 is built with the same constructions (the paper uses D3Q19 only).
- *   - The angle theta_i between F and c_i is undefined at F = 0.  cos(theta_i) is taken as 0
- *     where ||F|| <= 1e-5 (far from interfaces, and at points where F vanishes by symmetry,
- *     where its direction is rounding noise); cos(theta_0) = 0 for the rest direction.  The
- *     perturbation is continuous at F = 0 (it vanishes with ||F||) and is applied for F != 0.
+ *   - The angle theta_i between F and c_i is undefined at F = 0, and where F vanishes by
+ *     symmetry inside a mixture its direction is rounding noise.  cos(theta_i) is multiplied
+ *     by a fade g(||F||) = 0 for ||F|| <= 1e-5, ||F||/1e-5 - 1 up to 2e-5, and 1 above
+ *     (continuous, so rounding near the cut moves the result only a little; real interfaces
+ *     have ||F|| ~ 0.1).  cos(theta_0) = 0 for the rest direction.  The perturbation is
+ *     continuous at F = 0 (it vanishes with ||F||) and is applied for F != 0.
  *   - Step 0 uses the gradient of the initial phase field as the "previous" gradient.
  *   - Site criterion is strict (>).  An alternative local rule |rho^N_pre| < Gamma
  *     (site_rule = 1) uses the current pre-sink phase field.
@@ -430,7 +432,7 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
         double F2 = Fv[0] * Fv[0] + Fv[1] * Fv[1] + Fv[2] * Fv[2];
         double Fn = sqrt(F2);
         int has_grad = F2 > 0.0;
-        int has_dir = Fn > 1e-5;
+        double fade = Fn >= 2e-5 ? 1.0 : (Fn > 1e-5 ? Fn / 1e-5 - 1.0 : 0.0);
 
         for (int i = 0; i < Q; ++i) {
             double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
@@ -443,10 +445,10 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
             if (has_grad) {
                 double Fc = Fv[0] * L->c[i][0] + Fv[1] * L->c[i][1] + Fv[2] * L->c[i][2];
                 fc += 2.25 * (s->p.sigma / tau) * Fn * (L->W[i] * Fc * Fc / F2 - L->C[i]);
-                if (i != 0 && has_dir) {
+                if (i != 0) {
                     double cn = sqrt((double)(L->c[i][0] * L->c[i][0] + L->c[i][1] * L->c[i][1] +
                                               L->c[i][2] * L->c[i][2]));
-                    cosv = Fc / (Fn * cn);
+                    cosv = Fc / (Fn * cn) * fade;
                 }
             }
             /* recolouring (Eq. recolor); f_i^eq(rho, 0) = rho t_i(abar) */

@@ -134,7 +134,7 @@ static const char* validate(const cge_params* p) {
     if (!is_fin(p->gamma)) return "gamma must be finite";
     if (p->site_rule != CGE_SITE_GRAD_GT && p->site_rule != CGE_SITE_PHASE_LT)
         return "unknown site rule";
-    if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_FUSED) return "unknown kernel";
+    if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_SPLIT) return "unknown kernel";
     return nullptr;
 }
 
@@ -163,17 +163,24 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
         delete c;
         return CGE_EDEVICE;
     }
-    if (params->kernel == CGE_KERNEL_FUSED && !fused_supported(c)) {
+    // the fused step needs D3Q19 and no solid nodes (the latter is known at cge_bind); the
+    // split step needs unit relaxation times
+    const bool unit = split_supported(c);
+    if ((params->kernel == CGE_KERNEL_FUSED && c->Q != 19) ||
+        (params->kernel == CGE_KERNEL_SPLIT && !unit)) {
         delete c;
         return CGE_EUNSUPPORTED;
     }
-    c->kernel = (params->kernel == CGE_KERNEL_TWOPASS || !fused_supported(c)) ? CGE_KERNEL_TWOPASS
-                                                                                : CGE_KERNEL_FUSED;
+    c->kernel = CGE_KERNEL_TWOPASS;  // resolved at cge_bind
+    const bool need_mom = unit && (params->kernel == CGE_KERNEL_AUTO ||
+                                   params->kernel == CGE_KERNEL_SPLIT);
     const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type
     c->acc_len = twopass_blocks(c);
-    if (fused_supported(c) && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
+    if (c->Q == 19 && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
     c->obs_blocks = twopass_blocks(c);
-    bool ok = hipMalloc(&c->rhoN, c->g.N * mbytes) == hipSuccess &&
+    bool ok = (c->Q != 19 || hipMalloc(&c->carry2, c->g.N) == hipSuccess) &&
+              (!need_mom || hipMalloc(&c->mom, split_scratch_bytes(params)) == hipSuccess) &&
+              hipMalloc(&c->rhoN, c->g.N * mbytes) == hipSuccess &&
               hipMalloc(&c->acc_sink, c->acc_len * sizeof(double)) == hipSuccess &&
               hipMalloc(&c->acc_sites, c->acc_len * sizeof(long long)) == hipSuccess &&
               hipMalloc(&c->obs_part, (CGE_NOBS * c->obs_blocks + c->g.N) * sizeof(double)) ==
@@ -198,12 +205,24 @@ cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
     if (!c) return CGE_EINVAL;
     if (!pop_a || !pop_b || !carry) return fail(c, CGE_EINVAL, "pop_a, pop_b, carry required");
     if (pop_a == pop_b) return fail(c, CGE_EINVAL, "pop_a and pop_b must differ");
+    if (flags && c->p.kernel == CGE_KERNEL_FUSED)
+        return fail(c, CGE_EUNSUPPORTED, "the fused step does not support solid nodes");
     c->pop[0] = pop_a;
     c->pop[1] = pop_b;
     c->cur = 0;
     c->carry = carry;
     c->flags = flags;
     c->phi_field = phi_field;
+    switch (c->p.kernel) {
+        case CGE_KERNEL_TWOPASS: c->kernel = CGE_KERNEL_TWOPASS; break;
+        case CGE_KERNEL_FUSED:
+            c->kernel = fused_supported(c) ? CGE_KERNEL_FUSED : CGE_KERNEL_TWOPASS;
+            break;
+        case CGE_KERNEL_SPLIT: c->kernel = CGE_KERNEL_SPLIT; break;
+        default:
+            c->kernel = c->mom ? CGE_KERNEL_SPLIT
+                               : (fused_supported(c) ? CGE_KERNEL_FUSED : CGE_KERNEL_TWOPASS);
+    }
     c->bound = true;
     return CGE_OK;
 }
@@ -293,7 +312,11 @@ cge_status cge_step(cge_ctx* c, long long nsteps) {
     if (nsteps < 0) return fail(c, CGE_EINVAL, "nsteps must be >= 0");
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps == 0) return CGE_OK;
-    return c->kernel == CGE_KERNEL_FUSED ? fused_steps(c, nsteps) : twopass_steps(c, nsteps);
+    switch (c->kernel) {
+        case CGE_KERNEL_FUSED: return fused_steps(c, nsteps);
+        case CGE_KERNEL_SPLIT: return split_steps(c, nsteps);
+        default: return twopass_steps(c, nsteps);
+    }
 }
 
 cge_status cge_observables(cge_ctx* c, cge_obs* out) {
@@ -355,7 +378,11 @@ cge_status cge_timing(cge_ctx* c, double* total_ms, long long* steps) {
 
 const char* cge_kernel_name(const cge_ctx* c) {
     if (!c) return "";
-    return c->kernel == CGE_KERNEL_FUSED ? "k_fused" : "k_collide";
+    switch (c->kernel) {
+        case CGE_KERNEL_FUSED: return "k_fused";
+        case CGE_KERNEL_SPLIT: return "k_finish";
+        default: return "k_collide";
+    }
 }
 
 cge_status cge_lattice_tables(int lattice, double* W, double* A, double* B, double* C, int* cv,
@@ -394,6 +421,8 @@ void cge_destroy(cge_ctx* c) {
     if (!c) return;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     (void)hipFree(c->rhoN);
+    (void)hipFree(c->carry2);
+    (void)hipFree(c->mom);
     (void)hipFree(c->acc_sink);
     (void)hipFree(c->acc_sites);
     (void)hipFree(c->obs_part);

@@ -28,6 +28,8 @@ struct cge_ctx {
     bool bound = false;
     // library scratch
     void* rhoN = nullptr;           // N elements of the arithmetic type
+    unsigned char* carry2 = nullptr;  // second site-mask buffer of the fused step (N bytes)
+    void* mom = nullptr;              // moment record of the split step ([4][N])
     double* acc_sink = nullptr;     // per-block cumulative sink (FP64)
     long long* acc_sites = nullptr; // per-block cumulative site count
     long long acc_len = 0;
@@ -55,6 +57,9 @@ cge_status check(cge_ctx* c, hipError_t e, const char* what);
 // step implementations: launch `nsteps` steps, swapping c->cur
 cge_status twopass_steps(cge_ctx* c, long long nsteps);
 cge_status fused_steps(cge_ctx* c, long long nsteps);
+cge_status split_steps(cge_ctx* c, long long nsteps);
+bool split_supported(const cge_ctx* c);
+size_t split_scratch_bytes(const cge_params* p);
 bool fused_supported(const cge_ctx* c);
 long long twopass_blocks(const cge_ctx* c);
 long long fused_blocks(const cge_ctx* c);

@@ -50,14 +50,18 @@ __device__ __forceinline__ _Float16 sr_half(float v, uint32_t r) {
     return up == h_is_hi ? h : o;
 }
 
-// store with the storage type's rounding: nearest for double/float, stochastic for half
+// rounding to the storage type: nearest for double/float, stochastic for half
 template <typename S, typename M>
-__device__ __forceinline__ void st(S* p, M v, uint64_t key) {
-    *p = static_cast<S>(v);
+__device__ __forceinline__ S enc(M v, uint64_t key) {
+    return static_cast<S>(v);
 }
 template <>
-__device__ __forceinline__ void st<_Float16, float>(_Float16* p, float v, uint64_t key) {
-    *p = sr_half(v, static_cast<uint32_t>(mix64(key) >> 32));
+__device__ __forceinline__ _Float16 enc<_Float16, float>(float v, uint64_t key) {
+    return sr_half(v, static_cast<uint32_t>(mix64(key) >> 32));
+}
+template <typename S, typename M>
+__device__ __forceinline__ void st(S* p, M v, uint64_t key) {
+    *p = enc<S, M>(v, key);
 }
 
 // neighbour coordinates with periodic wrap
@@ -154,6 +158,15 @@ __device__ __forceinline__ M site_sink(const Phys<M>& P, const uint8_t* __restri
     return phi * P.inv_sbar;
 }
 
+// The same decision from values fetched ahead of the populations: the carried mask byte and
+// the node's flux (P.phi when no field is bound).
+template <typename M>
+__device__ __forceinline__ M site_sink_pre(const Phys<M>& P, uint8_t carry_byte, M phi, M rho,
+                                           M dsum) {
+    const bool m = P.site_rule == 0 ? carry_byte != 0 : fabs(dsum / rho) < P.gamma;
+    return m ? phi * P.inv_sbar : M(0);
+}
+
 // Colour gradient by the compact isotropic stencil: F = (1/c_s^2) sum_i W_i rho^N(x+c_i) c_i
 template <int Q, typename M, typename R>
 __device__ __forceinline__ void gradient(const R* __restrict__ rhoN, const Geo& g, const Nb& b,
@@ -172,11 +185,21 @@ __device__ __forceinline__ void gradient(const R* __restrict__ rhoN, const Geo& 
 }
 
 // BGK collision with harmonic tau and alpha-equilibrium (Eqs. collision, feq), perturbation
-// (Eq. perturb) and recolouring (Eq. recolor), in place on the encoded populations.
-// Inputs are post-sink; drho = rho - rho_ref = sum_i ft_i.  Returns ||F||.
-template <int Q, typename M>
-__device__ __forceinline__ M collide(M (&ft)[Q], M (&dd)[Q], M drho, M rho, M rhoN,
-                                     const M (&u)[3], const M (&F)[3], const Phys<M>& P) {
+// (Eq. perturb) and recolouring (Eq. recolor), direction by direction.  Inputs are post-sink
+// moments: drho = rho - rho_ref = sum_i ft_i, rhoN, u; F is the colour gradient.  The new
+// populations depend on the old ones only through ft_i and these moments, so each direction
+// is read with load(i) -> ft_i and written with store(i, ft_i*, dd_i*) at once, which keeps
+// few values live.  With UNIT (both relaxation times 1, so 1/tau = 1 at every node) BGK
+// relaxation returns the equilibrium and load() is not called.  Returns ||F||.
+//
+// Everything that depends on the direction only through its weight class (rest, axis,
+// diagonal) is formed once per node:
+//   feq_i = base_k + W_k rho (c_i.u) (3 + 4.5 c_i.u),   base_k = A_k drho + B_k dB - 1.5 W_k rho u.u
+//   pert_i = (9/4)(sigma/tau) [W_k (F.c_i)^2 / |F| - C_k |F|]
+//   dd_i = rho^N full_i + [2 beta (rho_r rho_b / rho) fade / (|F| |c_i|) t_k(abar)] (F.c_i)
+template <int Q, typename M, bool UNIT = false, typename Load, typename Store>
+__device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M (&u)[3],
+                                     const M (&F)[3], const Phys<M>& P, Store&& store) {
     const M pr = M(0.5) * (M(1) + rhoN);  // rho_r / rho
     const M pb = M(0.5) * (M(1) - rhoN);  // rho_b / rho
     const M omega = pr * P.omega_r + pb * P.omega_b;
@@ -190,20 +213,62 @@ __device__ __forceinline__ M collide(M (&ft)[Q], M (&dd)[Q], M drho, M rho, M rh
     const M invFn = hg ? M(1) / Fn : M(0);
     const M kp = M(2.25) * P.sigma * omega;                         // (9/4) sigma / tau
     const M sep = M(0.5) * P.beta * (M(1) - rhoN * rhoN) * rho;      // 2 beta rho_r rho_b / rho
+    // cos(theta_i) = F.c_i / (|F| |c_i|) fades out linearly between |F| = 2e-5 and 1e-5: where
+    // F vanishes by symmetry inside a mixture its direction is rounding noise
+    const M fade = Fn >= M(2e-5) ? M(1) : (Fn > M(1e-5) ? Fn * M(1e5) - M(1) : M(0));
+    const M cosw = invFn * fade;
+    // per weight class k: 0 rest, 1 axis (|c| = 1), 2 diagonal (|c| = sqrt 2)
+    constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;  // first direction of classes 1 and 2
+    M base[3], wr[3], pf[3], kc[3], tref[3], gs[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = k == 0 ? 0 : (k == 1 ? i1 : i2);
+        const M A = M(restA<Q>(i)), B = M(restB<Q>(i)), W = M(weight<Q>(i));
+        wr[k] = W * rho;
+        base[k] = A * drho + B * dB - M(1.5) * wr[k] * uu;
+        pf[k] = kp * W * invFn;
+        kc[k] = kp * M(pertC<Q>(i)) * Fn;
+        tref[k] = P.rho_ref * (A + B * P.alpha_ref);
+        gs[k] = sep * cosw * M(inv_len<Q>(i)) * (A + B * abar);
+    }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const M A = M(restA<Q>(i)), B = M(restB<Q>(i)), W = M(weight<Q>(i));
+        const int k = norm2<Q>(i);  // 0, 1, 2 = weight class
         const M cu = M(Lat<Q>::cx[i]) * u[0] + M(Lat<Q>::cy[i]) * u[1] + M(Lat<Q>::cz[i]) * u[2];
-        const M feq = A * drho + B * dB + W * rho * (M(3) * cu + M(4.5) * cu * cu - M(1.5) * uu);
-        M f1 = ft[i] - omega * (ft[i] - feq);
         const M Fc = M(Lat<Q>::cx[i]) * F[0] + M(Lat<Q>::cy[i]) * F[1] + M(Lat<Q>::cz[i]) * F[2];
-        f1 += kp * (W * Fc * Fc * invFn - M(pertC<Q>(i)) * Fn);
-        const M full = f1 + P.rho_ref * (A + B * P.alpha_ref);
-        const M cosv = Fn > M(1e-5) ? Fc * invFn * M(inv_len<Q>(i)) : M(0);
-        dd[i] = rhoN * full + sep * cosv * (A + B * abar);
-        ft[i] = f1;
+        const M feq = base[k] + wr[k] * cu * (M(3) + M(4.5) * cu);
+        M f1;
+        if (UNIT) {
+            f1 = feq;
+        } else {
+            const M fti = load(i);
+            f1 = fti - omega * (fti - feq);
+        }
+        f1 += pf[k] * Fc * Fc - kc[k];
+        const M full = f1 + tref[k];
+        store(i, f1, rhoN * full + gs[k] * Fc);
     }
     return Fn;
+}
+
+// Neutral wetting: a solid node takes the W-weighted mean of rho^N over its fluid neighbours.
+template <int Q, typename R>
+__global__ __launch_bounds__(kTPBX) void k_wet(const uint8_t* __restrict__ flags,
+                                               R* __restrict__ rhoN, Geo g) {
+    int x, y, z;
+    long long n;
+    if (!node_xyz(g, x, y, z, n)) return;
+    if (!flags[n]) return;
+    const Nb b = wrap(g, x, y, z);
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const long long m = shifted<Q, 1>(g, b, x, y, z, i);
+        if (flags[m]) continue;
+        num += weight<Q>(i) * static_cast<double>(rhoN[m]);
+        den += weight<Q>(i);
+    }
+    rhoN[n] = static_cast<R>(den > 0.0 ? num / den : 0.0);
 }
 
 // ---------------------------------------------------------------- block reductions (FP64)

@@ -1,0 +1,203 @@
+// Split step for unit relaxation times (tau_r = tau_b = 1): two passes, populations read once.
+//
+// With 1/tau = 1 at every node, BGK relaxation returns the equilibrium (Eq. collision), so
+// the post-collision populations depend on the pulled ones only through the post-sink
+// moments: rho (via drho = sum ft_i), rho^N and j.  The first pass pulls, applies the sink
+// and writes those moments (rho^N in the arithmetic type, drho and j in the storage type's
+// width: FP64 next to FP64 populations, FP32 otherwise); the second pass reads them back,
+// takes the colour gradient from the rho^N field, and runs equilibrium, perturbation and
+// recolouring (Eqs. feq, perturb, recolor) without touching the old populations.
+//
+// Per node: 2Q reads + 2Q writes of populations, plus the moment record written and read
+// once (24 B at FP32 storage) and the neighbours' rho^N (cache hits).  Both kernels are one
+// thread per node with no synchronisation, so many waves hide memory latency.
+#include "internal.hpp"
+#include "node.hpp"
+
+namespace cge {
+
+template <typename S>
+using MomT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
+
+// Periodic addressing of one block (one x-row segment at fixed y = blockIdx.y, z =
+// blockIdx.z): the y and z parts of every neighbour index are the same for all lanes, so each
+// (slot, row, plane) base is a scalar pointer and only the x offset (3 values per lane) varies.
+struct RowOff {
+    long long yrow[3], zpl[3];  // element offsets of rows y-1, y, y+1 and planes z-1, z, z+1
+    uint32_t xo[3];             // byte offsets of x-1, x, x+1 (times the element size)
+};
+
+__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Call at kernel entry, before any lane-dependent branch.
+template <typename T>
+__device__ __forceinline__ RowOff row_offsets(const Geo& g, int x) {
+    RowOff r;
+    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // readfirstlane keeps the uniform offsets in scalar registers (they fit in 31 bits)
+        const int yo = __builtin_amdgcn_readfirstlane(wrapc(y - 1 + d, g.ny) * g.nx);
+        const int zo = __builtin_amdgcn_readfirstlane(wrapc(z - 1 + d, g.nz));
+        r.yrow[d] = yo;
+        r.zpl[d] = (long long)zo * ((long long)g.nx * g.ny);
+        r.xo[d] = (uint32_t)wrapc(x - 1 + d, g.nx) * (uint32_t)sizeof(T);
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// Pass 1: pull, sink, moments; FP64 sink bookkeeping per block.
+template <int Q, typename S, typename M, bool WALLS>
+__global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const uint8_t* __restrict__ carry,
+                                                   const void* __restrict__ phi_field,
+                                                   M* __restrict__ rhoN, MomT<S>* __restrict__ mom,
+                                                   double* __restrict__ acc_sink,
+                                                   long long* __restrict__ acc_sites, Geo g,
+                                                   Phys<M> P) {
+    int x, y, z;
+    long long n;
+    const bool valid = node_xyz(g, x, y, z, n);
+    const RowOff r = row_offsets<S>(g, x < g.nx ? x : 0);
+    double v[2] = {0.0, 0.0};
+    if (valid && !(WALLS && flags[n])) {
+        M j[3] = {M(0), M(0), M(0)}, drho = M(0), dsum = M(0);
+        if constexpr (WALLS) {
+            const Nb b = wrap(g, x, y, z);
+            M ft[Q], dd[Q];
+            pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
+            moments<Q>(ft, dd, drho, dsum, j);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {  // pull (Eq. Stream): from x - c_i
+                const long long rowz = r.yrow[1 - Lat<Q>::cy[i]] + r.zpl[1 - Lat<Q>::cz[i]];
+                const uint32_t xo = r.xo[1 - Lat<Q>::cx[i]];
+                const M a = static_cast<M>(ld_at(src + (long long)i * g.N + rowz, xo));
+                drho += a;
+                dsum += static_cast<M>(ld_at(src + (long long)(Q + i) * g.N + rowz, xo));
+                if (Lat<Q>::cx[i]) j[0] += Lat<Q>::cx[i] * a;
+                if (Lat<Q>::cy[i]) j[1] += Lat<Q>::cy[i] * a;
+                if (Lat<Q>::cz[i]) j[2] += Lat<Q>::cz[i] * a;
+            }
+        }
+        const M rho = P.rho_ref + drho;
+        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum);
+        dsum -= M(2) * s;
+        if (s != M(0)) {
+            v[0] = static_cast<double>(s);
+            v[1] = 1.0;
+        }
+        rhoN[n] = dsum / rho;
+        mom[n] = static_cast<MomT<S>>(drho);
+        mom[g.N + n] = static_cast<MomT<S>>(j[0]);
+        mom[2 * g.N + n] = static_cast<MomT<S>>(j[1]);
+        mom[3 * g.N + n] = static_cast<MomT<S>>(j[2]);
+    }
+    const bool is_max[2] = {false, false};
+    double out[2];
+    block_reduce<2>(v, is_max, threadIdx.x, blockDim.x, out);
+    if (threadIdx.x == 0) {
+        const long long bid =
+            blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        acc_sink[bid] += out[0];
+        acc_sites[bid] += static_cast<long long>(out[1]);
+    }
+}
+
+// Pass 2: gradient, equilibrium, perturbation, recolouring, store, next site mask.
+template <int Q, typename S, typename M, bool WALLS>
+__global__ __launch_bounds__(kTPBX) void k_finish(S* __restrict__ dst,
+                                                  const uint8_t* __restrict__ flags,
+                                                  uint8_t* __restrict__ carry,
+                                                  const M* __restrict__ rhoN,
+                                                  const MomT<S>* __restrict__ mom, Geo g,
+                                                  Phys<M> P, uint64_t salt) {
+    int x, y, z;
+    long long n;
+    const bool valid = node_xyz(g, x, y, z, n);
+    const RowOff r = row_offsets<M>(g, x < g.nx ? x : 0);
+    if (!valid) return;
+    if (WALLS && flags[n]) return;
+    const M drho = static_cast<M>(mom[n]);
+    const M rho = P.rho_ref + drho;
+    const M inv_rho = M(1) / rho;
+    const M u[3] = {static_cast<M>(mom[g.N + n]) * inv_rho,
+                    static_cast<M>(mom[2 * g.N + n]) * inv_rho,
+                    static_cast<M>(mom[3 * g.N + n]) * inv_rho};
+    M F[3];
+    if constexpr (WALLS) {
+        const Nb b = wrap(g, x, y, z);
+        gradient<Q>(rhoN, g, b, x, y, z, F);
+    } else {  // F = 3 sum_i W_i rho^N(x + c_i) c_i
+        F[0] = F[1] = F[2] = M(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const long long rowz = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]];
+            const M v = M(weight<Q>(i)) * ld_at(rhoN + rowz, r.xo[1 + Lat<Q>::cx[i]]);
+            if (Lat<Q>::cx[i]) F[0] += Lat<Q>::cx[i] * v;
+            if (Lat<Q>::cy[i]) F[1] += Lat<Q>::cy[i] * v;
+            if (Lat<Q>::cz[i]) F[2] += Lat<Q>::cz[i] * v;
+        }
+        F[0] *= M(3);
+        F[1] *= M(3);
+        F[2] *= M(3);
+    }
+    // stores at the node itself: the row base is uniform, x is the lane offset
+    const long long row = r.yrow[1] + r.zpl[1];
+    const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(S);
+    const M Fn = collide<Q, M, true>([](int) { return M(0); }, drho, rho, rhoN[n], u, F, P,
+                                     [&](int i, M a, M d) {
+                                         const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N +
+                                                              (uint64_t)n;
+                                         S* pa = dst + (long long)i * g.N + row;
+                                         S* pd = dst + (long long)(Q + i) * g.N + row;
+                                         st(reinterpret_cast<S*>(reinterpret_cast<char*>(pa) + xb), a, key);
+                                         st(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
+                                            key + (uint64_t)g.N);
+                                     });
+    carry[n] = Fn > P.gamma ? 1 : 0;
+}
+
+bool split_supported(const cge_ctx* c) { return c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0; }
+
+size_t split_scratch_bytes(const cge_params* p) {
+    const size_t e = p->precision == CGE_FP64 ? 8 : 4;
+    return 4 * e * (size_t)p->nx * p->ny * p->nz;
+}
+
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status split_impl(cge_ctx* c, long long nsteps) {
+    if (!split_supported(c)) return fail(c, CGE_EUNSUPPORTED, "split step needs tau = 1");
+    if (!c->mom) return fail(c, CGE_ESTATE, "moment scratch missing");
+    const Phys<M> P = phys<M>(c);
+    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+    M* rhoN = static_cast<M*>(c->rhoN);
+    MomT<S>* mom = static_cast<MomT<S>*>(c->mom);
+    const uint64_t seedmix = mix64(c->p.seed);
+    for (long long t = 0; t < nsteps; ++t) {
+        const S* src = static_cast<const S*>(c->pop[c->cur]);
+        S* dst = static_cast<S*>(c->pop[1 - c->cur]);
+        const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
+        timing_begin(c);
+        hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
+                           c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
+        if (WALLS) hipLaunchKernelGGL((k_wet<Q, M>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+        hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
+                           c->carry, rhoN, mom, c->g, P, salt);
+        timing_end(c);
+        if (cge_status s = check(c, hipGetLastError(), "split step launch")) return s;
+        c->cur = 1 - c->cur;
+        c->step += 1;
+    }
+    return CGE_OK;
+}
+
+cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_impl, c, nsteps); }
+
+}  // namespace cge

@@ -30,26 +30,6 @@ __global__ __launch_bounds__(kTPBX) void k_phase(const S* __restrict__ src,
     rhoN[n] = dsum / rho;
 }
 
-// Neutral wetting: a solid node takes the W-weighted mean of rho^N over its fluid neighbours.
-template <int Q, typename R>
-__global__ __launch_bounds__(kTPBX) void k_wet(const uint8_t* __restrict__ flags,
-                                               R* __restrict__ rhoN, Geo g) {
-    int x, y, z;
-    long long n;
-    if (!node_xyz(g, x, y, z, n)) return;
-    if (!flags[n]) return;
-    const Nb b = wrap(g, x, y, z);
-    double num = 0.0, den = 0.0;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const long long m = shifted<Q, 1>(g, b, x, y, z, i);
-        if (flags[m]) continue;
-        num += weight<Q>(i) * static_cast<double>(rhoN[m]);
-        den += weight<Q>(i);
-    }
-    rhoN[n] = static_cast<R>(den > 0.0 ? num / den : 0.0);
-}
-
 // Site mask ||F|| > gamma from the rho^N field (no collision); solid nodes get 0.
 template <int Q, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_carry(const uint8_t* __restrict__ flags,
@@ -100,13 +80,13 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         const M rN = dsum * inv_rho;
         M F[3];
         gradient<Q>(rhoN, g, b, x, y, z, F);
-        const M Fn = collide<Q>(ft, dd, drho, rho, rN, u, F, P);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N + (uint64_t)n;
-            st(dst + (long long)i * g.N + n, ft[i], key);
-            st(dst + (long long)(Q + i) * g.N + n, dd[i], key + (uint64_t)g.N);
-        }
+        const M Fn = collide<Q>([&](int i) { return ft[i]; }, drho, rho, rN, u, F, P,
+                                [&](int i, M a, M d) {
+                                    const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N +
+                                                         (uint64_t)n;
+                                    st(dst + (long long)i * g.N + n, a, key);
+                                    st(dst + (long long)(Q + i) * g.N + n, d, key + (uint64_t)g.N);
+                                });
         carry[n] = Fn > P.gamma ? 1 : 0;
     }
     const bool is_max[2] = {false, false};

@@ -18,21 +18,42 @@ CASES = {
     "d2q9_adjoint_field": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3)),
     "d3q19_grad": ("sphere3d", (14, 16, 70), dict(radius=5.0, phi=1e-3)),
     "d3q19_walls_ratio": ("sessile3d", (14, 18, 70), dict(radius=6.0, phi=1e-3)),
+    # several z-chunks and a ragged last tile in x (70 = 64 + 6) and y (10 = 4 + 4 + 2)
+    "d3q19_chunks": ("sphere3d", (40, 10, 70), dict(radius=4.5, phi=1e-3)),
+    # relaxation times other than 1 (the general collision path of the fused step)
+    "d3q19_tau": ("sphere3d", (20, 12, 70), dict(radius=4.0, phi=1e-3, tau=(1.0, 0.8))),
 }
+
+# step implementations to check per case: the two-pass step covers everything, the fused
+# single-pass step D3Q19 without solid nodes, the split step unit relaxation times
+def _kernels(wl, over):
+    ks = ["twopass"]
+    if wl == "sphere3d":
+        ks.append("fused")
+    tau = over.get("tau", (1.0, 1.0) if wl != "sessile3d" else (1.0, 0.6))
+    if tuple(tau) == (1.0, 1.0):
+        ks.append("split")
+    return ks
+
+
+KERNELS = {name: _kernels(wl, over) for name, (wl, _, over) in CASES.items()}
+PARAMS = [(name, k) for name in CASES for k in KERNELS[name]]
 
 
 def _flush(msg):
     print(msg, flush=True)
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_fp64_matches_oracle_step_by_step(name):
+@pytest.mark.parametrize("name,kernel", PARAMS)
+def test_fp64_matches_oracle_step_by_step(name, kernel):
     wl, shape, over = CASES[name]
     w = case(wl, shape, **over)
     Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
-    _flush(f"[parity fp64] {name} shape={shape}")
+    _flush(f"[parity fp64] {name} {kernel} shape={shape}")
     ora = oracle_for(w)
-    sim = gpu_for(w, "fp64")
+    sim = gpu_for(w, "fp64", kernel=kernel)
+    assert sim.kernel_name() == {"twopass": "k_collide", "fused": "k_fused",
+                                 "split": "k_finish"}[kernel]
     # initial state and site mask
     e0 = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in, w["solid"])
     assert e0 < 1e-14, e0
@@ -63,18 +84,17 @@ def test_fp64_matches_oracle_step_by_step(name):
     sim.close()
 
 
-@pytest.mark.parametrize("name", ["d2q9_grad", "d2q9_walls_field", "d3q19_grad",
-                                  "d3q19_walls_ratio"])
+@pytest.mark.parametrize("name,kernel", [pk for pk in PARAMS if pk[0] != "d2q9_phase"])
 @pytest.mark.parametrize("precision", ["fp32s"])
-def test_fp32_frozen_mask_within_1e5(name, precision):
+def test_fp32_frozen_mask_within_1e5(name, kernel, precision):
     """FP32 shifted storage against the FP64 oracle with the oracle's site sets imposed
     (a site decision within rounding of Gamma may legitimately flip in FP32)."""
     wl, shape, over = CASES[name]
     w = case(wl, shape, **over)
     Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
-    _flush(f"[parity {precision} frozen] {name}")
+    _flush(f"[parity {precision} frozen] {name} {kernel}")
     ora = oracle_for(w)
-    sim = gpu_for(w, precision)
+    sim = gpu_for(w, precision, kernel=kernel)
     import torch
     worst = 0.0
     for step in range(1, 61):
@@ -214,3 +234,44 @@ def test_edge_cases_no_sites_all_sites_and_tiny_domains():
         e = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, (1.0, 1.0))
         assert e < 1e-12, (shape, e)
         sim.close()
+
+
+@pytest.mark.parametrize("other", ["fused", "split"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16s"])
+def test_step_forms_match_twopass(precision, other):
+    """The single-pass, split and two-pass steps run the same arithmetic; their states agree
+    to rounding of the arithmetic (storage rounding included), site masks and counters
+    exactly in FP64."""
+    w = case("sphere3d", (40, 10, 70), radius=4.5, phi=1e-3)
+    _flush(f"[{other} vs twopass] {precision}")
+    sims = [gpu_for(w, precision, kernel=k, seed=7) for k in ("twopass", other)]
+    for s in sims:
+        s.step(9)
+    f = [s.populations().cpu().numpy() for s in sims]
+    e = e_pop(f[0], f[1], 19, (1.0, 1.0))
+    tol = {"fp64": 1e-13, "fp32s": 1e-6, "fp16s": 2e-2}[precision]
+    _flush(f"  e_pop({other}, twopass) = {e:.3e}")
+    assert e < tol, e
+    o = [s.observables() for s in sims]
+    if precision == "fp64":
+        for k in ("n_sites", "site_steps", "step"):
+            assert o[0][k] == o[1][k], k
+        assert bool((sims[0].carry == sims[1].carry).all())
+    for s in sims:
+        s.close()
+
+
+def test_fused_odd_and_even_step_counts_keep_the_mask():
+    """The fused step double-buffers the site mask; after any number of steps the caller's
+    carry buffer holds the mask of the current state."""
+    w = case("sphere3d", (20, 12, 70), radius=4.0, phi=1e-3)
+    _flush("[fused mask hand-back]")
+    a = gpu_for(w, "fp64", kernel="fused")
+    b = gpu_for(w, "fp64", kernel="twopass")
+    for n in (1, 2, 3):
+        a.step(n)
+        b.step(n)
+        same = bool((a.carry == b.carry).all())
+        assert same, n
+    a.close()
+    b.close()
