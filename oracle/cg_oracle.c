@@ -37,7 +37,10 @@
  *     continuous at F = 0 (it vanishes with ||F||) and is applied for F != 0.
  *   - Step 0 uses the gradient of the initial phase field as the "previous" gradient.
  *   - Site criterion is strict (>).  An alternative local rule |rho^N_pre| < Gamma
- *     (site_rule = 1) uses the current pre-sink phase field.
+ *     (site_rule = 1) uses the current pre-sink phase field.  A soft rule (site_rule = 2)
+ *     weights the sink by the logistic function of (||F_prev|| - Gamma)/kappa; it stands in
+ *     for the threshold where derivatives with respect to Gamma are taken (sites counted
+ *     where the weight exceeds 1/2).
  *   - Solid nodes carry no populations; for the gradient stencil a solid node takes the
  *     W-weighted mean of rho^N over its fluid neighbours (neutral wetting).
  *   - Blue recolouring uses F_br = -F_rb, i.e. cos(theta_br) = -cos(theta_rb).
@@ -68,7 +71,9 @@ typedef struct {
     int Q, nx, ny, nz;
     double rho_in[2], tau[2], sigma, beta;
     double phi, sbar, gamma;
-    int site_rule; /* 0: ||F_prev|| > gamma (paper); 1: |rho^N_pre| < gamma */
+    int site_rule; /* 0: ||F_prev|| > gamma (paper); 1: |rho^N_pre| < gamma;
+                      2: soft weight 1 / (1 + exp(-(||F_prev|| - gamma) / kappa)) */
+    double kappa;
 } ora_params;
 
 typedef struct {
@@ -366,8 +371,23 @@ void ora_set_counters(ora_ctx* s, long long step, long long site_steps, double s
 
 /* ------------------------------------------------------------------ one time step */
 
+/* Site weight of node n: 0 or 1 for the sharp rules; for the soft rule (a differentiable
+ * stand-in for the threshold, used to take derivatives with respect to Gamma) the logistic
+ * function of (||F_prev|| - Gamma) / kappa. */
+static double site_weight(ora_ctx* s, long long n) {
+    if (s->p.site_rule == 2) return 1.0 / (1.0 + exp(-(s->fmag[n] - s->p.gamma) / s->p.kappa));
+    if (s->p.site_rule == 0) return s->fmag[n] > s->p.gamma ? 1.0 : 0.0;
+    double rr = 0.0, rb = 0.0;
+    for (int i = 0; i < s->L.Q; ++i) {
+        rr += F(s, 0, i)[n];
+        rb += F(s, 1, i)[n];
+    }
+    return fabs((rr - rb) / (rr + rb)) < s->p.gamma ? 1.0 : 0.0;
+}
+
 static int site_of(ora_ctx* s, long long n) {
     if (s->p.site_rule == 0) return s->fmag[n] > s->p.gamma;
+    if (s->p.site_rule == 2) return site_weight(s, n) > 0.5;
     double rr = 0.0, rb = 0.0;
     for (int i = 0; i < s->L.Q; ++i) {
         rr += F(s, 0, i)[n];
@@ -386,15 +406,15 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
             if (mask_out) mask_out[n] = 0;
             continue;
         }
-        int m = mask_in ? (mask_in[n] != 0) : site_of(s, n);
-        if (mask_out) mask_out[n] = (unsigned char)m;
-        if (!m) continue;
+        double m = mask_in ? (mask_in[n] != 0 ? 1.0 : 0.0) : site_weight(s, n);
+        if (mask_out) mask_out[n] = (unsigned char)(m > 0.5);
+        if (m == 0.0) continue;
         double phi = s->phi_field ? s->phi_field[n] : s->p.phi;
-        double sink = phi / s->p.sbar; /* phi = Sbar * varphi * dx, removed mass varphi*dt */
+        double sink = m * (phi / s->p.sbar); /* phi = Sbar * varphi * dx, removed mass varphi*dt */
         F(s, 0, 0)[n] -= sink;
         F(s, 1, 0)[n] += sink;
         s->sink_total += sink;
-        s->site_steps += 1;
+        if (m > 0.5) s->site_steps += 1;
     }
 
     /* step 4: colour-blind moments and phase field, for all nodes before any gradient */

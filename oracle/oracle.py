@@ -21,7 +21,7 @@ class OraParams(C.Structure):
     _fields_ = [("Q", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("rho_in", C.c_double * 2), ("tau", C.c_double * 2), ("sigma", C.c_double),
                 ("beta", C.c_double), ("phi", C.c_double), ("sbar", C.c_double),
-                ("gamma", C.c_double), ("site_rule", C.c_int)]
+                ("gamma", C.c_double), ("site_rule", C.c_int), ("kappa", C.c_double)]
 
 
 class OraObs(C.Structure):
@@ -90,7 +90,7 @@ def tables(Q):
 
 class Oracle:
     """One oracle simulation.  `params` keys: Q, shape (nz, ny, nx), rho_in, tau, sigma,
-    beta, phi, sbar, gamma, site_rule ('grad' or 'phase')."""
+    beta, phi, sbar, gamma, site_rule ('grad', 'phase' or 'soft'), kappa (soft rule width)."""
 
     def __init__(self, params, solid=None, phi_field=None):
         Q = int(params["Q"])
@@ -104,7 +104,8 @@ class Oracle:
         p.phi = params.get("phi", 0.0)
         p.sbar = params.get("sbar", 3.0)
         p.gamma = params["gamma"]
-        p.site_rule = {"grad": 0, "phase": 1}[params.get("site_rule", "grad")]
+        p.site_rule = {"grad": 0, "phase": 1, "soft": 2}[params.get("site_rule", "grad")]
+        p.kappa = params.get("kappa", 0.01)
         self.Q, self.shape, self.N = Q, (nz, ny, nx), nx * ny * nz
         self.D = 2 if Q == 9 else 3
         self._solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)

@@ -1,0 +1,99 @@
+"""Pins of the FP64 CPU adjoint reference (oracle/adjoint.py, autograd through a plain
+PyTorch CPU step): its forward equals the C oracle's, its gradients equal central finite
+differences, and the red-mass sensitivity equals the closed form -m(x,t)/Sbar."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as A
+from oracle.oracle import tables
+from tests.helpers import case, oracle_for
+
+DT = torch.float64
+
+
+@pytest.mark.parametrize("Q", [9, 19])
+def test_tables_agree_with_the_c_oracle(Q):
+    L = A.lattice(Q)
+    t = tables(Q)
+    assert np.array_equal(L["ct"].numpy().astype(int), t["c"])
+    for k in ("W", "A", "B", "C"):
+        assert np.allclose(L[k].numpy(), t[k], rtol=0, atol=1e-16), k
+
+
+@pytest.mark.parametrize("wl,shape,over", [
+    ("drop2d", (1, 20, 26), dict(radius=6.0, phi=1e-3, site_rule="grad", gamma=0.305)),
+    ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=1e-3)),
+    ("drop2d", (1, 20, 26), dict(radius=6.0, phi=1e-3, site_rule="soft", gamma=0.305,
+                                 kappa=0.01)),
+    ("drop2d", (1, 20, 26), dict(radius=6.0, phi=1e-3, tau=(1.0, 0.7), beta=0.5,
+                                 site_rule="grad", gamma=0.305)),
+])
+def test_forward_equals_the_c_oracle(wl, shape, over):
+    w = case(wl, shape, **over)
+    p = w["params"]
+    ora = oracle_for(w)
+    ora.step(8)
+    f = A.run(p, w["rho_r"], w["rho_b"], torch.full(shape, p["phi"], dtype=DT), 8)
+    assert np.abs(f.detach().numpy() - ora.populations()).max() < 1e-14
+
+
+def _instance(site_rule="grad"):
+    w = case("adjoint2d", (1, 16, 18), radius=5.0, phi=3e-3)
+    p = dict(w["params"], site_rule=site_rule, kappa=0.02)
+    rng = np.random.default_rng(11)
+    target = np.tanh((5.5 - np.hypot(*np.meshgrid(np.arange(18) - 9.0, np.arange(16) - 8.0))) / 2.0)
+    return w, p, torch.as_tensor(w["phi_field"], dtype=DT), torch.as_tensor(target[None]), rng
+
+
+def test_gradient_wrt_flux_matches_central_differences():
+    """Hard sites, held fixed at the base run's masks for the perturbed runs."""
+    w, p, phi, target, rng = _instance()
+    n = 25
+    _, masks = A.run(p, w["rho_r"], w["rho_b"], phi, n, return_masks=True)
+    g = A.gradients(p, w["rho_r"], w["rho_b"], phi, n, target, masks=masks)["grad_phi"]
+    assert float(g.abs().max()) > 0
+    # central differences carry an O(eps^2) truncation error (relative ~1e-4 .. 1e-3 at
+    # eps = 1e-3 on this instance); a wrong gradient would leave a floor that does not shrink,
+    # so the error must also fall ~100x when eps falls 10x
+    for trial in range(3):
+        v = torch.as_tensor(rng.standard_normal(phi.shape), dtype=DT) * phi
+        ad = float((g * v).sum())
+        err = []
+        for eps in (1e-3, 1e-4):
+            lp = A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], phi + eps * v, n, masks=masks),
+                             target)
+            lm = A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], phi - eps * v, n, masks=masks),
+                             target)
+            err.append(abs(float(lp - lm) / (2 * eps) - ad) / abs(ad))
+        assert err[0] < 2e-3 and err[1] < 2e-5 and err[1] < err[0] / 30, (trial, err)
+
+
+def test_gradient_wrt_gamma_matches_central_differences_soft_sites():
+    w, p, phi, target, _ = _instance("soft")
+    n = 25
+    res = A.gradients(p, w["rho_r"], w["rho_b"], phi, n, target)
+    assert res["grad_gamma"] != 0.0
+    err = []
+    for rel in (1e-3, 1e-4):
+        eps = rel * p["gamma"]
+        lp = A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], phi, n,
+                               gamma=torch.tensor(p["gamma"] + eps, dtype=DT)), target)
+        lm = A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], phi, n,
+                               gamma=torch.tensor(p["gamma"] - eps, dtype=DT)), target)
+        err.append(abs(float(lp - lm) / (2 * eps) - res["grad_gamma"]) / abs(res["grad_gamma"]))
+    assert err[0] < 2e-3 and err[1] < 2e-5 and err[1] < err[0] / 30, err
+
+
+def test_red_mass_sensitivity_is_minus_mask_over_sbar():
+    """Every operator but the sink conserves red mass, so dM_r(T)/dphi(x, t) = -m(x, t)/Sbar
+    exactly (hard sites)."""
+    w, p, phi, _, _ = _instance()
+    n = 12
+    _, masks = A.run(p, w["rho_r"], w["rho_b"], phi, n, return_masks=True)
+    ph = phi.expand((n,) + phi.shape).clone().requires_grad_(True)
+    f = A.run(p, w["rho_r"], w["rho_b"], ph, n, masks=masks)
+    f[0].sum().backward()
+    expect = -masks / p["sbar"]
+    assert masks.sum() > 0
+    assert float((ph.grad - expect).abs().max()) < 1e-13
