@@ -52,8 +52,11 @@ typedef enum { CGE_FP64 = 0, CGE_FP32S = 1, CGE_FP16S = 2 } cge_precision;
 
 /* Evaporation-site rule.  GRAD_GT: ||F_{n-1}(x)|| > gamma with the colour gradient of the
  * previous step (Sec. II.B, site criterion and the remark after the method summary).
- * PHASE_LT: |rho^N(x)| < gamma from the current pre-sink phase field (a local variant). */
-typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1 } cge_site_rule;
+ * PHASE_LT: |rho^N(x)| < gamma from the current pre-sink phase field (a local variant).
+ * SOFT: the sink is weighted by 1 / (1 + exp(-(||F_{n-1}(x)|| - gamma) / kappa)), a smooth
+ * stand-in for GRAD_GT that makes the step differentiable in gamma (two-pass step only);
+ * nodes with weight > 1/2 count as sites in the observables. */
+typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } cge_site_rule;
 
 /* Step implementation.
  *   TWOPASS: any lattice, geometry and relaxation times; writes the post-sink phase field to
@@ -83,6 +86,7 @@ typedef struct {
     double phi;             /* uniform mass flux when no flux field is bound (Sec. II.B)  */
     double sbar;            /* layer factor Sbar >= 1 (Eq. relation)                      */
     double gamma;           /* site threshold Gamma (site criterion)                      */
+    double kappa;           /* width of the soft site rule, > 0 (CGE_SITE_SOFT only)      */
     int site_rule;          /* cge_site_rule                                              */
     int kernel;             /* cge_kernel                                                 */
     unsigned long long seed; /* stochastic-rounding stream (FP16S only)                   */
@@ -124,8 +128,9 @@ size_t cge_population_bytes(const cge_params* params);
  *                  deviation f_i^r + f_i^b - rho_in[1] t_i(alpha_b) and the colour
  *                  difference f_i^r - f_i^b of the post-collision values, stored so that
  *                  streaming is a pull.  Use cge_set/get_populations to convert.
- *   carry        : nx*ny*nz bytes; 1 where the next step evaporates (site mask).  It may be
- *                  overwritten between steps to impose a site set for the next step.
+ *   carry        : the site data carried to the next step: nx*ny*nz bytes, 1 where the next
+ *                  step evaporates (site mask; it may be overwritten between steps to impose
+ *                  a site set), or for CGE_SITE_SOFT nx*ny*nz doubles holding ||F_{n-1}||.
  *   flags        : nullable, nx*ny*nz bytes, nonzero = solid node (halfway bounce-back,
  *                  neutral wetting).  Not changed by the library.
  *   phi_field    : nullable, nx*ny*nz per-node fluxes phi(x) (double for FP64, float for
@@ -148,15 +153,48 @@ cge_status cge_set_populations(cge_ctx* ctx, const double* f);
 cge_status cge_get_populations(cge_ctx* ctx, double* f);
 
 /* Raw snapshot of the state in the library's own encoding (bitwise exact round trip): the
- * current population buffer followed by the site mask, cge_state_bytes() bytes of device
- * memory at dst / src.  Counters are not included (see cge_set_counters).  Used for
- * checkpoint / resume and by the adjoint's recomputation segments. */
+ * current population buffer, then the carried site data from the next 256-byte boundary;
+ * cge_state_bytes() bytes of device memory at dst / src (256-byte aligned).  Counters are not
+ * included (see cge_set_counters).  Used for checkpoint / resume and by the adjoint's
+ * recomputation segments. */
 size_t cge_state_bytes(const cge_params* params);
 cge_status cge_save_state(cge_ctx* ctx, void* dst);
 cge_status cge_load_state(cge_ctx* ctx, const void* src);
 
+/* Adjoint (reverse mode) of nsteps steps, for domains without solid nodes and the site rules
+ * GRAD_GT (sites held at those of the forward run) and SOFT.  The loss is given through its
+ * derivative with respect to the final phase field rho^N_T (e.g. 2 (rho^N_T - target) for a
+ * squared mismatch), and the gradients with respect to the flux field phi(x) and the site
+ * threshold Gamma are returned.
+ *   cge_forward_ckpt : from the current state, advance nsteps and save the state (as
+ *                      cge_save_state) at steps 0, K, 2K, ... into ckpt[0..ceil(nsteps/K)-1],
+ *                      each of cge_state_bytes().
+ *   cge_backward     : call after cge_forward_ckpt with the same nsteps and K, with the state
+ *                      after nsteps current.  seg: K * round_up(cge_state_bytes(), 256) bytes
+ *                      for the recomputed states of one segment; work: cge_adjoint_bytes();
+ *                      dL_drhoN: [N] doubles; grad_phi (out): [N] doubles, dL/dphi(x) summed
+ *                      over the steps (phi held over time); grad_phi_t (out, nullable):
+ *                      [nsteps][N] doubles, dL/dphi(x, t) per step; grad_gamma (host, nullable):
+ *                      dL/dGamma (0 for GRAD_GT).  All buffers except grad_gamma are device
+ *                      memory.  Forward states are recomputed from the checkpoints; the step
+ *                      counter and sink bookkeeping are restored, the populations are not
+ *                      (reload a state with cge_load_state).
+ * Errors: CGE_EINVAL (missing buffers, nsteps or K < 1), CGE_EUNSUPPORTED (solid nodes,
+ * PHASE_LT rule), CGE_EDEVICE. */
+size_t cge_adjoint_bytes(const cge_params* params);
+cge_status cge_forward_ckpt(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt);
+cge_status cge_backward(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt, void* seg,
+                        void* work, const double* dL_drhoN, double* grad_phi, double* grad_phi_t,
+                        double* grad_gamma);
+
 /* Recompute the site mask from the current state (gradient of its phase field). */
 cge_status cge_reset_sites(cge_ctx* ctx);
+
+/* Change the site threshold Gamma (and, for the SOFT rule, the width kappa > 0; pass
+ * kappa <= 0 to keep it) of a live context; later steps use the new values.  Under GRAD_GT the
+ * carried mask was taken with the old Gamma: call cge_reset_sites or load a state to retake
+ * it.  CGE_EINVAL for a non-finite value. */
+cge_status cge_set_site_threshold(cge_ctx* ctx, double gamma, double kappa);
 
 /* Restore the step counter and the FP64 sink bookkeeping (checkpoint resume). */
 cge_status cge_set_counters(cge_ctx* ctx, long long step, long long site_steps,

@@ -157,7 +157,7 @@ def run(params, rho_r, rho_b, phi, nsteps, gamma=None, masks=None, return_masks=
         elif masks is not None:
             w = torch.as_tensor(masks[n], dtype=DT)
         else:
-            w = (fprev > float(gamma)).to(DT).detach()
+            w = (fprev > float(gamma.detach())).to(DT)
         used.append(w.detach())
         f, fprev = step(L, params, f, fprev, ph, w)
     return (f, torch.stack(used)) if return_masks else f

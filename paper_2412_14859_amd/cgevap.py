@@ -15,14 +15,14 @@ LIB_PATH = os.path.join(HERE, "libcgevap.so")
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32s": 1, "fp16s": 2}
 KERNELS = {"auto": 0, "twopass": 1, "fused": 2, "split": 3}
-SITE_RULES = {"grad": 0, "phase": 1}
+SITE_RULES = {"grad": 0, "phase": 1, "soft": 2}
 ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 
 # every symbol the header declares
 EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
            "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
-           "cge_load_state", "cge_reset_sites", "cge_set_counters",
-           "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
+           "cge_load_state", "cge_adjoint_bytes", "cge_forward_ckpt", "cge_backward",
+           "cge_reset_sites", "cge_set_site_threshold", "cge_set_counters", "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
 
@@ -31,7 +31,8 @@ class CgeParams(C.Structure):
     _fields_ = [("lattice", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("precision", C.c_int), ("rho_in", C.c_double * 2), ("tau", C.c_double * 2),
                 ("sigma", C.c_double), ("beta", C.c_double), ("phi", C.c_double),
-                ("sbar", C.c_double), ("gamma", C.c_double), ("site_rule", C.c_int),
+                ("sbar", C.c_double), ("gamma", C.c_double), ("kappa", C.c_double),
+                ("site_rule", C.c_int),
                 ("kernel", C.c_int), ("seed", C.c_ulonglong)]
 
 
@@ -76,7 +77,12 @@ def lib():
         L.cge_state_bytes.restype = C.c_size_t
         L.cge_save_state.argtypes = [vp, vp]
         L.cge_load_state.argtypes = [vp, vp]
+        L.cge_adjoint_bytes.argtypes = [P(CgeParams)]
+        L.cge_adjoint_bytes.restype = C.c_size_t
+        L.cge_forward_ckpt.argtypes = [vp, C.c_longlong, C.c_int, P(vp)]
+        L.cge_backward.argtypes = [vp, C.c_longlong, C.c_int, P(vp), vp, vp, vp, vp, vp, dp]
         L.cge_reset_sites.argtypes = [vp]
+        L.cge_set_site_threshold.argtypes = [vp, C.c_double, C.c_double]
         L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
         L.cge_step.argtypes = [vp, C.c_longlong]
         L.cge_observables.argtypes = [vp, P(CgeObs)]
@@ -111,6 +117,7 @@ def make_params(params, precision="fp64", kernel="auto", seed=0):
     p.phi = params.get("phi", 0.0)
     p.sbar = params.get("sbar", 3.0)
     p.gamma = params["gamma"]
+    p.kappa = params.get("kappa", 0.01)
     p.site_rule = SITE_RULES[params.get("site_rule", "grad")]
     p.kernel = KERNELS[kernel]
     p.seed = seed
@@ -165,7 +172,9 @@ class Simulation:
             self._ctx = ctx
             dev = self.device
             self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(2)]
-            self.carry = torch.zeros(self.shape, dtype=torch.uint8, device=dev)
+            soft = params.get("site_rule") == "soft"
+            self.carry = torch.zeros(self.shape, dtype=torch.float64 if soft else torch.uint8,
+                                     device=dev)
             self.flags = None if solid is None else torch.as_tensor(
                 np.ascontiguousarray(solid, np.uint8), device=dev)
             pdt = torch.float64 if precision == "fp64" else torch.float32
@@ -240,6 +249,47 @@ class Simulation:
     def reset_sites(self):
         self._check(lib().cge_reset_sites(self._ctx))
 
+    def set_site_threshold(self, gamma, kappa=0.0):
+        self._check(lib().cge_set_site_threshold(self._ctx, float(gamma), float(kappa)))
+        self.params["gamma"] = float(gamma)
+        if kappa > 0:
+            self.params["kappa"] = float(kappa)
+
+    # ----------------------------------------------------------------------------- adjoint
+    def _state_bytes(self):
+        return lib().cge_state_bytes(C.byref(make_params(self.params, self.precision)))
+
+    def forward_ckpt(self, nsteps, K):
+        """Advance nsteps, keeping the state at steps 0, K, 2K, ... (device tensors)."""
+        nck = (int(nsteps) + K - 1) // K
+        ck = [self.torch.empty(self._state_bytes(), dtype=self.torch.uint8, device=self.device)
+              for _ in range(nck)]
+        arr = (C.c_void_p * nck)(*[t.data_ptr() for t in ck])
+        self._check(lib().cge_forward_ckpt(self._ctx, int(nsteps), int(K), arr))
+        return ck
+
+    def backward(self, ckpt, nsteps, K, dL_drhoN, per_step=False):
+        """Gradients of a loss given by dL/drho^N of the state after nsteps (the current one,
+        reached by forward_ckpt).  Returns grad_phi [shape] (phi held over time), grad_phi_t
+        [nsteps, shape] when per_step, and grad_gamma.  The populations are left at a
+        recomputed state: load a saved one before stepping on."""
+        t = self.torch
+        nck = len(ckpt)
+        assert nck == (int(nsteps) + K - 1) // K
+        sb = (self._state_bytes() + 255) // 256 * 256
+        seg = t.empty(K * sb, dtype=t.uint8, device=self.device)
+        work = t.empty(lib().cge_adjoint_bytes(C.byref(make_params(self.params, self.precision))),
+                       dtype=t.uint8, device=self.device)
+        g = self._dev64(dL_drhoN).reshape(self.shape).contiguous()
+        gphi = t.empty(self.shape, dtype=t.float64, device=self.device)
+        gpt = (t.empty((int(nsteps),) + self.shape, dtype=t.float64, device=self.device)
+               if per_step else None)
+        gg = C.c_double()
+        arr = (C.c_void_p * nck)(*[c.data_ptr() for c in ckpt])
+        self._check(lib().cge_backward(self._ctx, int(nsteps), int(K), arr, _ptr(seg), _ptr(work),
+                                       _ptr(g), _ptr(gphi), _ptr(gpt), C.byref(gg)))
+        return {"grad_phi": gphi, "grad_phi_t": gpt, "grad_gamma": gg.value}
+
     def set_counters(self, step=0, site_steps=0, sink_total=0.0):
         self._check(lib().cge_set_counters(self._ctx, step, site_steps, sink_total))
 
@@ -267,3 +317,49 @@ def copy_probe(dst, src, nbytes, stream):
     st = lib().cge_copy_probe(_ptr(dst), _ptr(src), int(nbytes), C.c_void_p(stream.cuda_stream))
     if st != OK:
         raise CgeError(st, "copy probe failed")
+
+
+def _autograd_function():
+    import torch
+
+    class EvaporationRun(torch.autograd.Function):
+        """rho^N after nsteps from a fixed start state, differentiable in the flux field phi(x)
+        and the site threshold Gamma (hard sites held at the forward run's, or soft sites).
+        The forward keeps a checkpoint every K steps; the backward recomputes each segment
+        and runs the library's reverse steps."""
+
+        @staticmethod
+        def forward(ctx, phi_field, gamma, sim, start, nsteps, K):
+            if sim.phi_field is None:
+                raise ValueError("the simulation needs a flux field (phi_field=...)")
+            sim.phi_field.copy_(phi_field.detach().reshape(sim.shape).to(sim.phi_field.dtype))
+            sim.set_site_threshold(float(gamma))
+            sim.load_state(start)
+            sim.set_counters()
+            ckpt = sim.forward_ckpt(nsteps, K)
+            ctx.sim, ctx.ckpt, ctx.nsteps, ctx.K = sim, ckpt, nsteps, K
+            ctx.phi_dtype, ctx.gamma_like = phi_field.dtype, gamma
+            return sim.fields()["rhoN"]
+
+        @staticmethod
+        def backward(ctx, grad_rhoN):
+            sim = ctx.sim
+            r = sim.backward(ctx.ckpt, ctx.nsteps, ctx.K, grad_rhoN.contiguous())
+            gphi = r["grad_phi"].to(ctx.phi_dtype)
+            gg = torch.as_tensor(r["grad_gamma"], dtype=ctx.gamma_like.dtype,
+                                 device=ctx.gamma_like.device)
+            return gphi, gg, None, None, None, None
+
+    return EvaporationRun
+
+
+_EVAP_FN = None
+
+
+def evaporate(sim, phi_field, gamma, nsteps, K, start):
+    """Differentiable run: rho^N(x, nsteps) from the saved state `start` (Simulation.save_state)
+    under the flux field phi_field and threshold gamma (tensors; gradients flow to both)."""
+    global _EVAP_FN
+    if _EVAP_FN is None:
+        _EVAP_FN = _autograd_function()
+    return _EVAP_FN.apply(phi_field, gamma, sim, start, int(nsteps), int(K))

@@ -1,0 +1,426 @@
+// Adjoint of the step (reverse mode), for periodic domains and the site rules GRAD_GT (sites
+// held at those of the forward run) and SOFT.
+//
+// Notation: the state of step n is the pre-sink encoded populations (ft_i, dd_i) of every node
+// plus the carried site data.  The adjoint of a state is lambda = dL/d(ft, dd).  Because the
+// colour differences enter the step only through their sum (the phase field) and the phase
+// field's dependence on rho adds the same term to every colour-blind direction, lambda of a
+// node is kept as Q values mu'_i plus two scalars (a, b):
+//     dL/dft_i = mu'_i + a,    dL/ddd_i = b    (all i).
+//
+// One reverse step n (state S_n, adjoint of S_{n+1} given):
+//   k_phase       post-sink rho^N of S_n (the forward kernel);
+//   k_adj_local   per node: gather the adjoint of the post-collision values from x + c_i
+//                 (reverse of the pull), recompute the forward intermediates, and apply the
+//                 transposed Jacobian of collision, perturbation and recolouring (Eqs. collision,
+//                 feq, perturb, recolor); writes mu'_i, the local dL/drho^N, rho, dL/dF;
+//   k_adj_gather  per node: dL/drho^N += sum_i 3 W_i c_i . dL/dF(x - c_i) (the transposed
+//                 gradient stencil), giving (a, b); the sink s = m phi / Sbar enters as
+//                 dd_0 -= 2 s, so dL/ds = -2 b, hence dL/dphi(x, n) = -2 b m / Sbar; for the
+//                 soft rule also dL/dm, which flows into dL/d||F_{n-1}|| and dL/dGamma.
+// The forward states of a segment of K steps are recomputed from the segment's checkpoint.
+#include <vector>
+
+#include "internal.hpp"
+#include "node.hpp"
+
+namespace cge {
+
+// adjoint workspace (doubles): mu[2][Q][N], ab[2][2][N], aF[2][N], loc[2][N], lamF[3][N],
+// then one gamma partial per block of the node grid
+struct AdjWork {
+    double *mu[2], *ab[2], *aF[2], *loc, *lamF, *gpart;
+};
+
+// Index 1 of mu, ab, aF is the input of a reverse step (adjoint of the later state) and
+// index 0 its result; the two halves of the buffer swap roles with the parity of the step.
+static AdjWork adj_work(const cge_ctx* c, void* base, int parity) {
+    const long long N = c->g.N, Q = c->Q;
+    double* p = static_cast<double*>(base);
+    AdjWork w;
+    w.mu[parity] = p;
+    w.mu[1 - parity] = p + Q * N;
+    p += 2 * Q * N;
+    w.ab[parity] = p;
+    w.ab[1 - parity] = p + 2 * N;
+    p += 4 * N;
+    w.aF[parity] = p;
+    w.aF[1 - parity] = p + N;
+    p += 2 * N;
+    w.loc = p;
+    p += 2 * N;
+    w.lamF = p;
+    p += 3 * N;
+    w.gpart = p;
+    return w;
+}
+
+size_t adjoint_bytes(const cge_params* pr) {
+    const long long N = (long long)pr->nx * pr->ny * pr->nz;
+    const long long Q = pr->lattice;
+    const Geo g{pr->nx, pr->ny, pr->nz, N};
+    const dim3 gr = node_grid(g);
+    const long long nblk = (long long)gr.x * gr.y * gr.z;
+    return (size_t)(2 * Q * N + 4 * N + 2 * N + 2 * N + 3 * N + nblk) * sizeof(double);
+}
+
+// Seed: lambda of S_T from dL/drho^N_T, rho^N = sum dd / (rho_ref + sum ft) (pre-sink).
+template <int Q, typename S, typename M>
+__global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
+                                                    const double* __restrict__ g_rhoN,
+                                                    double* __restrict__ mu, double* __restrict__ ab,
+                                                    double* __restrict__ aF, Geo g, Phys<M> P) {
+    int x, y, z;
+    long long n;
+    if (!node_xyz(g, x, y, z, n)) return;
+    const Nb b = wrap(g, x, y, z);
+    M ft[Q], dd[Q], j[3], drho, dsum;
+    pull<Q, false>(src, nullptr, g, b, x, y, z, n, ft, dd);
+    moments<Q>(ft, dd, drho, dsum, j);
+    const double rho = static_cast<double>(P.rho_ref + drho);
+    const double rN = static_cast<double>(dsum) / rho;
+    const double gr = g_rhoN[n];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) mu[(long long)i * g.N + n] = 0.0;
+    ab[n] = -gr * rN / rho;
+    ab[g.N + n] = gr / rho;
+    aF[n] = 0.0;
+}
+
+// Local transposed Jacobian at one node (see the file comment).  All adjoint arithmetic is
+// FP64.
+template <int Q, typename S, typename M>
+__global__ __launch_bounds__(kTPBX) void k_adj_local(
+    const S* __restrict__ src, const void* __restrict__ carry, const void* __restrict__ phi_field,
+    const M* __restrict__ rhoNf, const double* __restrict__ mu1, const double* __restrict__ ab1,
+    const double* __restrict__ aF1, double* __restrict__ mu0, double* __restrict__ loc,
+    double* __restrict__ lamF, Geo g, Phys<double> P) {
+    int x, y, z;
+    long long n;
+    if (!node_xyz(g, x, y, z, n)) return;
+    const Nb nb = wrap(g, x, y, z);
+    // forward recomputation
+    M ftm[Q], ddm[Q], jm[3], drhom, dsumm;
+    pull<Q, false>(src, nullptr, g, nb, x, y, z, n, ftm, ddm);
+    moments<Q>(ftm, ddm, drhom, dsumm, jm);
+    const double drho = static_cast<double>(drhom);
+    const double rho = P.rho_ref + drho;
+    const double rN = static_cast<double>(rhoNf[n]);
+    const double u[3] = {static_cast<double>(jm[0]) / rho, static_cast<double>(jm[1]) / rho,
+                         static_cast<double>(jm[2]) / rho};
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double F[3];
+    gradient<Q>(rhoNf, g, nb, x, y, z, F);
+    const double pr = 0.5 * (1.0 + rN), pb = 0.5 * (1.0 - rN);
+    const double om = pr * P.omega_r + pb * P.omega_b;
+    const double abar = pr * P.alpha_r + pb * P.alpha_b;
+    const double F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    const bool hg = F2 > 0.0;
+    const double Fn = hg ? sqrt(F2) : 0.0;
+    const double iF = hg ? 1.0 / Fn : 0.0;
+    const double fade = Fn >= 2e-5 ? 1.0 : (Fn > 1e-5 ? Fn * 1e5 - 1.0 : 0.0);
+    const double dfade = (Fn > 1e-5 && Fn < 2e-5) ? 1e5 : 0.0;
+    const double kp = 2.25 * P.sigma * om;
+    const double sep = 0.5 * P.beta * (1.0 - rN * rN) * rho;
+
+    double xi[Q];  // dL/df''_i
+    double dsep = 0.0, dab = 0.0, dkp = 0.0, dom = 0.0, drho_p = 0.0, drN = 0.0;
+    double du[3] = {0.0, 0.0, 0.0}, dF[3] = {0.0, 0.0, 0.0}, sF = 0.0;  // dF += sF * F
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
+        const double A = restA<Q>(i), B = restB<Q>(i), W = weight<Q>(i);
+        const double cu = cx * u[0] + cy * u[1] + cz * u[2];
+        const double Fc = cx * F[0] + cy * F[1] + cz * F[2];
+        const double t = A + B * abar;
+        const double feq = rho * (t + W * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        const double f = static_cast<double>(ftm[i]) + P.rho_ref * (A + B * P.alpha_ref);
+        const double f1 = f - om * (f - feq);
+        const double Pq = W * Fc * Fc * iF - pertC<Q>(i) * Fn;
+        const double f2 = f1 + kp * Pq;
+        const double il = inv_len<Q>(i);
+        const double cosf = Fc * iF * fade * il;
+        // adjoint of this direction's outputs, gathered from x + c_i
+        const long long xn = shifted<Q, 1>(g, nb, x, y, z, i);
+        const double mus = mu1[(long long)i * g.N + xn] + ab1[xn];
+        const double etas = ab1[g.N + xn];
+        // dd* = rN f2 + sep cosf t ; ft* = f2 - tref
+        const double x2 = mus + rN * etas;
+        xi[i] = x2;
+        drN += f2 * etas;
+        dsep += etas * cosf * t;
+        dab += etas * sep * cosf * B;
+        // d(Fc fade / |F|)/dF = fade (c/|F| - Fc F/|F|^3) + dfade (Fc/|F|) F/|F|
+        const double q = etas * sep * t * il;
+        dF[0] += q * fade * iF * cx;
+        dF[1] += q * fade * iF * cy;
+        dF[2] += q * fade * iF * cz;
+        sF += q * Fc * (dfade * iF * iF - fade * iF * iF * iF);
+        // f2 = f1 + kp Pq, Pq = W Fc^2/|F| - C |F|
+        dkp += x2 * Pq;
+        const double pv = x2 * kp * 2.0 * W * Fc * iF;
+        dF[0] += pv * cx;
+        dF[1] += pv * cy;
+        dF[2] += pv * cz;
+        sF += x2 * kp * (-W * Fc * Fc * iF * iF * iF - pertC<Q>(i) * iF);
+        // f1 = f - om (f - feq)
+        dom += x2 * (feq - f);
+        const double dfeq = om * x2;
+        drho_p += dfeq * feq / rho;
+        dab += dfeq * rho * B;
+        const double g3 = dfeq * rho * W * (3.0 + 9.0 * cu);
+        du[0] += g3 * cx - dfeq * rho * W * 3.0 * u[0];
+        du[1] += g3 * cy - dfeq * rho * W * 3.0 * u[1];
+        du[2] += g3 * cz - dfeq * rho * W * 3.0 * u[2];
+    }
+    dom += 2.25 * P.sigma * dkp;
+    // sep = beta (1 - rN^2) rho / 2
+    drN += dsep * (-P.beta * rN * rho);
+    drho_p += dsep * 0.5 * P.beta * (1.0 - rN * rN);
+    // om and abar depend on rN through pr = (1 + rN)/2
+    drN += 0.5 * (P.omega_r - P.omega_b) * dom + 0.5 * (P.alpha_r - P.alpha_b) * dab;
+    // u = j / rho
+    const double dj[3] = {du[0] / rho, du[1] / rho, du[2] / rho};
+    drho_p -= (du[0] * u[0] + du[1] * u[1] + du[2] * u[2]) / rho;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        mu0[(long long)i * g.N + n] = (1.0 - om) * xi[i] + drho_p + Lat<Q>::cx[i] * dj[0] +
+                                      Lat<Q>::cy[i] * dj[1] + Lat<Q>::cz[i] * dj[2];
+    loc[n] = drN;
+    loc[g.N + n] = rho;
+    // the carried ||F_n|| feeds the next step's soft site weight
+    const double aFn = aF1 ? aF1[n] * iF : 0.0;
+    lamF[n] = dF[0] + (sF + aFn) * F[0];
+    lamF[g.N + n] = dF[1] + (sF + aFn) * F[1];
+    lamF[2 * g.N + n] = dF[2] + (sF + aFn) * F[2];
+}
+
+// Transposed gradient stencil, assembly of (a, b), and the sink adjoint.
+template <int Q, typename S, typename M>
+__global__ __launch_bounds__(kTPBX) void k_adj_gather(
+    const void* __restrict__ carry, const void* __restrict__ phi_field,
+    const M* __restrict__ rhoNf, const double* __restrict__ loc, const double* __restrict__ lamF,
+    double* __restrict__ ab0, double* __restrict__ aF0, double* __restrict__ grad_phi,
+    double* __restrict__ grad_phi_t, double* __restrict__ gpart, Geo g, Phys<double> P) {
+    int x, y, z;
+    long long n;
+    const bool valid = node_xyz(g, x, y, z, n);
+    double gg = 0.0;
+    if (valid) {
+        const Nb nb = wrap(g, x, y, z);
+        double G = loc[n];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {  // F(x - c_i) contains 3 W_i c_i rho^N(x)
+            const long long m = shifted<Q, -1>(g, nb, x, y, z, i);
+            G += 3.0 * weight<Q>(i) *
+                 (Lat<Q>::cx[i] * lamF[m] + Lat<Q>::cy[i] * lamF[g.N + m] +
+                  Lat<Q>::cz[i] * lamF[2 * g.N + m]);
+        }
+        const double rho = loc[g.N + n];
+        const double rN = static_cast<double>(rhoNf[n]);
+        const double b = G / rho;
+        ab0[n] = -G * rN / rho;
+        ab0[g.N + n] = b;
+        const double dLds = -2.0 * b;
+        const double w = site_weight<double>(P, carry, n, 1.0, 0.0);
+        const double phi = node_phi<S, double>(P, phi_field, n);
+        const double gphi = dLds * w * P.inv_sbar;
+        grad_phi[n] += gphi;
+        if (grad_phi_t) grad_phi_t[n] = gphi;
+        if (P.site_rule == 2) {
+            const double dLdw = dLds * phi * P.inv_sbar;
+            const double sp = w * (1.0 - w) * P.inv_kappa;  // dw / d||F_{n-1}||
+            aF0[n] = dLdw * sp;
+            gg = -dLdw * sp;
+        } else {
+            aF0[n] = 0.0;
+        }
+    }
+    const bool is_max[1] = {false};
+    double v[1] = {gg}, out[1];
+    block_reduce<1>(v, is_max, threadIdx.x, blockDim.x, out);
+    if (threadIdx.x == 0) {
+        const long long bid =
+            blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        gpart[bid] += out[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* __restrict__ p, long long n) {
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+static hipError_t zero(double* p, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// post-sink rho^N of a stored state (same arithmetic as the forward first pass)
+template <int Q, typename S, typename M>
+__global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src,
+                                                       const void* __restrict__ carry,
+                                                       const void* __restrict__ phi_field,
+                                                       M* __restrict__ rhoN, Geo g, Phys<M> P) {
+    int x, y, z;
+    long long n;
+    if (!node_xyz(g, x, y, z, n)) return;
+    const Nb b = wrap(g, x, y, z);
+    M ft[Q], dd[Q], j[3], drho, dsum;
+    pull<Q, false>(src, nullptr, g, b, x, y, z, n, ft, dd);
+    moments<Q>(ft, dd, drho, dsum, j);
+    const M rho = P.rho_ref + drho;
+    dsum -= M(2) * site_sink<S>(P, carry, phi_field, n, rho, dsum);
+    rhoN[n] = dsum / rho;
+}
+
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, AdjWork w) {
+    if constexpr (WALLS) {
+        return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
+    } else {
+        hipLaunchKernelGGL((k_adj_seed<Q, S, M>), node_grid(c->g), node_block(c->g), 0, c->stream,
+                           static_cast<const S*>(c->pop[c->cur]), g_rhoN, w.mu[1], w.ab[1],
+                           w.aF[1], c->g, phys<M>(c));
+        return check(c, hipGetLastError(), "adjoint seed");
+    }
+}
+
+// One reverse step on the stored state (pop, carry); adjoint 1 -> 0.
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* carry, AdjWork w,
+                             double* grad_phi, double* grad_phi_t) {
+    if constexpr (WALLS) {
+        return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
+    } else {
+        const Phys<M> Pm = phys<M>(c);
+        const Phys<double> P = phys<double>(c);
+        const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+        M* rhoN = static_cast<M*>(c->rhoN);
+        hipLaunchKernelGGL((k_phase_state<Q, S, M>), gr, bl, 0, c->stream,
+                           static_cast<const S*>(pop), carry, c->phi_field, rhoN, c->g, Pm);
+        hipLaunchKernelGGL((k_adj_local<Q, S, M>), gr, bl, 0, c->stream,
+                           static_cast<const S*>(pop), carry, c->phi_field, rhoN, w.mu[1],
+                           w.ab[1], w.aF[1], w.mu[0], w.loc, w.lamF, c->g, P);
+        hipLaunchKernelGGL((k_adj_gather<Q, S, M>), gr, bl, 0, c->stream, carry, c->phi_field,
+                           rhoN, w.loc, w.lamF, w.ab[0], w.aF[0], grad_phi, grad_phi_t, w.gpart,
+                           c->g, P);
+        return check(c, hipGetLastError(), "adjoint step");
+    }
+}
+
+cge_status adjoint_seed(cge_ctx* c, const double* g_rhoN, void* work, int parity) {
+    AdjWork w = adj_work(c, work, parity);
+    CGE_DISPATCH(c, seed_impl, c, g_rhoN, w);
+}
+
+cge_status adjoint_rstep(cge_ctx* c, const void* pop, const void* carry, void* work, int parity,
+                         double* grad_phi, double* grad_phi_t) {
+    AdjWork w = adj_work(c, work, parity);
+    CGE_DISPATCH(c, rstep_impl, c, pop, carry, w, grad_phi, grad_phi_t);
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace cge
+
+using namespace cge;
+
+extern "C" {
+
+size_t cge_adjoint_bytes(const cge_params* p) {
+    if (!cge_population_bytes(p)) return 0;
+    return adjoint_bytes(p);
+}
+
+cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ckpt) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (nsteps < 1 || K < 1 || !ckpt) return fail(c, CGE_EINVAL, "nsteps >= 1, K >= 1, ckpt");
+    for (long long n0 = 0, j = 0; n0 < nsteps; n0 += K, ++j) {
+        if (!ckpt[j]) return fail(c, CGE_EINVAL, "NULL checkpoint buffer");
+        if (cge_status s = cge_save_state(c, ckpt[j])) return s;
+        if (cge_status s = cge_step(c, nsteps - n0 < K ? nsteps - n0 : K)) return s;
+    }
+    return CGE_OK;
+}
+
+cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, void* seg,
+                        void* work, const double* dL_drhoN, double* grad_phi,
+                        double* grad_phi_t, double* grad_gamma) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (nsteps < 1 || K < 1 || !ckpt || !seg || !work || !dL_drhoN || !grad_phi)
+        return fail(c, CGE_EINVAL, "missing argument");
+    if (c->flags) return fail(c, CGE_EUNSUPPORTED, "adjoint needs a domain without solid nodes");
+    if (c->p.site_rule == CGE_SITE_PHASE_LT)
+        return fail(c, CGE_EUNSUPPORTED, "adjoint supports the gradient site rules only");
+    const long long N = c->g.N;
+    const size_t sb = align256(cge_state_bytes(&c->p));
+    // layout of a saved state: populations, then the carried site data at a 256-byte boundary
+    const size_t carry_at = align256(cge_population_bytes(&c->p));
+    char* segb = static_cast<char*>(seg);
+    // forward bookkeeping is restored after the recomputation
+    const long long step0 = c->step;
+    std::vector<char> acc_save((size_t)c->acc_len * (sizeof(double) + sizeof(long long)));
+    if (cge_status s = check(c, hipMemcpyAsync(acc_save.data(), c->acc_sink,
+                                               c->acc_len * sizeof(double),
+                                               hipMemcpyDeviceToHost, c->stream), "acc save"))
+        return s;
+    if (cge_status s = check(c, hipMemcpyAsync(acc_save.data() + c->acc_len * sizeof(double),
+                                               c->acc_sites, c->acc_len * sizeof(long long),
+                                               hipMemcpyDeviceToHost, c->stream), "acc save"))
+        return s;
+    if (cge_status s = check(c, hipStreamSynchronize(c->stream), "sync")) return s;
+
+    const dim3 gr = node_grid(c->g);
+    const long long nblk = (long long)gr.x * gr.y * gr.z;
+    AdjWork w0 = adj_work(c, work, 0);
+    if (zero(grad_phi, N, c->stream) != hipSuccess || zero(w0.gpart, nblk, c->stream) != hipSuccess)
+        return fail(c, CGE_EDEVICE, "clearing gradients failed");
+    // seed from the current state (the state after nsteps)
+    int parity = 0;
+    if (cge_status s = adjoint_seed(c, dL_drhoN, work, parity)) return s;
+    const long long nseg = (nsteps + K - 1) / K;
+    for (long long j = nseg - 1; j >= 0; --j) {
+        const long long n0 = j * K;
+        const long long len = nsteps - n0 < K ? nsteps - n0 : K;
+        if (cge_status s = cge_load_state(c, ckpt[j])) return s;
+        c->step = step0 - nsteps + n0;  // the recomputed steps draw the same rounding keys
+        for (long long t = 0; t < len; ++t) {  // states n0 .. n0 + len - 1
+            if (cge_status s = cge_save_state(c, segb + t * sb)) return s;
+            if (t + 1 < len)
+                if (cge_status s = cge_step(c, 1)) return s;
+        }
+        for (long long t = len - 1; t >= 0; --t) {
+            double* gt = grad_phi_t ? grad_phi_t + (n0 + t) * N : nullptr;
+            if (cge_status s = adjoint_rstep(c, segb + t * sb, segb + t * sb + carry_at,
+                                             work, parity, grad_phi, gt))
+                return s;
+            parity = 1 - parity;
+        }
+    }
+    // dL/dGamma: fixed-order sum of the per-block partials
+    std::vector<double> gp((size_t)nblk);
+    if (cge_status s = check(c, hipMemcpyAsync(gp.data(), w0.gpart, nblk * sizeof(double),
+                                               hipMemcpyDeviceToHost, c->stream), "gamma copy"))
+        return s;
+    if (cge_status s = check(c, hipMemcpyAsync(c->acc_sink, acc_save.data(),
+                                               c->acc_len * sizeof(double),
+                                               hipMemcpyHostToDevice, c->stream), "acc restore"))
+        return s;
+    if (cge_status s = check(c, hipMemcpyAsync(c->acc_sites,
+                                               acc_save.data() + c->acc_len * sizeof(double),
+                                               c->acc_len * sizeof(long long),
+                                               hipMemcpyHostToDevice, c->stream), "acc restore"))
+        return s;
+    if (cge_status s = check(c, hipStreamSynchronize(c->stream), "sync")) return s;
+    c->step = step0;
+    double gsum = 0.0;
+    for (double v : gp) gsum += v;
+    if (grad_gamma) *grad_gamma = gsum;
+    return CGE_OK;
+}
+
+}  // extern "C"

@@ -46,6 +46,7 @@ Phys<M> phys(const cge_ctx* c) {
     P.gamma = M(c->p.gamma);
     P.phi = M(c->p.phi);
     P.inv_sbar = M(1.0 / c->p.sbar);
+    P.inv_kappa = M(c->p.site_rule == CGE_SITE_SOFT ? 1.0 / c->p.kappa : 0.0);
     P.site_rule = c->p.site_rule;
     return P;
 }
@@ -132,8 +133,11 @@ static const char* validate(const cge_params* p) {
     if (!is_fin(p->phi)) return "phi must be finite";
     if (!(is_fin(p->sbar) && p->sbar >= 1.0)) return "sbar must be >= 1";
     if (!is_fin(p->gamma)) return "gamma must be finite";
-    if (p->site_rule != CGE_SITE_GRAD_GT && p->site_rule != CGE_SITE_PHASE_LT)
+    if (p->site_rule != CGE_SITE_GRAD_GT && p->site_rule != CGE_SITE_PHASE_LT &&
+        p->site_rule != CGE_SITE_SOFT)
         return "unknown site rule";
+    if (p->site_rule == CGE_SITE_SOFT && !(is_fin(p->kappa) && p->kappa > 0.0))
+        return "kappa must be > 0 for the soft site rule";
     if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_SPLIT) return "unknown kernel";
     return nullptr;
 }
@@ -166,7 +170,8 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     // the fused step needs D3Q19 and no solid nodes (the latter is known at cge_bind); the
     // split step needs unit relaxation times
     const bool unit = split_supported(c);
-    if ((params->kernel == CGE_KERNEL_FUSED && c->Q != 19) ||
+    const bool soft = params->site_rule == CGE_SITE_SOFT;
+    if ((params->kernel == CGE_KERNEL_FUSED && (c->Q != 19 || soft)) ||
         (params->kernel == CGE_KERNEL_SPLIT && !unit)) {
         delete c;
         return CGE_EUNSUPPORTED;
@@ -261,9 +266,18 @@ cge_status cge_get_populations(cge_ctx* c, double* f) {
     return get_populations(c, f);
 }
 
+static size_t carry_bytes(const cge_params* p) {
+    return (size_t)p->nx * p->ny * p->nz * (p->site_rule == CGE_SITE_SOFT ? sizeof(double) : 1);
+}
+
+// the carried site data starts at the first 256-byte boundary after the populations
+static size_t carry_offset(const cge_params* p) {
+    return (cge_population_bytes(p) + 255) & ~(size_t)255;
+}
+
 size_t cge_state_bytes(const cge_params* p) {
     const size_t pb = cge_population_bytes(p);
-    return pb ? pb + (size_t)p->nx * p->ny * p->nz : 0;
+    return pb ? carry_offset(p) + carry_bytes(p) : 0;
 }
 
 cge_status cge_save_state(cge_ctx* c, void* dst) {
@@ -274,8 +288,9 @@ cge_status cge_save_state(cge_ctx* c, void* dst) {
     if (cge_status s = check(c, hipMemcpyAsync(dst, c->pop[c->cur], pb, hipMemcpyDeviceToDevice,
                                                c->stream), "state save"))
         return s;
-    return check(c, hipMemcpyAsync(static_cast<char*>(dst) + pb, c->carry, (size_t)c->g.N,
-                                   hipMemcpyDeviceToDevice, c->stream), "state save");
+    return check(c, hipMemcpyAsync(static_cast<char*>(dst) + carry_offset(&c->p), c->carry,
+                                   carry_bytes(&c->p), hipMemcpyDeviceToDevice, c->stream),
+                 "state save");
 }
 
 cge_status cge_load_state(cge_ctx* c, const void* src) {
@@ -286,14 +301,24 @@ cge_status cge_load_state(cge_ctx* c, const void* src) {
     if (cge_status s = check(c, hipMemcpyAsync(c->pop[c->cur], src, pb, hipMemcpyDeviceToDevice,
                                                c->stream), "state load"))
         return s;
-    return check(c, hipMemcpyAsync(c->carry, static_cast<const char*>(src) + pb, (size_t)c->g.N,
-                                   hipMemcpyDeviceToDevice, c->stream), "state load");
+    return check(c, hipMemcpyAsync(c->carry, static_cast<const char*>(src) + carry_offset(&c->p),
+                                   carry_bytes(&c->p), hipMemcpyDeviceToDevice, c->stream),
+                 "state load");
 }
 
 cge_status cge_reset_sites(cge_ctx* c) {
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     return reset_sites(c);
+}
+
+cge_status cge_set_site_threshold(cge_ctx* c, double gamma, double kappa) {
+    if (!c) return CGE_EINVAL;
+    if (!is_fin(gamma) || !is_fin(kappa))
+        return fail(c, CGE_EINVAL, "site threshold must be finite");
+    c->p.gamma = gamma;
+    if (kappa > 0.0) c->p.kappa = kappa;
+    return CGE_OK;
 }
 
 cge_status cge_set_counters(cge_ctx* c, long long step, long long site_steps, double sink_total) {

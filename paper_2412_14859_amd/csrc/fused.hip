@@ -318,7 +318,8 @@ __global__ __launch_bounds__(256) void k_copy_bytes(const uint8_t* __restrict__ 
 // The Q slots of one component must fit a buffer resource's signed 32-bit byte range.
 bool fused_supported(const cge_ctx* c) {
     const long long elem = c->p.precision == CGE_FP64 ? 8 : (c->p.precision == CGE_FP32S ? 4 : 2);
-    return c->Q == 19 && c->flags == nullptr && 19ll * c->g.N * elem < (1ll << 31);
+    return c->Q == 19 && c->flags == nullptr && c->p.site_rule != CGE_SITE_SOFT &&
+           19ll * c->g.N * elem < (1ll << 31);
 }
 
 long long fused_blocks(const cge_ctx* c) { return fused_shape(c->g).nb; }

@@ -75,6 +75,9 @@ cge_status set_populations(cge_ctx* c, const double* f);
 cge_status get_populations(cge_ctx* c, double* f);
 cge_status fields(cge_ctx* c, double* rr, double* rb, double* u, double* rhoN);
 
+// adjoint workspace size
+size_t adjoint_bytes(const cge_params* p);
+
 // observables into c->obs_res (device), then copied to host by the caller
 cge_status observables(cge_ctx* c);
 

@@ -77,7 +77,8 @@ struct Phys {
     M gamma;
     M phi;            // uniform flux
     M inv_sbar;
-    int site_rule;    // 0 grad, 1 phase
+    M inv_kappa;      // soft site rule width
+    int site_rule;    // 0 grad, 1 phase, 2 soft
 };
 
 struct Geo {

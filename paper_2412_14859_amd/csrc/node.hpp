@@ -140,22 +140,63 @@ __device__ __forceinline__ void moments(const M (&ft)[Q], const M (&dd)[Q], M& d
     }
 }
 
-// Site decision and sink for one node (site criterion; Eqs. relation, exchange).
-// Returns the sink s applied (0 if not a site).  dsum is pre-sink on entry.
-// The flux field is stored in double next to FP64 populations and in float otherwise.
+// Site weight m(x) of the sink (site criterion of Sec. II.B) from the carried site data:
+//   rule 0: the carried mask byte (||F_{n-1}|| > Gamma, set by the previous step);
+//   rule 1: |rho^N_pre| < Gamma from the current pre-sink phase field (dsum / rho);
+//   rule 2: the logistic function of (||F_{n-1}|| - Gamma) / kappa with the carried gradient
+//           magnitude (double): a differentiable stand-in for the threshold.
+template <typename M>
+__device__ __forceinline__ M site_weight(const Phys<M>& P, const void* __restrict__ carry,
+                                         long long n, M rho, M dsum) {
+    if (P.site_rule == 2) {
+        const M fprev = static_cast<M>(static_cast<const double*>(carry)[n]);
+        return M(1) / (M(1) + exp(-(fprev - P.gamma) * P.inv_kappa));
+    }
+    if (P.site_rule == 0) return static_cast<const uint8_t*>(carry)[n] ? M(1) : M(0);
+    return fabs(dsum / rho) < P.gamma ? M(1) : M(0);
+}
+
+// A node counts as a site when its weight exceeds 1/2 (exactly the sharp rules' sites).
+template <typename M>
+__device__ __forceinline__ bool is_site(M w) {
+    return w > M(0.5);
+}
+
+// Carry of the next step: the mask byte, or ||F_n|| for the soft rule.
+template <typename M>
+__device__ __forceinline__ void carry_store(const Phys<M>& P, void* __restrict__ carry, long long n,
+                                            M Fn) {
+    if (P.site_rule == 2) static_cast<double*>(carry)[n] = static_cast<double>(Fn);
+    else static_cast<uint8_t*>(carry)[n] = Fn > P.gamma ? 1 : 0;
+}
+
+// Node flux phi(x): the bound field (double next to FP64 populations, float otherwise) or the
+// uniform value.
 template <typename S>
 using PhiT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
 
 template <typename S, typename M>
-__device__ __forceinline__ M site_sink(const Phys<M>& P, const uint8_t* __restrict__ carry,
+__device__ __forceinline__ M node_phi(const Phys<M>& P, const void* __restrict__ phi_field,
+                                      long long n) {
+    return phi_field ? static_cast<M>(static_cast<const PhiT<S>*>(phi_field)[n]) : P.phi;
+}
+
+// Sink s = m phi / Sbar of one node (Eqs. relation, exchange); w receives the weight m.
+// dsum is pre-sink.
+template <typename S, typename M>
+__device__ __forceinline__ M site_sink(const Phys<M>& P, const void* __restrict__ carry,
+                                       const void* __restrict__ phi_field, long long n, M rho,
+                                       M dsum, M& w) {
+    w = site_weight<M>(P, carry, n, rho, dsum);
+    if (w == M(0)) return M(0);
+    return w * (node_phi<S, M>(P, phi_field, n) * P.inv_sbar);
+}
+template <typename S, typename M>
+__device__ __forceinline__ M site_sink(const Phys<M>& P, const void* __restrict__ carry,
                                        const void* __restrict__ phi_field, long long n, M rho,
                                        M dsum) {
-    bool m;
-    if (P.site_rule == 0) m = carry[n] != 0;
-    else m = fabs(dsum / rho) < P.gamma;
-    if (!m) return M(0);
-    const M phi = phi_field ? static_cast<M>(static_cast<const PhiT<S>*>(phi_field)[n]) : P.phi;
-    return phi * P.inv_sbar;
+    M w;
+    return site_sink<S, M>(P, carry, phi_field, n, rho, dsum, w);
 }
 
 // The same decision from values fetched ahead of the populations: the carried mask byte and

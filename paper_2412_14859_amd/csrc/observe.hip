@@ -59,7 +59,7 @@ __device__ __forceinline__ long long block_id() {
 template <int Q, typename S, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_obs_a(const S* __restrict__ src,
                                                  const uint8_t* __restrict__ flags,
-                                                 const uint8_t* __restrict__ carry,
+                                                 const void* __restrict__ carry,
                                                  double* __restrict__ rhoN,
                                                  double* __restrict__ part, long long nblk, Geo g,
                                                  Phys<double> P, double zeta) {
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kTPBX) void k_obs_a(const S* __restrict__ src,
         v[O_NNEG] = nneg;
         if (rN > 0.9) { v[O_PIN] = p; v[O_NIN] = 1.0; }
         if (rN < -0.9) { v[O_POUT] = p; v[O_NOUT] = 1.0; }
-        const bool site = P.site_rule == 0 ? carry[n] != 0 : fabs(rN) < P.gamma;
+        const bool site = is_site(site_weight<double>(P, carry, n, rho, rr - rb));
         v[O_NSITES] = site ? 1.0 : 0.0;
         v[O_MAXU] = sqrt(j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / rho;
         v[O_MAXRR] = rr;

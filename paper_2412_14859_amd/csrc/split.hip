@@ -87,12 +87,11 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
             }
         }
         const M rho = P.rho_ref + drho;
-        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum);
+        M wgt;
+        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum, wgt);
         dsum -= M(2) * s;
-        if (s != M(0)) {
-            v[0] = static_cast<double>(s);
-            v[1] = 1.0;
-        }
+        v[0] = static_cast<double>(s);
+        v[1] = is_site(wgt) ? 1.0 : 0.0;
         rhoN[n] = dsum / rho;
         mom[n] = static_cast<MomT<S>>(drho);
         mom[g.N + n] = static_cast<MomT<S>>(j[0]);
@@ -164,7 +163,9 @@ __global__ __launch_bounds__(kTPBX) void k_finish(S* __restrict__ dst,
     carry[n] = Fn > P.gamma ? 1 : 0;
 }
 
-bool split_supported(const cge_ctx* c) { return c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0; }
+bool split_supported(const cge_ctx* c) {
+    return c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0 && c->p.site_rule != CGE_SITE_SOFT;
+}
 
 size_t split_scratch_bytes(const cge_params* p) {
     const size_t e = p->precision == CGE_FP64 ? 8 : 4;

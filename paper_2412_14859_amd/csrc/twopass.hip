@@ -13,7 +13,7 @@ namespace cge {
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_phase(const S* __restrict__ src,
                                                  const uint8_t* __restrict__ flags,
-                                                 const uint8_t* __restrict__ carry,
+                                                 const void* __restrict__ carry,
                                                  const void* __restrict__ phi_field,
                                                  M* __restrict__ rhoN, Geo g, Phys<M> P,
                                                  int apply_sink) {
@@ -30,29 +30,30 @@ __global__ __launch_bounds__(kTPBX) void k_phase(const S* __restrict__ src,
     rhoN[n] = dsum / rho;
 }
 
-// Site mask ||F|| > gamma from the rho^N field (no collision); solid nodes get 0.
+// Site data (mask byte, or ||F|| for the soft rule) from the rho^N field, without
+// collision; solid nodes get 0.
 template <int Q, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_carry(const uint8_t* __restrict__ flags,
                                                  const M* __restrict__ rhoN,
-                                                 uint8_t* __restrict__ carry, Geo g, Phys<M> P) {
+                                                 void* __restrict__ carry, Geo g, Phys<M> P) {
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
     if (WALLS && flags[n]) {
-        carry[n] = 0;
+        carry_store<M>(P, carry, n, M(0));
         return;
     }
     const Nb b = wrap(g, x, y, z);
     M F[3];
     gradient<Q>(rhoN, g, b, x, y, z, F);
-    carry[n] = sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]) > P.gamma ? 1 : 0;
+    carry_store<M>(P, carry, n, sqrt(F[0] * F[0] + F[1] * F[1] + F[2] * F[2]));
 }
 
 // Pass 2: the full step at one node.
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S* __restrict__ dst,
                                                    const uint8_t* __restrict__ flags,
-                                                   uint8_t* __restrict__ carry,
+                                                   void* __restrict__ carry,
                                                    const void* __restrict__ phi_field,
                                                    const M* __restrict__ rhoN,
                                                    double* __restrict__ acc_sink,
@@ -68,13 +69,12 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
         moments<Q>(ft, dd, drho, dsum, j);
         const M rho = P.rho_ref + drho;
-        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum);
+        M w;
+        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum, w);
         dd[0] -= M(2) * s;
         dsum -= M(2) * s;
-        if (s != M(0)) {
-            v[0] = static_cast<double>(s);
-            v[1] = 1.0;
-        }
+        v[0] = static_cast<double>(s);
+        v[1] = is_site(w) ? 1.0 : 0.0;
         const M inv_rho = M(1) / rho;
         const M u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
         const M rN = dsum * inv_rho;
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
                                     st(dst + (long long)i * g.N + n, a, key);
                                     st(dst + (long long)(Q + i) * g.N + n, d, key + (uint64_t)g.N);
                                 });
-        carry[n] = Fn > P.gamma ? 1 : 0;
+        carry_store<M>(P, carry, n, Fn);
     }
     const bool is_max[2] = {false, false};
     double out[2];

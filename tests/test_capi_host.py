@@ -41,7 +41,8 @@ def _params(**over):
 
 @pytest.mark.parametrize("over", [dict(lattice=7), dict(nx=0), dict(nz=2), dict(tau=0.5),
                                   dict(rho_in=0.0), dict(beta=1.5), dict(sbar=0.5),
-                                  dict(precision=3), dict(site_rule=2), dict(kernel=9),
+                                  dict(precision=3), dict(site_rule=3), dict(kernel=9),
+                                  dict(site_rule=2, kappa=0.0), dict(site_rule=2, kappa=float("nan")),
                                   dict(sigma=-1.0), dict(phi=float("nan")),
                                   dict(gamma=float("inf"))])
 def test_invalid_parameters_are_rejected_on_the_host(over):

@@ -1,0 +1,256 @@
+"""GPU adjoint (cge_forward_ckpt / cge_backward) against the FP64 CPU autograd reference on
+the same seeded inputs, against central finite differences of the GPU's own forward run, and
+through the torch.autograd.Function wrapper.
+
+Loss: L = sum_x (rho^N_T - target)^2, so dL/drho^N_T = 2 (rho^N_T - target).  Hard sites
+(||F_{n-1}|| > Gamma) are held at the forward run's; soft sites are logistic in
+(||F_{n-1}|| - Gamma) / kappa and also give dL/dGamma."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as A
+from tests.helpers import case, gpu_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _target(shape, r):
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz) - (nz - 1) / 2.0, np.arange(ny) - ny / 2.0,
+                          np.arange(nx) - nx / 2.0, indexing="ij")
+    rr = np.sqrt(x * x + y * y + (z * z if nz > 1 else 0.0))
+    return np.tanh((r - rr) / 2.0)
+
+
+CASES = {
+    # name: (workload, shape, overrides, target radius)
+    "d2q9_hard": ("adjoint2d", (1, 16, 18), dict(radius=5.0, phi=3e-3, site_rule="grad"), 5.5),
+    "d2q9_soft": ("adjoint2d", (1, 16, 18), dict(radius=5.0, phi=3e-3, site_rule="soft",
+                                                 kappa=0.02), 5.5),
+    "d2q9_soft_ratio": ("adjoint2d", (1, 20, 22), dict(radius=6.0, phi=3e-3, site_rule="soft",
+                                                       kappa=0.02, rho_in=(1.0, 0.5),
+                                                       tau=(1.0, 0.7), beta=0.6), 6.5),
+    "d3q19_soft": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3, site_rule="soft",
+                                                kappa=0.02), 3.3),
+    "d3q19_hard": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3), 3.3),
+}
+
+
+def _setup(name):
+    wl, shape, over, r = CASES[name]
+    w = case(wl, shape, **over)
+    if w["phi_field"] is None:  # a seeded field around the uniform flux
+        rng = np.random.default_rng(5)
+        w["phi_field"] = w["params"]["phi"] * rng.uniform(0.8, 1.2, shape)
+    return w, _target(shape, r)
+
+
+def _gpu_gradients(w, target, nsteps, K, precision="fp64", per_step=False, kernel="auto"):
+    import torch
+    sim = gpu_for(w, precision, kernel=kernel)
+    ck = sim.forward_ckpt(nsteps, K)
+    rn = sim.fields()["rhoN"]
+    g = 2.0 * (rn - torch.as_tensor(target, device=rn.device))
+    loss = float(((rn.cpu().numpy() - target) ** 2).sum())
+    r = sim.backward(ck, nsteps, K, g, per_step=per_step)
+    step = sim.observables()["step"]
+    out = {"loss": loss, "grad_phi": r["grad_phi"].cpu().numpy(), "grad_gamma": r["grad_gamma"],
+           "grad_phi_t": None if r["grad_phi_t"] is None else r["grad_phi_t"].cpu().numpy(),
+           "step_after": step}
+    sim.close()
+    return out
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_gradients_match_the_autograd_reference(name):
+    w, target = _setup(name)
+    p = w["params"]
+    nsteps, K = 25, 7  # segments 7, 7, 7, 4
+    _flush(f"[adjoint fp64] {name} {w['rho_r'].shape} n={nsteps} K={K}")
+    got = _gpu_gradients(w, target, nsteps, K)
+    ref = A.gradients(p, w["rho_r"], w["rho_b"], w["phi_field"], nsteps, target)
+    assert abs(got["loss"] - ref["loss"]) <= 1e-12 * ref["loss"]
+    gr = ref["grad_phi"].numpy()
+    assert np.abs(gr).max() > 0
+    e = _rel(got["grad_phi"], gr)
+    _flush(f"  grad_phi rel err {e:.2e}")
+    assert e < 1e-10, e
+    if p["site_rule"] == "soft":
+        eg = abs(got["grad_gamma"] - ref["grad_gamma"]) / abs(ref["grad_gamma"])
+        _flush(f"  grad_gamma {got['grad_gamma']:.6e} ref {ref['grad_gamma']:.6e} rel {eg:.2e}")
+        assert eg < 1e-10, eg
+    else:
+        assert got["grad_gamma"] == 0.0
+    assert got["step_after"] == nsteps  # the step counter is restored
+
+
+def test_per_step_flux_gradient_matches_the_reference():
+    w, target = _setup("d2q9_soft")
+    p = w["params"]
+    nsteps, K = 12, 5
+    _flush("[adjoint fp64] per-step dL/dphi(x, t)")
+    got = _gpu_gradients(w, target, nsteps, K, per_step=True)
+    ref = A.gradients(p, w["rho_r"], w["rho_b"], w["phi_field"], nsteps, target,
+                      space_time=True)["grad_phi"].numpy()
+    assert got["grad_phi_t"].shape == ref.shape
+    e = _rel(got["grad_phi_t"], ref)
+    assert e < 1e-10, e
+    # the time-constant gradient is the sum over the steps
+    assert np.abs(got["grad_phi_t"].sum(0) - got["grad_phi"]).max() <= 1e-15 * nsteps * \
+        np.abs(got["grad_phi"]).max()
+
+
+def test_checkpoint_interval_does_not_change_the_gradients():
+    w, target = _setup("d2q9_soft")
+    _flush("[adjoint] K in (1, 4, 9, 30) for 9 steps")
+    res = [_gpu_gradients(w, target, 9, K) for K in (1, 4, 9, 30)]
+    for r in res[1:]:
+        assert np.array_equal(r["grad_phi"], res[0]["grad_phi"])
+        assert r["grad_gamma"] == res[0]["grad_gamma"]
+
+
+def _reference_fp32_storage(w, target, nsteps):
+    """The autograd reference on the trajectory of FP32 storage: after every step the state is
+    rounded to nearest float32 in the stored encoding (ft_i = f_i^r + f_i^b - rho_b^in
+    t_i(alpha_b), dd_i = f_i^r - f_i^b), as is the flux field; the rounding passes gradients
+    through unchanged."""
+    import torch
+    DT = torch.float64
+    p = w["params"]
+    L = A.lattice(int(p["Q"]))
+    a_b = A.alphas(float(L["W"][0]), p["rho_in"])[1]
+    tref = ((L["A"] + L["B"] * a_b) * p["rho_in"][1])[:, None, None, None]
+
+    def rnd(x):
+        return x + (x.float().double() - x).detach()
+
+    def store(f):
+        ft, dd = rnd(f[0] + f[1] - tref), rnd(f[0] - f[1])
+        return torch.stack([(ft + tref + dd) / 2, (ft + tref - dd) / 2])
+
+    ph = torch.as_tensor(w["phi_field"], dtype=torch.float32).double().requires_grad_(True)
+    g = torch.tensor(p["gamma"], dtype=DT, requires_grad=True)
+    f = store(A.equilibrium_state(L, p, torch.as_tensor(w["rho_r"], dtype=DT),
+                                  torch.as_tensor(w["rho_b"], dtype=DT))).detach()
+    fprev = A.gradient_magnitude(L, f).detach()
+    for _ in range(nsteps):
+        m = torch.sigmoid((fprev - g) / p["kappa"])
+        f, fprev = A.step(L, p, f, fprev, ph, m)
+        f = store(f)
+    A.loss_rhoN(f, torch.as_tensor(target, dtype=DT)).backward()
+    return ph.grad.numpy(), float(g.grad)
+
+
+@pytest.mark.parametrize("name", ["d2q9_soft", "d2q9_soft_ratio"])
+def test_fp32_storage_gradients(name):
+    """FP32 storage: the adjoint of the FP32-storage trajectory equals the reference's on the
+    same rounded trajectory.  Against FP64 the gradients move by what rounding the state
+    moves them (~2e-4 on the equal-density case, in the reference as well), so that
+    comparison only bounds the size."""
+    w, target = _setup(name)
+    _flush(f"[adjoint fp32s] {name}")
+    g32 = _gpu_gradients(w, target, 25, 7, "fp32s")
+    rp, rg = _reference_fp32_storage(w, target, 25)
+    e = _rel(g32["grad_phi"], rp)
+    eg = abs(g32["grad_gamma"] - rg) / abs(rg)
+    g64 = _gpu_gradients(w, target, 25, 7, "fp64")
+    e64 = _rel(g32["grad_phi"], g64["grad_phi"])
+    _flush(f"  vs rounded reference: grad_phi {e:.2e} grad_gamma {eg:.2e}; vs fp64 {e64:.2e}")
+    assert e < 1e-9 and eg < 1e-9, (e, eg)
+    assert e64 < 5e-3
+
+
+def test_split_forward_recomputation_gives_the_same_gradients():
+    """Hard sites at unit relaxation times: the recomputed forward may run any step form (the
+    forms round differently, so the gradients agree to the reference tolerance)."""
+    w, target = _setup("d3q19_hard")
+    _flush("[adjoint] d3q19 hard, two-pass vs split forward")
+    a = _gpu_gradients(w, target, 10, 4, kernel="twopass")
+    b = _gpu_gradients(w, target, 10, 4, kernel="split")
+    assert _rel(b["grad_phi"], a["grad_phi"]) < 1e-10
+
+
+def test_central_differences_on_32x32_soft_sites():
+    """Directional derivatives of the GPU's own FP64 forward (central differences with
+    relative step 1e-3) against the adjoint, for phi and Gamma."""
+    import torch
+    w = case("adjoint2d", (1, 32, 32), radius=9.0, phi=3e-3, site_rule="soft", kappa=0.02)
+    target = _target((1, 32, 32), 9.5)
+    p = w["params"]
+    nsteps, K = 40, 10
+    _flush("[adjoint FD] d2q9 32x32 soft, 40 steps")
+    got = _gpu_gradients(w, target, nsteps, K)
+
+    def loss(phi_field, gamma):
+        ww = dict(w, phi_field=phi_field, params=dict(p, gamma=gamma))
+        sim = gpu_for(ww, "fp64")
+        sim.step(nsteps)
+        rn = sim.fields()["rhoN"].cpu().numpy()
+        sim.close()
+        return float(((rn - target) ** 2).sum())
+
+    rng = np.random.default_rng(3)
+    for trial in range(2):
+        v = rng.standard_normal(w["phi_field"].shape) * w["phi_field"]
+        ad = float((got["grad_phi"] * v).sum())
+        eps = 1e-3
+        fd = (loss(w["phi_field"] + eps * v, p["gamma"]) -
+              loss(w["phi_field"] - eps * v, p["gamma"])) / (2 * eps)
+        _flush(f"  phi dir {trial}: adjoint {ad:.8e} fd {fd:.8e}")
+        assert abs(fd - ad) <= 2e-3 * abs(ad), (trial, fd, ad)
+    eps = 1e-3 * p["gamma"]
+    fd = (loss(w["phi_field"], p["gamma"] + eps) - loss(w["phi_field"], p["gamma"] - eps)) / (2 * eps)
+    _flush(f"  gamma: adjoint {got['grad_gamma']:.8e} fd {fd:.8e}")
+    assert abs(fd - got["grad_gamma"]) <= 2e-3 * abs(got["grad_gamma"])
+    del torch
+
+
+def test_autograd_function_wrapper():
+    import torch
+    from paper_2412_14859_amd import cgevap
+    w, target = _setup("d2q9_soft")
+    _flush("[adjoint] torch.autograd.Function")
+    sim = gpu_for(w, "fp64")
+    start = sim.save_state().clone()
+    dev = sim.device
+    phi = torch.as_tensor(w["phi_field"], device=dev).requires_grad_(True)
+    gamma = torch.tensor(w["params"]["gamma"], dtype=torch.float64, device=dev,
+                         requires_grad=True)
+    tgt = torch.as_tensor(target, device=dev)
+    for _ in range(2):  # the start state is reloaded on every call
+        phi.grad = gamma.grad = None
+        rn = cgevap.evaporate(sim, phi, gamma, 25, 7, start)
+        loss = ((rn - tgt) ** 2).sum()
+        loss.backward()
+        ref = A.gradients(w["params"], w["rho_r"], w["rho_b"], w["phi_field"], 25, target)
+        assert abs(float(loss) - ref["loss"]) <= 1e-12 * ref["loss"]
+        assert _rel(phi.grad.cpu().numpy(), ref["grad_phi"].numpy()) < 1e-10
+        assert abs(float(gamma.grad) - ref["grad_gamma"]) <= 1e-10 * abs(ref["grad_gamma"])
+    sim.close()
+
+
+def test_unsupported_configurations_are_rejected():
+    import torch
+    from paper_2412_14859_amd import cgevap
+    w = case("flat2d", (1, 12, 16), phi=1e-3)  # solid walls
+    sim = gpu_for(w, "fp64")
+    ck = sim.forward_ckpt(2, 2)
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.backward(ck, 2, 2, torch.zeros(sim.shape, dtype=torch.float64, device=sim.device))
+    assert e.value.status == cgevap.EUNSUPPORTED
+    sim.close()
+    w = case("drop2d", (1, 12, 16), radius=4.0, phi=1e-3)  # |rho^N| < Gamma site rule
+    sim = gpu_for(w, "fp64")
+    ck = sim.forward_ckpt(2, 2)
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.backward(ck, 2, 2, torch.zeros(sim.shape, dtype=torch.float64, device=sim.device))
+    assert e.value.status == cgevap.EUNSUPPORTED
+    sim.close()
