@@ -168,10 +168,13 @@ cge_status cge_load_state(cge_ctx* ctx, const void* src);
  * threshold Gamma are returned.
  *   cge_forward_ckpt : from the current state, advance nsteps and save the state (as
  *                      cge_save_state) at steps 0, K, 2K, ... into ckpt[0..ceil(nsteps/K)-1],
- *                      each of cge_state_bytes().
+ *                      each of cge_state_bytes().  At unit relaxation times it steps with the
+ *                      split form (CGE_KERNEL_SPLIT), which the backward recomputes with.
  *   cge_backward     : call after cge_forward_ckpt with the same nsteps and K, with the state
- *                      after nsteps current.  seg: K * round_up(cge_state_bytes(), 256) bytes
- *                      for the recomputed states of one segment; work: cge_adjoint_bytes();
+ *                      after nsteps current.  seg: cge_segment_bytes(K) bytes for the
+ *                      recomputed steps of one segment (at unit relaxation times each step's
+ *                      phase field, moments and site data, otherwise each state);
+ *                      work: cge_adjoint_bytes();
  *                      dL_drhoN: [N] doubles; grad_phi (out): [N] doubles, dL/dphi(x) summed
  *                      over the steps (phi held over time); grad_phi_t (out, nullable):
  *                      [nsteps][N] doubles, dL/dphi(x, t) per step; grad_gamma (host, nullable):
@@ -182,6 +185,7 @@ cge_status cge_load_state(cge_ctx* ctx, const void* src);
  * Errors: CGE_EINVAL (missing buffers, nsteps or K < 1), CGE_EUNSUPPORTED (solid nodes,
  * PHASE_LT rule), CGE_EDEVICE. */
 size_t cge_adjoint_bytes(const cge_params* params);
+size_t cge_segment_bytes(const cge_params* params, int K);
 cge_status cge_forward_ckpt(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt);
 cge_status cge_backward(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt, void* seg,
                         void* work, const double* dL_drhoN, double* grad_phi, double* grad_phi_t,

@@ -21,7 +21,7 @@ ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 # every symbol the header declares
 EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
            "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
-           "cge_load_state", "cge_adjoint_bytes", "cge_forward_ckpt", "cge_backward",
+           "cge_load_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
            "cge_reset_sites", "cge_set_site_threshold", "cge_set_counters", "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
@@ -79,6 +79,8 @@ def lib():
         L.cge_load_state.argtypes = [vp, vp]
         L.cge_adjoint_bytes.argtypes = [P(CgeParams)]
         L.cge_adjoint_bytes.restype = C.c_size_t
+        L.cge_segment_bytes.argtypes = [P(CgeParams), C.c_int]
+        L.cge_segment_bytes.restype = C.c_size_t
         L.cge_forward_ckpt.argtypes = [vp, C.c_longlong, C.c_int, P(vp)]
         L.cge_backward.argtypes = [vp, C.c_longlong, C.c_int, P(vp), vp, vp, vp, vp, vp, dp]
         L.cge_reset_sites.argtypes = [vp]
@@ -276,10 +278,10 @@ class Simulation:
         t = self.torch
         nck = len(ckpt)
         assert nck == (int(nsteps) + K - 1) // K
-        sb = (self._state_bytes() + 255) // 256 * 256
-        seg = t.empty(K * sb, dtype=t.uint8, device=self.device)
-        work = t.empty(lib().cge_adjoint_bytes(C.byref(make_params(self.params, self.precision))),
-                       dtype=t.uint8, device=self.device)
+        cp = make_params(self.params, self.precision)
+        seg = t.empty(lib().cge_segment_bytes(C.byref(cp), int(K)), dtype=t.uint8,
+                      device=self.device)
+        work = t.empty(lib().cge_adjoint_bytes(C.byref(cp)), dtype=t.uint8, device=self.device)
         g = self._dev64(dL_drhoN).reshape(self.shape).contiguous()
         gphi = t.empty(self.shape, dtype=t.float64, device=self.device)
         gpt = (t.empty((int(nsteps),) + self.shape, dtype=t.float64, device=self.device)

@@ -7,17 +7,21 @@
 // field's dependence on rho adds the same term to every colour-blind direction, lambda of a
 // node is kept as Q values mu'_i plus two scalars (a, b):
 //     dL/dft_i = mu'_i + a,    dL/ddd_i = b    (all i).
+// At unit relaxation times BGK returns the equilibrium, so the step depends on the old
+// populations only through the post-sink moments (rho, j) and mu'_i = p0 + c_i . dj: the
+// adjoint of a node is then D + 3 numbers, and the reverse step needs the forward's phase
+// field and moments only (kept by the split step during the recomputation), not its
+// populations.
 //
 // One reverse step n (state S_n, adjoint of S_{n+1} given):
-//   k_phase       post-sink rho^N of S_n (the forward kernel);
-//   k_adj_local   per node: gather the adjoint of the post-collision values from x + c_i
-//                 (reverse of the pull), recompute the forward intermediates, and apply the
-//                 transposed Jacobian of collision, perturbation and recolouring (Eqs. collision,
-//                 feq, perturb, recolor); writes mu'_i, the local dL/drho^N, rho, dL/dF;
-//   k_adj_gather  per node: dL/drho^N += sum_i 3 W_i c_i . dL/dF(x - c_i) (the transposed
-//                 gradient stencil), giving (a, b); the sink s = m phi / Sbar enters as
-//                 dd_0 -= 2 s, so dL/ds = -2 b, hence dL/dphi(x, n) = -2 b m / Sbar; for the
-//                 soft rule also dL/dm, which flows into dL/d||F_{n-1}|| and dL/dGamma.
+//   local   per node: gather the adjoint of the post-collision values from x + c_i (reverse
+//           of the pull), recompute the forward intermediates, and apply the transposed
+//           Jacobian of collision, perturbation and recolouring (Eqs. collision, feq,
+//           perturb, recolor); writes mu' (or p0, dj), the local dL/drho^N, rho, dL/dF;
+//   gather  per node: dL/drho^N += sum_i 3 W_i c_i . dL/dF(x - c_i) (the transposed
+//           gradient stencil), giving (a, b); the sink s = m phi / Sbar enters as
+//           dd_0 -= 2 s, so dL/ds = -2 b, hence dL/dphi(x, n) = -2 b m / Sbar; for the
+//           soft rule also dL/dm, which flows into dL/d||F_{n-1}|| and dL/dGamma.
 // The forward states of a segment of K steps are recomputed from the segment's checkpoint.
 #include <vector>
 
@@ -26,21 +30,21 @@
 
 namespace cge {
 
-// adjoint workspace (doubles): mu[2][Q][N], ab[2][2][N], aF[2][N], loc[2][N], lamF[3][N],
-// then one gamma partial per block of the node grid
+// adjoint workspace (doubles): mu[2][nmu][N], ab[2][2][N], aF[2][N], loc[2][N], lamF[3][N],
+// then one gamma partial per block of the node grid; nmu = Q, or 4 (p0, dj) at unit tau
 struct AdjWork {
     double *mu[2], *ab[2], *aF[2], *loc, *lamF, *gpart;
 };
 
 // Index 1 of mu, ab, aF is the input of a reverse step (adjoint of the later state) and
 // index 0 its result; the two halves of the buffer swap roles with the parity of the step.
-static AdjWork adj_work(const cge_ctx* c, void* base, int parity) {
-    const long long N = c->g.N, Q = c->Q;
+static AdjWork adj_work(const cge_ctx* c, void* base, int parity, int nmu) {
+    const long long N = c->g.N;
     double* p = static_cast<double*>(base);
     AdjWork w;
     w.mu[parity] = p;
-    w.mu[1 - parity] = p + Q * N;
-    p += 2 * Q * N;
+    w.mu[1 - parity] = p + nmu * N;
+    p += 2 * (long long)c->Q * N;  // room for the general layout
     w.ab[parity] = p;
     w.ab[1 - parity] = p + 2 * N;
     p += 4 * N;
@@ -64,8 +68,27 @@ size_t adjoint_bytes(const cge_params* pr) {
     return (size_t)(2 * Q * N + 4 * N + 2 * N + 2 * N + 3 * N + nblk) * sizeof(double);
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static bool unit_tau(const cge_params* p) { return p->tau[0] == 1.0 && p->tau[1] == 1.0; }
+
+// Slot of one recomputed step at unit tau: post-sink rho^N (arithmetic type), the moment
+// record, the carried site data.
+struct UnitSlot {
+    size_t rhoN, mom, carry, bytes;
+};
+static UnitSlot unit_slot(const cge_params* p) {
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    UnitSlot s;
+    s.rhoN = 0;
+    s.mom = align256(N * (p->precision == CGE_FP16S ? 4 : 8));
+    s.carry = s.mom + align256(split_scratch_bytes(p));
+    s.bytes = s.carry + align256(carry_bytes(p));
+    return s;
+}
+
 // Seed: lambda of S_T from dL/drho^N_T, rho^N = sum dd / (rho_ref + sum ft) (pre-sink).
-template <int Q, typename S, typename M>
+template <int Q, typename S, typename M, int NMU>
 __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
                                                     const double* __restrict__ g_rhoN,
                                                     double* __restrict__ mu, double* __restrict__ ab,
@@ -81,38 +104,26 @@ __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
     const double rN = static_cast<double>(dsum) / rho;
     const double gr = g_rhoN[n];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) mu[(long long)i * g.N + n] = 0.0;
+    for (int i = 0; i < NMU; ++i) mu[(long long)i * g.N + n] = 0.0;
     ab[n] = -gr * rN / rho;
     ab[g.N + n] = gr / rho;
     aF[n] = 0.0;
 }
 
-// Local transposed Jacobian at one node (see the file comment).  All adjoint arithmetic is
-// FP64.
-template <int Q, typename S, typename M>
-__global__ __launch_bounds__(kTPBX) void k_adj_local(
-    const S* __restrict__ src, const void* __restrict__ carry, const void* __restrict__ phi_field,
-    const M* __restrict__ rhoNf, const double* __restrict__ mu1, const double* __restrict__ ab1,
-    const double* __restrict__ aF1, double* __restrict__ mu0, double* __restrict__ loc,
-    double* __restrict__ lamF, Geo g, Phys<double> P) {
-    int x, y, z;
-    long long n;
-    if (!node_xyz(g, x, y, z, n)) return;
-    const Nb nb = wrap(g, x, y, z);
-    // forward recomputation
-    M ftm[Q], ddm[Q], jm[3], drhom, dsumm;
-    pull<Q, false>(src, nullptr, g, nb, x, y, z, n, ftm, ddm);
-    moments<Q>(ftm, ddm, drhom, dsumm, jm);
-    const double drho = static_cast<double>(drhom);
-    const double rho = P.rho_ref + drho;
-    const double rN = static_cast<double>(rhoNf[n]);
-    const double u[3] = {static_cast<double>(jm[0]) / rho, static_cast<double>(jm[1]) / rho,
-                         static_cast<double>(jm[2]) / rho};
+// Transposed Jacobian of equilibrium + BGK, perturbation and recolouring at one node, all in
+// FP64.  Inputs: post-sink rho, rho^N, u, the colour gradient F, the adjoint aF1n of the
+// carried ||F|| (soft rule), in(i, mus, etas) -> adjoint of this node's outputs ft*_i, dd*_i,
+// and (general tau only) fpop(i) -> the pulled total population f_i.  Outputs: the local
+// dL/drho^N, dL/drho, dL/dj, dL/dF; for general tau also xi(i, v) with v the direct part
+// (1 - 1/tau) dL/df''_i of dL/dft_i.
+template <int Q, bool UNIT, class In, class Fpop, class Xi>
+__device__ __forceinline__ void adj_node(const Phys<double>& P, double rho, double rN,
+                                         const double (&u)[3], const double (&F)[3], double aF1n,
+                                         In in, Fpop fpop, Xi xi, double& drN_o, double& drho_o,
+                                         double (&dj_o)[3], double (&lamF_o)[3]) {
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    double F[3];
-    gradient<Q>(rhoNf, g, nb, x, y, z, F);
     const double pr = 0.5 * (1.0 + rN), pb = 0.5 * (1.0 - rN);
-    const double om = pr * P.omega_r + pb * P.omega_b;
+    const double om = UNIT ? 1.0 : pr * P.omega_r + pb * P.omega_b;
     const double abar = pr * P.alpha_r + pb * P.alpha_b;
     const double F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
     const bool hg = F2 > 0.0;
@@ -123,7 +134,6 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
     const double kp = 2.25 * P.sigma * om;
     const double sep = 0.5 * P.beta * (1.0 - rN * rN) * rho;
 
-    double xi[Q];  // dL/df''_i
     double dsep = 0.0, dab = 0.0, dkp = 0.0, dom = 0.0, drho_p = 0.0, drN = 0.0;
     double du[3] = {0.0, 0.0, 0.0}, dF[3] = {0.0, 0.0, 0.0}, sF = 0.0;  // dF += sF * F
 #pragma unroll
@@ -134,19 +144,20 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
         const double Fc = cx * F[0] + cy * F[1] + cz * F[2];
         const double t = A + B * abar;
         const double feq = rho * (t + W * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        const double f = static_cast<double>(ftm[i]) + P.rho_ref * (A + B * P.alpha_ref);
-        const double f1 = f - om * (f - feq);
         const double Pq = W * Fc * Fc * iF - pertC<Q>(i) * Fn;
-        const double f2 = f1 + kp * Pq;
+        double f2, f = 0.0;
+        if constexpr (UNIT) {
+            f2 = feq + kp * Pq;
+        } else {
+            f = fpop(i);
+            f2 = f - om * (f - feq) + kp * Pq;
+        }
         const double il = inv_len<Q>(i);
         const double cosf = Fc * iF * fade * il;
-        // adjoint of this direction's outputs, gathered from x + c_i
-        const long long xn = shifted<Q, 1>(g, nb, x, y, z, i);
-        const double mus = mu1[(long long)i * g.N + xn] + ab1[xn];
-        const double etas = ab1[g.N + xn];
+        double mus, etas;
+        in(i, mus, etas);
         // dd* = rN f2 + sep cosf t ; ft* = f2 - tref
         const double x2 = mus + rN * etas;
-        xi[i] = x2;
         drN += f2 * etas;
         dsep += etas * cosf * t;
         dab += etas * sep * cosf * B;
@@ -157,14 +168,17 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
         dF[2] += q * fade * iF * cz;
         sF += q * Fc * (dfade * iF * iF - fade * iF * iF * iF);
         // f2 = f1 + kp Pq, Pq = W Fc^2/|F| - C |F|
-        dkp += x2 * Pq;
         const double pv = x2 * kp * 2.0 * W * Fc * iF;
         dF[0] += pv * cx;
         dF[1] += pv * cy;
         dF[2] += pv * cz;
         sF += x2 * kp * (-W * Fc * Fc * iF * iF * iF - pertC<Q>(i) * iF);
         // f1 = f - om (f - feq)
-        dom += x2 * (feq - f);
+        if constexpr (!UNIT) {
+            dkp += x2 * Pq;
+            dom += x2 * (feq - f);
+            xi(i, (1.0 - om) * x2);
+        }
         const double dfeq = om * x2;
         drho_p += dfeq * feq / rho;
         dab += dfeq * rho * B;
@@ -173,26 +187,114 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
         du[1] += g3 * cy - dfeq * rho * W * 3.0 * u[1];
         du[2] += g3 * cz - dfeq * rho * W * 3.0 * u[2];
     }
-    dom += 2.25 * P.sigma * dkp;
+    // om and abar depend on rN through pr = (1 + rN)/2 (om is constant at unit tau)
+    if constexpr (!UNIT) {
+        dom += 2.25 * P.sigma * dkp;
+        drN += 0.5 * (P.omega_r - P.omega_b) * dom;
+    }
+    drN += 0.5 * (P.alpha_r - P.alpha_b) * dab;
     // sep = beta (1 - rN^2) rho / 2
     drN += dsep * (-P.beta * rN * rho);
     drho_p += dsep * 0.5 * P.beta * (1.0 - rN * rN);
-    // om and abar depend on rN through pr = (1 + rN)/2
-    drN += 0.5 * (P.omega_r - P.omega_b) * dom + 0.5 * (P.alpha_r - P.alpha_b) * dab;
     // u = j / rho
-    const double dj[3] = {du[0] / rho, du[1] / rho, du[2] / rho};
+    dj_o[0] = du[0] / rho;
+    dj_o[1] = du[1] / rho;
+    dj_o[2] = du[2] / rho;
     drho_p -= (du[0] * u[0] + du[1] * u[1] + du[2] * u[2]) / rho;
+    drN_o = drN;
+    drho_o = drho_p;
+    // the carried ||F_n|| feeds the next step's soft site weight
+    const double aFn = aF1n * iF;
+    lamF_o[0] = dF[0] + (sF + aFn) * F[0];
+    lamF_o[1] = dF[1] + (sF + aFn) * F[1];
+    lamF_o[2] = dF[2] + (sF + aFn) * F[2];
+}
+
+// General relaxation times: recompute from the stored populations.
+template <int Q, typename S, typename M>
+__global__ __launch_bounds__(kTPBX) void k_adj_local(
+    const S* __restrict__ src, const M* __restrict__ rhoNf, const double* __restrict__ mu1,
+    const double* __restrict__ ab1, const double* __restrict__ aF1, double* __restrict__ mu0,
+    double* __restrict__ loc, double* __restrict__ lamF, Geo g, Phys<double> P) {
+    int x, y, z;
+    long long n;
+    if (!node_xyz(g, x, y, z, n)) return;
+    const Nb nb = wrap(g, x, y, z);
+    M ftm[Q], ddm[Q], jm[3], drhom, dsumm;
+    pull<Q, false>(src, nullptr, g, nb, x, y, z, n, ftm, ddm);
+    moments<Q>(ftm, ddm, drhom, dsumm, jm);
+    const double rho = P.rho_ref + static_cast<double>(drhom);
+    const double rN = static_cast<double>(rhoNf[n]);
+    const double u[3] = {static_cast<double>(jm[0]) / rho, static_cast<double>(jm[1]) / rho,
+                         static_cast<double>(jm[2]) / rho};
+    double F[3];
+    gradient<Q>(rhoNf, g, nb, x, y, z, F);
+    double xi[Q];
+    double drN, drho, dj[3], lf[3];
+    adj_node<Q, false>(
+        P, rho, rN, u, F, aF1[n],
+        [&](int i, double& mus, double& etas) {
+            const long long xn = shifted<Q, 1>(g, nb, x, y, z, i);
+            mus = mu1[(long long)i * g.N + xn] + ab1[xn];
+            etas = ab1[g.N + xn];
+        },
+        [&](int i) {
+            return static_cast<double>(ftm[i]) +
+                   P.rho_ref * (restA<Q>(i) + restB<Q>(i) * P.alpha_ref);
+        },
+        [&](int i, double v) { xi[i] = v; }, drN, drho, dj, lf);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-        mu0[(long long)i * g.N + n] = (1.0 - om) * xi[i] + drho_p + Lat<Q>::cx[i] * dj[0] +
+        mu0[(long long)i * g.N + n] = xi[i] + drho + Lat<Q>::cx[i] * dj[0] +
                                       Lat<Q>::cy[i] * dj[1] + Lat<Q>::cz[i] * dj[2];
     loc[n] = drN;
     loc[g.N + n] = rho;
-    // the carried ||F_n|| feeds the next step's soft site weight
-    const double aFn = aF1 ? aF1[n] * iF : 0.0;
-    lamF[n] = dF[0] + (sF + aFn) * F[0];
-    lamF[g.N + n] = dF[1] + (sF + aFn) * F[1];
-    lamF[2 * g.N + n] = dF[2] + (sF + aFn) * F[2];
+    lamF[n] = lf[0];
+    lamF[g.N + n] = lf[1];
+    lamF[2 * g.N + n] = lf[2];
+}
+
+// Unit relaxation times: the forward's phase field and moments of this step are given; the
+// adjoint of a node is (p0, dj) with mu'_i = p0 + c_i . dj.
+template <int Q, typename S, typename M>
+__global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
+    const M* __restrict__ rhoNf, const MomT<S>* __restrict__ mom, const double* __restrict__ mu1,
+    const double* __restrict__ ab1, const double* __restrict__ aF1, double* __restrict__ mu0,
+    double* __restrict__ loc, double* __restrict__ lamF, Geo g, Phys<double> P) {
+    int x, y, z;
+    long long n;
+    if (!node_xyz(g, x, y, z, n)) return;
+    const Nb nb = wrap(g, x, y, z);
+    const double rho = P.rho_ref + static_cast<double>(static_cast<M>(mom[n]));
+    const double rN = static_cast<double>(rhoNf[n]);
+    const double ir = 1.0 / rho;
+    const double u[3] = {static_cast<double>(static_cast<M>(mom[g.N + n])) * ir,
+                         static_cast<double>(static_cast<M>(mom[2 * g.N + n])) * ir,
+                         static_cast<double>(static_cast<M>(mom[3 * g.N + n])) * ir};
+    double F[3];
+    gradient<Q>(rhoNf, g, nb, x, y, z, F);
+    double drN, drho, dj[3], lf[3];
+    adj_node<Q, true>(
+        P, rho, rN, u, F, aF1[n],
+        [&](int i, double& mus, double& etas) {
+            const long long xn = shifted<Q, 1>(g, nb, x, y, z, i);
+            double m = mu1[xn] + ab1[xn];
+            if (Lat<Q>::cx[i]) m += Lat<Q>::cx[i] * mu1[g.N + xn];
+            if (Lat<Q>::cy[i]) m += Lat<Q>::cy[i] * mu1[2 * g.N + xn];
+            if (Lat<Q>::cz[i]) m += Lat<Q>::cz[i] * mu1[3 * g.N + xn];
+            mus = m;
+            etas = ab1[g.N + xn];
+        },
+        [](int) { return 0.0; }, [](int, double) {}, drN, drho, dj, lf);
+    mu0[n] = drho;
+    mu0[g.N + n] = dj[0];
+    mu0[2 * g.N + n] = dj[1];
+    mu0[3 * g.N + n] = dj[2];
+    loc[n] = drN;
+    loc[g.N + n] = rho;
+    lamF[n] = lf[0];
+    lamF[g.N + n] = lf[1];
+    lamF[2 * g.N + n] = lf[2];
 }
 
 // Transposed gradient stencil, assembly of (a, b), and the sink adjoint.
@@ -212,9 +314,11 @@ __global__ __launch_bounds__(kTPBX) void k_adj_gather(
 #pragma unroll
         for (int i = 1; i < Q; ++i) {  // F(x - c_i) contains 3 W_i c_i rho^N(x)
             const long long m = shifted<Q, -1>(g, nb, x, y, z, i);
-            G += 3.0 * weight<Q>(i) *
-                 (Lat<Q>::cx[i] * lamF[m] + Lat<Q>::cy[i] * lamF[g.N + m] +
-                  Lat<Q>::cz[i] * lamF[2 * g.N + m]);
+            double v = 0.0;
+            if (Lat<Q>::cx[i]) v += Lat<Q>::cx[i] * lamF[m];
+            if (Lat<Q>::cy[i]) v += Lat<Q>::cy[i] * lamF[g.N + m];
+            if (Lat<Q>::cz[i]) v += Lat<Q>::cz[i] * lamF[2 * g.N + m];
+            G += 3.0 * weight<Q>(i) * v;
         }
         const double rho = loc[g.N + n];
         const double rN = static_cast<double>(rhoNf[n]);
@@ -223,11 +327,11 @@ __global__ __launch_bounds__(kTPBX) void k_adj_gather(
         ab0[g.N + n] = b;
         const double dLds = -2.0 * b;
         const double w = site_weight<double>(P, carry, n, 1.0, 0.0);
-        const double phi = node_phi<S, double>(P, phi_field, n);
         const double gphi = dLds * w * P.inv_sbar;
         grad_phi[n] += gphi;
         if (grad_phi_t) grad_phi_t[n] = gphi;
-        if (P.site_rule == 2) {
+        if (P.site_rule == CGE_SITE_SOFT) {
+            const double phi = node_phi<S, double>(P, phi_field, n);
             const double dLdw = dLds * phi * P.inv_sbar;
             const double sp = w * (1.0 - w) * P.inv_kappa;  // dw / d||F_{n-1}||
             aF0[n] = dLdw * sp;
@@ -276,33 +380,48 @@ __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src
 }
 
 template <int Q, typename S, typename M, bool WALLS>
-static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, AdjWork w) {
+static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, AdjWork w, bool unit) {
     if constexpr (WALLS) {
         return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
     } else {
-        hipLaunchKernelGGL((k_adj_seed<Q, S, M>), node_grid(c->g), node_block(c->g), 0, c->stream,
-                           static_cast<const S*>(c->pop[c->cur]), g_rhoN, w.mu[1], w.ab[1],
-                           w.aF[1], c->g, phys<M>(c));
+        const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+        const S* src = static_cast<const S*>(c->pop[c->cur]);
+        if (unit)
+            hipLaunchKernelGGL((k_adj_seed<Q, S, M, 4>), gr, bl, 0, c->stream, src, g_rhoN,
+                               w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
+        else
+            hipLaunchKernelGGL((k_adj_seed<Q, S, M, Q>), gr, bl, 0, c->stream, src, g_rhoN,
+                               w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
         return check(c, hipGetLastError(), "adjoint seed");
     }
 }
 
-// One reverse step on the stored state (pop, carry); adjoint 1 -> 0.
+// One reverse step, adjoint 1 -> 0.  General tau: from the stored state (pop, carry).  Unit
+// tau: from the step's phase field, moments and carry (pop unused).
 template <int Q, typename S, typename M, bool WALLS>
-static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* carry, AdjWork w,
-                             double* grad_phi, double* grad_phi_t) {
+static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, const void* mom,
+                             const void* carry, AdjWork w, double* grad_phi, double* grad_phi_t) {
     if constexpr (WALLS) {
         return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
     } else {
-        const Phys<M> Pm = phys<M>(c);
         const Phys<double> P = phys<double>(c);
         const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-        M* rhoN = static_cast<M*>(c->rhoN);
-        hipLaunchKernelGGL((k_phase_state<Q, S, M>), gr, bl, 0, c->stream,
-                           static_cast<const S*>(pop), carry, c->phi_field, rhoN, c->g, Pm);
-        hipLaunchKernelGGL((k_adj_local<Q, S, M>), gr, bl, 0, c->stream,
-                           static_cast<const S*>(pop), carry, c->phi_field, rhoN, w.mu[1],
-                           w.ab[1], w.aF[1], w.mu[0], w.loc, w.lamF, c->g, P);
+        const M* rhoN;
+        if (pop) {
+            M* r = static_cast<M*>(c->rhoN);
+            hipLaunchKernelGGL((k_phase_state<Q, S, M>), gr, bl, 0, c->stream,
+                               static_cast<const S*>(pop), carry, c->phi_field, r, c->g,
+                               phys<M>(c));
+            hipLaunchKernelGGL((k_adj_local<Q, S, M>), gr, bl, 0, c->stream,
+                               static_cast<const S*>(pop), r, w.mu[1], w.ab[1], w.aF[1], w.mu[0],
+                               w.loc, w.lamF, c->g, P);
+            rhoN = r;
+        } else {
+            rhoN = static_cast<const M*>(rhoN_in);
+            hipLaunchKernelGGL((k_adj_local_unit<Q, S, M>), gr, bl, 0, c->stream, rhoN,
+                               static_cast<const MomT<S>*>(mom), w.mu[1], w.ab[1], w.aF[1],
+                               w.mu[0], w.loc, w.lamF, c->g, P);
+        }
         hipLaunchKernelGGL((k_adj_gather<Q, S, M>), gr, bl, 0, c->stream, carry, c->phi_field,
                            rhoN, w.loc, w.lamF, w.ab[0], w.aF[0], grad_phi, grad_phi_t, w.gpart,
                            c->g, P);
@@ -310,18 +429,18 @@ static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* carry, Adj
     }
 }
 
-cge_status adjoint_seed(cge_ctx* c, const double* g_rhoN, void* work, int parity) {
-    AdjWork w = adj_work(c, work, parity);
-    CGE_DISPATCH(c, seed_impl, c, g_rhoN, w);
+static cge_status adjoint_seed(cge_ctx* c, const double* g_rhoN, void* work, int parity,
+                               bool unit) {
+    AdjWork w = adj_work(c, work, parity, unit ? 4 : c->Q);
+    CGE_DISPATCH(c, seed_impl, c, g_rhoN, w, unit);
 }
 
-cge_status adjoint_rstep(cge_ctx* c, const void* pop, const void* carry, void* work, int parity,
-                         double* grad_phi, double* grad_phi_t) {
-    AdjWork w = adj_work(c, work, parity);
-    CGE_DISPATCH(c, rstep_impl, c, pop, carry, w, grad_phi, grad_phi_t);
+static cge_status adjoint_rstep(cge_ctx* c, const void* pop, const void* rhoN, const void* mom,
+                                const void* carry, void* work, int parity, double* grad_phi,
+                                double* grad_phi_t) {
+    AdjWork w = adj_work(c, work, parity, pop ? c->Q : 4);
+    CGE_DISPATCH(c, rstep_impl, c, pop, rhoN, mom, carry, w, grad_phi, grad_phi_t);
 }
-
-static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace cge
 
@@ -334,14 +453,24 @@ size_t cge_adjoint_bytes(const cge_params* p) {
     return adjoint_bytes(p);
 }
 
+size_t cge_segment_bytes(const cge_params* p, int K) {
+    if (!cge_population_bytes(p) || K < 1) return 0;
+    const size_t slot = unit_tau(p) ? unit_slot(p).bytes : align256(cge_state_bytes(p));
+    return (size_t)K * slot;
+}
+
 cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ckpt) {
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps < 1 || K < 1 || !ckpt) return fail(c, CGE_EINVAL, "nsteps >= 1, K >= 1, ckpt");
+    // at unit tau the backward recomputes with the split step, so the forward uses it too and
+    // the recomputed trajectory is the forward's bit for bit
+    const bool split = unit_tau(&c->p) && !c->flags;
     for (long long n0 = 0, j = 0; n0 < nsteps; n0 += K, ++j) {
         if (!ckpt[j]) return fail(c, CGE_EINVAL, "NULL checkpoint buffer");
         if (cge_status s = cge_save_state(c, ckpt[j])) return s;
-        if (cge_status s = cge_step(c, nsteps - n0 < K ? nsteps - n0 : K)) return s;
+        const long long n = nsteps - n0 < K ? nsteps - n0 : K;
+        if (cge_status s = split ? split_steps(c, n) : cge_step(c, n)) return s;
     }
     return CGE_OK;
 }
@@ -357,9 +486,12 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
     if (c->p.site_rule == CGE_SITE_PHASE_LT)
         return fail(c, CGE_EUNSUPPORTED, "adjoint supports the gradient site rules only");
     const long long N = c->g.N;
-    const size_t sb = align256(cge_state_bytes(&c->p));
+    const bool unit = unit_tau(&c->p);
+    const UnitSlot us = unit_slot(&c->p);
+    const size_t sb = unit ? us.bytes : align256(cge_state_bytes(&c->p));
     // layout of a saved state: populations, then the carried site data at a 256-byte boundary
     const size_t carry_at = align256(cge_population_bytes(&c->p));
+    const size_t cb = carry_bytes(&c->p);
     char* segb = static_cast<char*>(seg);
     // forward bookkeeping is restored after the recomputation
     const long long step0 = c->step;
@@ -376,28 +508,48 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
 
     const dim3 gr = node_grid(c->g);
     const long long nblk = (long long)gr.x * gr.y * gr.z;
-    AdjWork w0 = adj_work(c, work, 0);
+    AdjWork w0 = adj_work(c, work, 0, c->Q);
     if (zero(grad_phi, N, c->stream) != hipSuccess || zero(w0.gpart, nblk, c->stream) != hipSuccess)
         return fail(c, CGE_EDEVICE, "clearing gradients failed");
     // seed from the current state (the state after nsteps)
     int parity = 0;
-    if (cge_status s = adjoint_seed(c, dL_drhoN, work, parity)) return s;
+    if (cge_status s = adjoint_seed(c, dL_drhoN, work, parity, unit)) return s;
     const long long nseg = (nsteps + K - 1) / K;
     for (long long j = nseg - 1; j >= 0; --j) {
         const long long n0 = j * K;
         const long long len = nsteps - n0 < K ? nsteps - n0 : K;
         if (cge_status s = cge_load_state(c, ckpt[j])) return s;
         c->step = step0 - nsteps + n0;  // the recomputed steps draw the same rounding keys
-        for (long long t = 0; t < len; ++t) {  // states n0 .. n0 + len - 1
-            if (cge_status s = cge_save_state(c, segb + t * sb)) return s;
-            if (t + 1 < len)
-                if (cge_status s = cge_step(c, 1)) return s;
+        if (unit) {
+            // split steps keep each step's phase field, moments and incoming site data
+            if (cge_status s = check(c, hipMemcpyAsync(segb + us.carry, c->carry, cb,
+                                                       hipMemcpyDeviceToDevice, c->stream),
+                                     "segment carry"))
+                return s;
+            for (long long t = 0; t < len; ++t) {
+                char* sl = segb + t * sb;
+                void* cout = t + 1 < len ? static_cast<void*>(sl + sb + us.carry)
+                                         : static_cast<void*>(c->carry);
+                if (cge_status s = split_step_into(c, sl + us.carry, cout, sl + us.rhoN,
+                                                   sl + us.mom))
+                    return s;
+            }
+        } else {
+            for (long long t = 0; t < len; ++t) {  // states n0 .. n0 + len - 1
+                if (cge_status s = cge_save_state(c, segb + t * sb)) return s;
+                if (t + 1 < len)
+                    if (cge_status s = cge_step(c, 1)) return s;
+            }
         }
         for (long long t = len - 1; t >= 0; --t) {
             double* gt = grad_phi_t ? grad_phi_t + (n0 + t) * N : nullptr;
-            if (cge_status s = adjoint_rstep(c, segb + t * sb, segb + t * sb + carry_at,
-                                             work, parity, grad_phi, gt))
-                return s;
+            char* sl = segb + t * sb;
+            const cge_status s =
+                unit ? adjoint_rstep(c, nullptr, sl + us.rhoN, sl + us.mom, sl + us.carry, work,
+                                     parity, grad_phi, gt)
+                     : adjoint_rstep(c, sl, nullptr, nullptr, sl + carry_at, work, parity,
+                                     grad_phi, gt);
+            if (s) return s;
             parity = 1 - parity;
         }
     }

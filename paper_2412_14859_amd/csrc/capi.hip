@@ -177,8 +177,8 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
         return CGE_EUNSUPPORTED;
     }
     c->kernel = CGE_KERNEL_TWOPASS;  // resolved at cge_bind
-    const bool need_mom = unit && (params->kernel == CGE_KERNEL_AUTO ||
-                                   params->kernel == CGE_KERNEL_SPLIT);
+    // the moment record also serves the checkpointed forward run of the adjoint at unit tau
+    const bool need_mom = unit;
     const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type
     c->acc_len = twopass_blocks(c);
     if (c->Q == 19 && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
@@ -225,7 +225,7 @@ cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
             break;
         case CGE_KERNEL_SPLIT: c->kernel = CGE_KERNEL_SPLIT; break;
         default:
-            c->kernel = c->mom ? CGE_KERNEL_SPLIT
+            c->kernel = split_supported(c) ? CGE_KERNEL_SPLIT
                                : (fused_supported(c) ? CGE_KERNEL_FUSED : CGE_KERNEL_TWOPASS);
     }
     c->bound = true;
@@ -264,10 +264,6 @@ cge_status cge_get_populations(cge_ctx* c, double* f) {
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (!f) return fail(c, CGE_EINVAL, "f is NULL");
     return get_populations(c, f);
-}
-
-static size_t carry_bytes(const cge_params* p) {
-    return (size_t)p->nx * p->ny * p->nz * (p->site_rule == CGE_SITE_SOFT ? sizeof(double) : 1);
 }
 
 // the carried site data starts at the first 256-byte boundary after the populations

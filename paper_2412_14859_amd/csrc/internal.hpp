@@ -51,6 +51,11 @@ struct cge_ctx {
 
 namespace cge {
 
+// bytes of the carried site data: the mask byte, or ||F|| in FP64 for the soft rule
+inline size_t carry_bytes(const cge_params* p) {
+    return (size_t)p->nx * p->ny * p->nz * (p->site_rule == CGE_SITE_SOFT ? sizeof(double) : 1);
+}
+
 cge_status fail(cge_ctx* c, cge_status s, const std::string& msg);
 cge_status check(cge_ctx* c, hipError_t e, const char* what);
 
@@ -60,6 +65,9 @@ cge_status fused_steps(cge_ctx* c, long long nsteps);
 cge_status split_steps(cge_ctx* c, long long nsteps);
 bool split_supported(const cge_ctx* c);
 size_t split_scratch_bytes(const cge_params* p);
+// one split step with explicit site-data, phase-field and moment buffers
+cge_status split_step_into(cge_ctx* c, const void* carry_in, void* carry_out, void* rhoN,
+                           void* mom);
 bool fused_supported(const cge_ctx* c);
 long long twopass_blocks(const cge_ctx* c);
 long long fused_blocks(const cge_ctx* c);

@@ -172,6 +172,10 @@ __device__ __forceinline__ void carry_store(const Phys<M>& P, void* __restrict__
 
 // Node flux phi(x): the bound field (double next to FP64 populations, float otherwise) or the
 // uniform value.
+// Moment record of the split step (drho, j): FP64 next to FP64 populations, FP32 otherwise.
+template <typename S>
+using MomT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
+
 template <typename S>
 using PhiT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
 

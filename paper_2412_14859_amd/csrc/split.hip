@@ -16,9 +16,6 @@
 
 namespace cge {
 
-template <typename S>
-using MomT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
-
 // Periodic addressing of one block (one x-row segment at fixed y = blockIdx.y, z =
 // blockIdx.z): the y and z parts of every neighbour index are the same for all lanes, so each
 // (slot, row, plane) base is a scalar pointer and only the x offset (3 values per lane) varies.
@@ -55,7 +52,7 @@ __device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
                                                    const uint8_t* __restrict__ flags,
-                                                   const uint8_t* __restrict__ carry,
+                                                   const void* __restrict__ carry,
                                                    const void* __restrict__ phi_field,
                                                    M* __restrict__ rhoN, MomT<S>* __restrict__ mom,
                                                    double* __restrict__ acc_sink,
@@ -113,7 +110,7 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_finish(S* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
-                                                  uint8_t* __restrict__ carry,
+                                                  void* __restrict__ carry,
                                                   const M* __restrict__ rhoN,
                                                   const MomT<S>* __restrict__ mom, Geo g,
                                                   Phys<M> P, uint64_t salt) {
@@ -160,45 +157,58 @@ __global__ __launch_bounds__(kTPBX) void k_finish(S* __restrict__ dst,
                                          st(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
                                             key + (uint64_t)g.N);
                                      });
-    carry[n] = Fn > P.gamma ? 1 : 0;
+    carry_store(P, carry, n, Fn);
 }
 
-bool split_supported(const cge_ctx* c) {
-    return c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0 && c->p.site_rule != CGE_SITE_SOFT;
-}
+bool split_supported(const cge_ctx* c) { return c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0; }
 
 size_t split_scratch_bytes(const cge_params* p) {
     const size_t e = p->precision == CGE_FP64 ? 8 : 4;
     return 4 * e * (size_t)p->nx * p->ny * p->nz;
 }
 
+// One step from the current population buffer with explicit site-data and moment buffers:
+// the sink reads carry_in, the next step's site data goes to carry_out (the same buffer in a
+// plain run), rho^N and the moments to rhoN / mom (kept by the adjoint's recomputation).
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status split_one(cge_ctx* c, const void* carry_in, void* carry_out, void* rhoN_out,
+                            void* mom_out) {
+    const Phys<M> P = phys<M>(c);
+    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+    M* rhoN = static_cast<M*>(rhoN_out);
+    MomT<S>* mom = static_cast<MomT<S>*>(mom_out);
+    const S* src = static_cast<const S*>(c->pop[c->cur]);
+    S* dst = static_cast<S*>(c->pop[1 - c->cur]);
+    const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
+    timing_begin(c);
+    hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
+                       carry_in, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
+    if (WALLS) hipLaunchKernelGGL((k_wet<Q, M>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+    hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
+                       carry_out, rhoN, mom, c->g, P, salt);
+    timing_end(c);
+    if (cge_status s = check(c, hipGetLastError(), "split step launch")) return s;
+    c->cur = 1 - c->cur;
+    c->step += 1;
+    return CGE_OK;
+}
+
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status split_impl(cge_ctx* c, long long nsteps) {
     if (!split_supported(c)) return fail(c, CGE_EUNSUPPORTED, "split step needs tau = 1");
     if (!c->mom) return fail(c, CGE_ESTATE, "moment scratch missing");
-    const Phys<M> P = phys<M>(c);
-    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-    M* rhoN = static_cast<M*>(c->rhoN);
-    MomT<S>* mom = static_cast<MomT<S>*>(c->mom);
-    const uint64_t seedmix = mix64(c->p.seed);
-    for (long long t = 0; t < nsteps; ++t) {
-        const S* src = static_cast<const S*>(c->pop[c->cur]);
-        S* dst = static_cast<S*>(c->pop[1 - c->cur]);
-        const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
-        timing_begin(c);
-        hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
-                           c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
-        if (WALLS) hipLaunchKernelGGL((k_wet<Q, M>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
-        hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
-                           c->carry, rhoN, mom, c->g, P, salt);
-        timing_end(c);
-        if (cge_status s = check(c, hipGetLastError(), "split step launch")) return s;
-        c->cur = 1 - c->cur;
-        c->step += 1;
-    }
+    for (long long t = 0; t < nsteps; ++t)
+        if (cge_status s = split_one<Q, S, M, WALLS>(c, c->carry, c->carry, c->rhoN, c->mom))
+            return s;
     return CGE_OK;
 }
 
 cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_impl, c, nsteps); }
+
+cge_status split_step_into(cge_ctx* c, const void* carry_in, void* carry_out, void* rhoN,
+                           void* mom) {
+    if (!split_supported(c)) return fail(c, CGE_EUNSUPPORTED, "split step needs tau = 1");
+    CGE_DISPATCH(c, split_one, c, carry_in, carry_out, rhoN, mom);
+}
 
 }  // namespace cge

@@ -37,6 +37,8 @@ CASES = {
     "d3q19_soft": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3, site_rule="soft",
                                                 kappa=0.02), 3.3),
     "d3q19_hard": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3), 3.3),
+    # relaxation times other than 1: the reverse step recomputes from stored populations
+    "d3q19_tau": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3, tau=(1.0, 0.8)), 3.3),
 }
 
 
@@ -149,12 +151,16 @@ def _reference_fp32_storage(w, target, nsteps):
     return ph.grad.numpy(), float(g.grad)
 
 
-@pytest.mark.parametrize("name", ["d2q9_soft", "d2q9_soft_ratio"])
-def test_fp32_storage_gradients(name):
-    """FP32 storage: the adjoint of the FP32-storage trajectory equals the reference's on the
-    same rounded trajectory.  Against FP64 the gradients move by what rounding the state
-    moves them (~2e-4 on the equal-density case, in the reference as well), so that
-    comparison only bounds the size."""
+@pytest.mark.parametrize("name,tol", [("d2q9_soft_ratio", 1e-9), ("d2q9_soft", 1e-6)])
+def test_fp32_storage_gradients(name, tol):
+    """FP32 storage: the adjoint of the FP32-storage trajectory against the reference on the
+    trajectory with the populations rounded the same way.  With relaxation times other than
+    1 that is the whole story (tolerance 1e-9).  At unit relaxation times the split step
+    also rounds its moment record (rho, j) to FP32, which the reference does not model; that
+    shifts the trajectory by about 1e-7 (tolerance 1e-6; the FP64 tests pin the arithmetic of
+    this path).  Against FP64 the gradients move by what rounding the state moves them (~2e-4
+    on the equal-density case, in the reference as well), so that comparison bounds the size
+    only."""
     w, target = _setup(name)
     _flush(f"[adjoint fp32s] {name}")
     g32 = _gpu_gradients(w, target, 25, 7, "fp32s")
@@ -164,18 +170,21 @@ def test_fp32_storage_gradients(name):
     g64 = _gpu_gradients(w, target, 25, 7, "fp64")
     e64 = _rel(g32["grad_phi"], g64["grad_phi"])
     _flush(f"  vs rounded reference: grad_phi {e:.2e} grad_gamma {eg:.2e}; vs fp64 {e64:.2e}")
-    assert e < 1e-9 and eg < 1e-9, (e, eg)
+    assert e < tol and eg < tol, (e, eg)
     assert e64 < 5e-3
 
 
-def test_split_forward_recomputation_gives_the_same_gradients():
-    """Hard sites at unit relaxation times: the recomputed forward may run any step form (the
-    forms round differently, so the gradients agree to the reference tolerance)."""
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_checkpointed_run_does_not_depend_on_the_context_step_form(precision):
+    """At unit relaxation times the checkpointed forward and its recomputation use the split
+    step whatever step form the context runs, so the gradients are the same bit for bit."""
     w, target = _setup("d3q19_hard")
-    _flush("[adjoint] d3q19 hard, two-pass vs split forward")
-    a = _gpu_gradients(w, target, 10, 4, kernel="twopass")
-    b = _gpu_gradients(w, target, 10, 4, kernel="split")
-    assert _rel(b["grad_phi"], a["grad_phi"]) < 1e-10
+    _flush(f"[adjoint] d3q19 hard {precision}, two-pass / fused / split contexts")
+    res = [_gpu_gradients(w, target, 10, 4, precision, kernel=k)
+           for k in ("twopass", "fused", "split")]
+    for r in res[1:]:
+        assert np.array_equal(r["grad_phi"], res[0]["grad_phi"])
+        assert r["loss"] == res[0]["loss"]
 
 
 def test_central_differences_on_32x32_soft_sites():
@@ -231,7 +240,7 @@ def test_autograd_function_wrapper():
         loss = ((rn - tgt) ** 2).sum()
         loss.backward()
         ref = A.gradients(w["params"], w["rho_r"], w["rho_b"], w["phi_field"], 25, target)
-        assert abs(float(loss) - ref["loss"]) <= 1e-12 * ref["loss"]
+        assert abs(float(loss.detach()) - ref["loss"]) <= 1e-12 * ref["loss"]
         assert _rel(phi.grad.cpu().numpy(), ref["grad_phi"].numpy()) < 1e-10
         assert abs(float(gamma.grad) - ref["grad_gamma"]) <= 1e-10 * abs(ref["grad_gamma"])
     sim.close()

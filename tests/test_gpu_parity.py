@@ -35,9 +35,7 @@ CASES = {
 # single-pass step D3Q19 without solid nodes, the split step unit relaxation times
 def _kernels(wl, over):
     ks = ["twopass"]
-    if over.get("site_rule") == "soft":
-        return ks
-    if wl == "sphere3d":
+    if wl == "sphere3d" and over.get("site_rule") != "soft":
         ks.append("fused")
     tau = over.get("tau", (1.0, 1.0) if wl != "sessile3d" else (1.0, 0.6))
     if tuple(tau) == (1.0, 1.0):
