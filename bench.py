@@ -104,6 +104,50 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
     return res
 
 
+def adjoint_leg(n, steps, K, precision="fp32s"):
+    """Adjoint-to-forward cost on the D2Q9 n^2 drop with a seeded flux field (soft sites):
+    the checkpointed forward (checkpoint writes included) against the backward (segment
+    recomputation + reverse steps), both timed on the device, same grid and steps."""
+    import torch
+    from paper_2412_14859_amd import cgevap, inputs
+    w = inputs.workload("adjoint2d", shape=(1, n, n))
+    p = dict(w["params"], site_rule="soft", kappa=w["kappa"])
+    sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], phi_field=w["phi_field"],
+                            precision=precision)
+    start = sim.save_state().clone()
+    target = torch.as_tensor(w["target"], device=sim.device)
+
+    def once(nsteps):
+        sim.load_state(start)
+        sim.set_counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ck = sim.forward_ckpt(nsteps, K)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = 2.0 * (sim.fields()["rhoN"] - target)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = sim.backward(ck, nsteps, K, g)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return t1 - t0, t3 - t2, r
+
+    once(min(steps, 2 * K))  # warm-up: allocations and code paths
+    tf, tb, r = once(steps)
+    kname = sim.kernel_name()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": f"D2Q9 {n}^2 drop R={96 * n // 512}, seeded flux field, soft sites "
+                        f"(kappa={w['kappa']}), {precision}",
+            "steps": steps, "K": K, "forward_ms": round(tf * 1e3, 2),
+            "backward_ms": round(tb * 1e3, 2), "ratio": round(tb / tf, 3),
+            "forward_mlups": round(n * n * steps / tf / 1e6, 1),
+            "forward_kernel": kname,
+            "grad_gamma": r["grad_gamma"]}
+
+
 def copy_probe_gbs(nbytes=1 << 30, reps=5):
     """Achievable HBM bandwidth: the library's streaming copy kernel over nbytes, timed with
     events on torch's current stream (the stream the probe is launched on); read + write."""
@@ -155,6 +199,9 @@ def main():
     ap.add_argument("--size", type=int, default=256, help="edge of the cubic box")
     ap.add_argument("--no-legs", action="store_true", help="skip the FP64 and FP16S legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost legs")
+    ap.add_argument("--adjoint-only", type=int, default=0, metavar="N",
+                    help="print only the adjoint cost leg on the D2Q9 N^2 drop (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -164,6 +211,12 @@ def main():
     import torch
     from paper_2412_14859_amd import inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.adjoint_only:
+        copy_gbs, _ = copy_probe_gbs()  # also the counter calibration kernel of a profile
+        leg = adjoint_leg(args.adjoint_only, args.steps, 100)
+        leg["copy_probe_gbs"] = round(copy_gbs, 1)
+        print(json.dumps(leg), flush=True)
+        return
     n = args.size
     w = inputs.workload("sphere3d", shape=(n, n, n), radius=64.0 * n / 256)
     copy_gbs, copy_ms = copy_probe_gbs()
@@ -179,7 +232,7 @@ def main():
     tb = stored_traffic(main_leg["kernel"], n, args.precision)
     traffic = None if tb is None else round(tb / (step_ms * 1e-3) / 1e9, 1)
     out = {
-        "metric": "MLUPS (D3Q19 CG + reaction-limited evaporation step)",
+        "metric": "MLUPS + % HBM roofline, D3Q19 CG+evap FP32 vs FP64; adjoint/forward time",
         "value": round(main_leg["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -209,6 +262,9 @@ def main():
         "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                  for k, v in legs.items()},
     }
+    if not args.no_adjoint:
+        out["adjoint"] = {"512": adjoint_leg(512, 2000, 100),
+                          "2048": adjoint_leg(2048, 400, 100)}
     if not args.no_cpu:
         cb = cpu_baseline()
         out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v)

@@ -105,7 +105,8 @@ __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
     const double gr = g_rhoN[n];
 #pragma unroll
     for (int i = 0; i < NMU; ++i) mu[(long long)i * g.N + n] = 0.0;
-    ab[n] = -gr * rN / rho;
+    if (NMU == 4) mu[n] = -gr * rN / rho;  // unit layout: q0 = p0 + a
+    else ab[n] = -gr * rN / rho;
     ab[g.N + n] = gr / rho;
     aF[n] = 0.0;
 }
@@ -255,7 +256,8 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
 }
 
 // Unit relaxation times: the forward's phase field and moments of this step are given; the
-// adjoint of a node is (p0, dj) with mu'_i = p0 + c_i . dj.
+// adjoint of a node is (q0, dj, b) with dL/dft_i = q0 + c_i . dj (q0 = p0 + a) and dL/ddd_i = b.
+// One block is one x-row segment, so the neighbours' row and plane offsets are uniform.
 template <int Q, typename S, typename M>
 __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     const M* __restrict__ rhoNf, const MomT<S>* __restrict__ mom, const double* __restrict__ mu1,
@@ -263,22 +265,35 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     double* __restrict__ loc, double* __restrict__ lamF, Geo g, Phys<double> P) {
     int x, y, z;
     long long n;
-    if (!node_xyz(g, x, y, z, n)) return;
-    const Nb nb = wrap(g, x, y, z);
+    const bool valid = node_xyz(g, x, y, z, n);
+    const RowOff r = row_offsets<char>(g, x < g.nx ? x : 0);  // element offsets
+    if (!valid) return;
     const double rho = P.rho_ref + static_cast<double>(static_cast<M>(mom[n]));
     const double rN = static_cast<double>(rhoNf[n]);
     const double ir = 1.0 / rho;
     const double u[3] = {static_cast<double>(static_cast<M>(mom[g.N + n])) * ir,
                          static_cast<double>(static_cast<M>(mom[2 * g.N + n])) * ir,
                          static_cast<double>(static_cast<M>(mom[3 * g.N + n])) * ir};
-    double F[3];
-    gradient<Q>(rhoNf, g, nb, x, y, z, F);
+    double F[3] = {0.0, 0.0, 0.0};  // F = 3 sum_i W_i rho^N(x + c_i) c_i
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const long long m = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]] +
+                            r.xo[1 + Lat<Q>::cx[i]];
+        const double v = weight<Q>(i) * static_cast<double>(rhoNf[m]);
+        if (Lat<Q>::cx[i]) F[0] += Lat<Q>::cx[i] * v;
+        if (Lat<Q>::cy[i]) F[1] += Lat<Q>::cy[i] * v;
+        if (Lat<Q>::cz[i]) F[2] += Lat<Q>::cz[i] * v;
+    }
+    F[0] *= 3.0;
+    F[1] *= 3.0;
+    F[2] *= 3.0;
     double drN, drho, dj[3], lf[3];
     adj_node<Q, true>(
         P, rho, rN, u, F, aF1[n],
         [&](int i, double& mus, double& etas) {
-            const long long xn = shifted<Q, 1>(g, nb, x, y, z, i);
-            double m = mu1[xn] + ab1[xn];
+            const long long xn = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]] +
+                                 r.xo[1 + Lat<Q>::cx[i]];
+            double m = mu1[xn];
             if (Lat<Q>::cx[i]) m += Lat<Q>::cx[i] * mu1[g.N + xn];
             if (Lat<Q>::cy[i]) m += Lat<Q>::cy[i] * mu1[2 * g.N + xn];
             if (Lat<Q>::cz[i]) m += Lat<Q>::cz[i] * mu1[3 * g.N + xn];
@@ -289,31 +304,34 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     mu0[n] = drho;
     mu0[g.N + n] = dj[0];
     mu0[2 * g.N + n] = dj[1];
-    mu0[3 * g.N + n] = dj[2];
+    if (Lat<Q>::D == 3) mu0[3 * g.N + n] = dj[2];
     loc[n] = drN;
     loc[g.N + n] = rho;
     lamF[n] = lf[0];
     lamF[g.N + n] = lf[1];
-    lamF[2 * g.N + n] = lf[2];
+    if (Lat<Q>::D == 3) lamF[2 * g.N + n] = lf[2];
 }
 
 // Transposed gradient stencil, assembly of (a, b), and the sink adjoint.
-template <int Q, typename S, typename M>
+// At unit tau the result a is folded into q0 = p0 + a (mu0, written by the local kernel).
+template <int Q, typename S, typename M, bool UNIT>
 __global__ __launch_bounds__(kTPBX) void k_adj_gather(
     const void* __restrict__ carry, const void* __restrict__ phi_field,
     const M* __restrict__ rhoNf, const double* __restrict__ loc, const double* __restrict__ lamF,
-    double* __restrict__ ab0, double* __restrict__ aF0, double* __restrict__ grad_phi,
-    double* __restrict__ grad_phi_t, double* __restrict__ gpart, Geo g, Phys<double> P) {
+    double* __restrict__ q0, double* __restrict__ ab0, double* __restrict__ aF0,
+    double* __restrict__ grad_phi, double* __restrict__ grad_phi_t, double* __restrict__ gpart,
+    Geo g, Phys<double> P) {
     int x, y, z;
     long long n;
     const bool valid = node_xyz(g, x, y, z, n);
+    const RowOff r = row_offsets<char>(g, x < g.nx ? x : 0);  // element offsets
     double gg = 0.0;
     if (valid) {
-        const Nb nb = wrap(g, x, y, z);
         double G = loc[n];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {  // F(x - c_i) contains 3 W_i c_i rho^N(x)
-            const long long m = shifted<Q, -1>(g, nb, x, y, z, i);
+            const long long m = r.yrow[1 - Lat<Q>::cy[i]] + r.zpl[1 - Lat<Q>::cz[i]] +
+                                r.xo[1 - Lat<Q>::cx[i]];
             double v = 0.0;
             if (Lat<Q>::cx[i]) v += Lat<Q>::cx[i] * lamF[m];
             if (Lat<Q>::cy[i]) v += Lat<Q>::cy[i] * lamF[g.N + m];
@@ -323,7 +341,8 @@ __global__ __launch_bounds__(kTPBX) void k_adj_gather(
         const double rho = loc[g.N + n];
         const double rN = static_cast<double>(rhoNf[n]);
         const double b = G / rho;
-        ab0[n] = -G * rN / rho;
+        if constexpr (UNIT) q0[n] += -G * rN / rho;
+        else ab0[n] = -G * rN / rho;
         ab0[g.N + n] = b;
         const double dLds = -2.0 * b;
         const double w = site_weight<double>(P, carry, n, 1.0, 0.0);
@@ -422,9 +441,14 @@ static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, c
                                static_cast<const MomT<S>*>(mom), w.mu[1], w.ab[1], w.aF[1],
                                w.mu[0], w.loc, w.lamF, c->g, P);
         }
-        hipLaunchKernelGGL((k_adj_gather<Q, S, M>), gr, bl, 0, c->stream, carry, c->phi_field,
-                           rhoN, w.loc, w.lamF, w.ab[0], w.aF[0], grad_phi, grad_phi_t, w.gpart,
-                           c->g, P);
+        if (pop)
+            hipLaunchKernelGGL((k_adj_gather<Q, S, M, false>), gr, bl, 0, c->stream, carry,
+                               c->phi_field, rhoN, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
+                               grad_phi, grad_phi_t, w.gpart, c->g, P);
+        else
+            hipLaunchKernelGGL((k_adj_gather<Q, S, M, true>), gr, bl, 0, c->stream, carry,
+                               c->phi_field, rhoN, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
+                               grad_phi, grad_phi_t, w.gpart, c->g, P);
         return check(c, hipGetLastError(), "adjoint step");
     }
 }

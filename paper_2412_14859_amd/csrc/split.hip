@@ -16,38 +16,6 @@
 
 namespace cge {
 
-// Periodic addressing of one block (one x-row segment at fixed y = blockIdx.y, z =
-// blockIdx.z): the y and z parts of every neighbour index are the same for all lanes, so each
-// (slot, row, plane) base is a scalar pointer and only the x offset (3 values per lane) varies.
-struct RowOff {
-    long long yrow[3], zpl[3];  // element offsets of rows y-1, y, y+1 and planes z-1, z, z+1
-    uint32_t xo[3];             // byte offsets of x-1, x, x+1 (times the element size)
-};
-
-__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-
-// Call at kernel entry, before any lane-dependent branch.
-template <typename T>
-__device__ __forceinline__ RowOff row_offsets(const Geo& g, int x) {
-    RowOff r;
-    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        // readfirstlane keeps the uniform offsets in scalar registers (they fit in 31 bits)
-        const int yo = __builtin_amdgcn_readfirstlane(wrapc(y - 1 + d, g.ny) * g.nx);
-        const int zo = __builtin_amdgcn_readfirstlane(wrapc(z - 1 + d, g.nz));
-        r.yrow[d] = yo;
-        r.zpl[d] = (long long)zo * ((long long)g.nx * g.ny);
-        r.xo[d] = (uint32_t)wrapc(x - 1 + d, g.nx) * (uint32_t)sizeof(T);
-    }
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
 // Pass 1: pull, sink, moments; FP64 sink bookkeeping per block.
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
