@@ -225,7 +225,12 @@ def main():
     if not args.no_legs:
         for prec in ("fp64", "fp16s"):
             if prec != args.precision:
-                legs[prec] = run_leg(w, prec, max(args.steps // 2, 10), args.warmup, args.kernel)
+                legs[prec] = run_leg(w, prec, args.steps, args.warmup, args.kernel)
+        # drop volume after the same steps, against the FP64 run
+        legs[args.precision] = dict(main_leg)
+        v64 = legs["fp64"]["v_mass"]
+        for leg in legs.values():
+            leg["v_mass_rel_vs_fp64"] = (leg["v_mass"] - v64) / v64
     N = n ** 3
     achieved = main_leg["achieved_gbs"]
     step_ms = main_leg["kernel_ms_per_step"]
@@ -259,8 +264,8 @@ def main():
                      "bytes_per_node": main_leg["bytes_per_node"],
                      "copy_probe_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
-        "legs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                 for k, v in legs.items()},
+        "legs": {k: {kk: (float(f"{vv:.9g}") if isinstance(vv, float) else vv)
+                     for kk, vv in v.items()} for k, v in legs.items()},
     }
     if not args.no_adjoint:
         out["adjoint"] = {"512": adjoint_leg(512, 2000, 100),

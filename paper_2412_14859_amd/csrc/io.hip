@@ -6,13 +6,24 @@
 
 namespace cge {
 
+// Rounding of an imported FP64 value to the storage type.  Half storage rounds
+// stochastically, as the step does: a uniform initial state rounded to nearest would give every
+// bulk node the same rounding error, which adds up to a mass offset over the domain.
+template <typename S>
+__device__ __forceinline__ S enc_import(double v, uint64_t key) {
+    if constexpr (std::is_same<S, _Float16>::value)
+        return enc<_Float16, float>(static_cast<float>(v), key);
+    else
+        return static_cast<S>(v);
+}
+
 // Store the post-streaming pair (fr, fb) of direction i at node n into the slot the next
 // pull reads it from: (i, n - c_i), or (opp(i), n) when n - c_i is solid.
 template <int Q, typename S, bool WALLS>
 __device__ __forceinline__ void store_prestream(S* __restrict__ dst, const uint8_t* __restrict__ flags,
                                                 const Geo& g, const Nb& b, int x, int y, int z,
                                                 long long n, int i, double fr, double fb,
-                                                double rho_ref, double alpha_ref) {
+                                                double rho_ref, double alpha_ref, uint64_t salt) {
     long long sn = shifted<Q, -1>(g, b, x, y, z, i);
     int di = i;
     if (WALLS && i != 0 && flags[sn]) {
@@ -22,8 +33,9 @@ __device__ __forceinline__ void store_prestream(S* __restrict__ dst, const uint8
     // the shift and encoding depend on the direction the value is stored under; the
     // bounce-back pair (i, opp(i)) shares the same rest weight, so either index gives it
     const double tref = rho_ref * (restA<Q>(i) + restB<Q>(i) * alpha_ref);
-    dst[(long long)di * g.N + sn] = static_cast<S>(fr + fb - tref);
-    dst[(long long)(Q + di) * g.N + sn] = static_cast<S>(fr - fb);
+    const uint64_t key = salt + (uint64_t)(2 * di) * (uint64_t)g.N + (uint64_t)sn;
+    dst[(long long)di * g.N + sn] = enc_import<S>(fr + fb - tref, key);
+    dst[(long long)(Q + di) * g.N + sn] = enc_import<S>(fr - fb, key + (uint64_t)g.N);
 }
 
 template <int Q, typename S, bool WALLS>
@@ -31,7 +43,7 @@ __global__ __launch_bounds__(kTPBX) void k_init(S* __restrict__ dst, const uint8
                                                 const double* __restrict__ rr,
                                                 const double* __restrict__ rb,
                                                 const double* __restrict__ u, Geo g,
-                                                Phys<double> P) {
+                                                Phys<double> P, uint64_t salt) {
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
@@ -48,14 +60,14 @@ __global__ __launch_bounds__(kTPBX) void k_init(S* __restrict__ dst, const uint8
         const double fr = rr[n] * (restA<Q>(i) + restB<Q>(i) * P.alpha_r + vel);
         const double fb = rb[n] * (restA<Q>(i) + restB<Q>(i) * P.alpha_b + vel);
         store_prestream<Q, S, WALLS>(dst, flags, g, b, x, y, z, n, i, fr, fb, P.rho_ref,
-                                     P.alpha_ref);
+                                     P.alpha_ref, salt);
     }
 }
 
 template <int Q, typename S, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_import(S* __restrict__ dst, const uint8_t* __restrict__ flags,
                                                   const double* __restrict__ f, Geo g,
-                                                  Phys<double> P) {
+                                                  Phys<double> P, uint64_t salt) {
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
@@ -64,7 +76,8 @@ __global__ __launch_bounds__(kTPBX) void k_import(S* __restrict__ dst, const uin
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         store_prestream<Q, S, WALLS>(dst, flags, g, b, x, y, z, n, i, f[(long long)i * g.N + n],
-                                     f[(long long)(Q + i) * g.N + n], P.rho_ref, P.alpha_ref);
+                                     f[(long long)(Q + i) * g.N + n], P.rho_ref, P.alpha_ref,
+                                     salt);
 }
 
 template <int Q, typename S, bool WALLS>
@@ -122,10 +135,16 @@ __global__ __launch_bounds__(kTPBX) void k_fields(const S* __restrict__ src,
     if (rhoN) rhoN[n] = rho > 0.0 ? (r - bl) / rho : 0.0;
 }
 
+// rounding keys of imported states: a stream of their own, apart from the steps' keys
+static uint64_t import_salt(const cge_ctx* c) {
+    return mix64(mix64(c->p.seed) ^ 0x9E3779B97F4A7C15ull) * 0x100000001B3ull;
+}
+
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status init_impl(cge_ctx* c, const double* rr, const double* rb, const double* u) {
     hipLaunchKernelGGL((k_init<Q, S, WALLS>), node_grid(c->g), node_block(c->g), 0, c->stream,
-                       static_cast<S*>(c->pop[c->cur]), c->flags, rr, rb, u, c->g, phys<double>(c));
+                       static_cast<S*>(c->pop[c->cur]), c->flags, rr, rb, u, c->g, phys<double>(c),
+                       import_salt(c));
     return check(c, hipGetLastError(), "init kernel");
 }
 cge_status init_equilibrium(cge_ctx* c, const double* rr, const double* rb, const double* u) {
@@ -135,7 +154,8 @@ cge_status init_equilibrium(cge_ctx* c, const double* rr, const double* rb, cons
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status import_impl(cge_ctx* c, const double* f) {
     hipLaunchKernelGGL((k_import<Q, S, WALLS>), node_grid(c->g), node_block(c->g), 0, c->stream,
-                       static_cast<S*>(c->pop[c->cur]), c->flags, f, c->g, phys<double>(c));
+                       static_cast<S*>(c->pop[c->cur]), c->flags, f, c->g, phys<double>(c),
+                       import_salt(c));
     return check(c, hipGetLastError(), "import kernel");
 }
 cge_status set_populations(cge_ctx* c, const double* f) { CGE_DISPATCH(c, import_impl, c, f); }

@@ -191,6 +191,31 @@ def test_fp32_drop2d_volume_and_frozen_error():
     sim.close()
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32s", 1e-5), ("fp16s", 1e-3)])
+def test_drop3d_volume_against_the_fp64_oracle(precision, tol):
+    """D3Q19 sphere (32^3, R = 8, phi = 1e-3 so that the drop loses ~10 % of its volume in
+    300 steps): free-run drop volume M_r / rho_r^in against the FP64 oracle.  FP16 storage
+    rounds stochastically, also when the initial state is stored (rounding a uniform bulk to
+    nearest would shift the volume by a fixed amount per bulk node)."""
+    w = case("sphere3d", (32, 32, 32), radius=8.0, phi=1e-3)
+    _flush(f"[volume {precision}] d3q19 32^3 300 steps")
+    ora = oracle_for(w)
+    sim = gpu_for(w, precision)
+    v0 = ora.observables()["v_mass"]
+    e0 = abs(sim.observables()["v_mass"] - v0) / v0
+    worst = e0
+    for n in (100, 100, 100):
+        sim.step(n)
+        ora.step(n)
+        vo = ora.observables()["v_mass"]
+        worst = max(worst, abs(sim.observables()["v_mass"] - vo) / vo)
+    loss = (v0 - vo) / v0
+    _flush(f"  initial volume rel. error {e0:.3e}, worst {worst:.3e}, volume lost {loss:.3e}")
+    assert loss > 0.01
+    assert worst < tol
+    sim.close()
+
+
 def test_determinism_and_resume_bitwise():
     import torch
     w = case("sphere3d", (12, 16, 70), radius=5.0, phi=1e-3)
