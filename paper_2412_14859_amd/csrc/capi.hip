@@ -105,9 +105,11 @@ static hipError_t zero_words(void* p, long long n, hipStream_t s) {
 
 cge_status copy_probe(void* dst, const void* src, size_t nbytes, hipStream_t s) {
     const long long n16 = (long long)(nbytes / 16);
+    // four 16-byte elements per thread: the fastest of the grid sizes measured for 1 GiB
+    const long long blocks = (n16 + 1023) / 1024;
     if (n16 > 0)
-        hipLaunchKernelGGL(k_copy, dim3(8192), dim3(256), 0, s, static_cast<const uint4*>(src),
-                           static_cast<uint4*>(dst), n16);
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
+                           0, s, static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
     return hipGetLastError() == hipSuccess ? CGE_OK : CGE_EDEVICE;
 }
 

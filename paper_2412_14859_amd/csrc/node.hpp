@@ -63,6 +63,11 @@ template <typename S, typename M>
 __device__ __forceinline__ void st(S* p, M v, uint64_t key) {
     *p = enc<S, M>(v, key);
 }
+// The same with a streaming (non-temporal) hint: the value is not read again in this step.
+template <typename S, typename M>
+__device__ __forceinline__ void st_nt(S* p, M v, uint64_t key) {
+    __builtin_nontemporal_store(enc<S, M>(v, key), p);
+}
 
 // neighbour coordinates with periodic wrap
 struct Nb {

@@ -121,9 +121,9 @@ __global__ __launch_bounds__(kTPBX) void k_finish(S* __restrict__ dst,
                                                               (uint64_t)n;
                                          S* pa = dst + (long long)i * g.N + row;
                                          S* pd = dst + (long long)(Q + i) * g.N + row;
-                                         st(reinterpret_cast<S*>(reinterpret_cast<char*>(pa) + xb), a, key);
-                                         st(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
-                                            key + (uint64_t)g.N);
+                                         st_nt(reinterpret_cast<S*>(reinterpret_cast<char*>(pa) + xb), a, key);
+                                         st_nt(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
+                                               key + (uint64_t)g.N);
                                      });
     carry_store(P, carry, n, Fn);
 }

@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
                                 [&](int i, M a, M d) {
                                     const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N +
                                                          (uint64_t)n;
-                                    st(dst + (long long)i * g.N + n, a, key);
-                                    st(dst + (long long)(Q + i) * g.N + n, d, key + (uint64_t)g.N);
+                                    st_nt(dst + (long long)i * g.N + n, a, key);
+                                    st_nt(dst + (long long)(Q + i) * g.N + n, d, key + (uint64_t)g.N);
                                 });
         carry_store<M>(P, carry, n, Fn);
     }
