@@ -44,10 +44,22 @@ __device__ __forceinline__ _Float16 sr_half(float v, uint32_t r) {
     const float of = static_cast<float>(o);
     const float lo = h_is_hi ? fabsf(of) : fabsf(b);
     const float hi = h_is_hi ? fabsf(b) : fabsf(of);
-    const float p = (fabsf(v) - lo) / (hi - lo);
+    // up with probability (|v| - lo) / (hi - lo), compared without the division
     const float u = static_cast<float>(r >> 8) * 5.9604644775390625e-8f;  // 2^-24
-    const bool up = u < p;
+    const bool up = u * (hi - lo) < fabsf(v) - lo;
     return up == h_is_hi ? h : o;
+}
+
+// 32-bit finaliser of MurmurHash3 (Appleby): a bijection with full avalanche, used to turn a
+// rounding key into random bits.  Within one step the keys of all stored values differ in
+// their low 32 bits while 2 Q N < 2^32 (above that, values far apart share random bits, which
+// leaves each rounding unbiased), and the per-step salt randomises those bits.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    return h ^ (h >> 16);
 }
 
 // rounding to the storage type: nearest for double/float, stochastic for half
@@ -57,7 +69,7 @@ __device__ __forceinline__ S enc(M v, uint64_t key) {
 }
 template <>
 __device__ __forceinline__ _Float16 enc<_Float16, float>(float v, uint64_t key) {
-    return sr_half(v, static_cast<uint32_t>(mix64(key) >> 32));
+    return sr_half(v, fmix32(static_cast<uint32_t>(key)));
 }
 template <typename S, typename M>
 __device__ __forceinline__ void st(S* p, M v, uint64_t key) {
