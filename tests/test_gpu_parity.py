@@ -216,6 +216,28 @@ def test_drop3d_volume_against_the_fp64_oracle(precision, tol):
     sim.close()
 
 
+@pytest.mark.parametrize("precision,bad", [("fp64", float("nan")), ("fp32s", float("inf"))])
+def test_non_finite_state_is_reported(precision, bad):
+    """A non-finite population loaded into the state makes cge_observables return
+    CGE_ENUMERIC; stepping such a state is still an ordinary launch."""
+    from paper_2412_14859_amd import cgevap
+    w = case("drop2d", (1, 20, 70), radius=5.0, phi=1e-3)
+    _flush(f"[non-finite] drop2d 20x70 {precision}")
+    sim = gpu_for(w, precision)
+    assert sim.observables()["mass_r"] > 0
+    f = sim.populations()
+    f[0, 3, 0, 7, 11] = bad
+    sim.set_populations(f)
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.observables()
+    assert e.value.status == cgevap.ENUMERIC
+    sim.step(2)
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.observables()
+    assert e.value.status == cgevap.ENUMERIC
+    sim.close()
+
+
 def test_determinism_and_resume_bitwise():
     import torch
     w = case("sphere3d", (12, 16, 70), radius=5.0, phi=1e-3)
