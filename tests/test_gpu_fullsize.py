@@ -1,0 +1,136 @@
+"""Parity at the full workload sizes, in the step form the benchmark times (the automatic
+choice), on sampled nodes.
+
+One node's post-collision values depend only on its own pre-sink state and site data and on
+rho^N at its neighbours (whose values depend only on their own state; with walls, a solid
+neighbour takes the wetting mean over its own fluid neighbours).  So the FP64 oracle run for
+one step on a small periodic box cut out around the node (3 nodes wide, 5 with walls) from the
+GPU's exported state computes the node's outputs exactly.  They are compared with the GPU's
+step on the whole domain: FP64 within 1e-12, FP32 storage within 1e-6 (one rounding of the
+stored value) and FP16 storage within 5e-3, relative to t_i(alpha_k) rho_k^in."""
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, tables
+from tests.helpers import case, gpu_for, pop_scale
+
+pytestmark = [pytest.mark.gpu]
+
+CASES = {
+    # name: (workload, overrides, precision, tolerance)
+    "sphere3d_256_fp32s": ("sphere3d", {}, "fp32s", 1e-6),
+    "sphere3d_256_fp64": ("sphere3d", {}, "fp64", 1e-12),
+    "sphere3d_256_fp16s": ("sphere3d", {}, "fp16s", 5e-3),
+    "flat2d_1024_fp64": ("flat2d", {}, "fp64", 1e-12),
+    "flat2d_1024_fp32s": ("flat2d", {}, "fp32s", 1e-6),
+    "ellipse2d_1024_fp32s": ("ellipse2d", {}, "fp32s", 1e-6),
+    "sessile3d_fp32s": ("sessile3d", {}, "fp32s", 1e-6),
+    "adjoint2d_512_soft_fp32s": ("adjoint2d", {"site_rule": "soft", "kappa": 0.01}, "fp32s", 1e-6),
+    "drop2d_128_phase_fp64": ("drop2d", {}, "fp64", 1e-12),
+}
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _samples(carry, solid, rng, k=24):
+    """Seeded nodes: half at sites (or largest soft weights), half anywhere in the fluid."""
+    fluid = np.ones(carry.shape, bool) if solid is None else solid == 0
+    if carry.dtype == np.uint8:
+        hot = np.argwhere((carry > 0) & fluid)
+    else:  # soft rule: carried ||F||, take the interface
+        hot = np.argwhere((carry > 0.05) & fluid)
+    anyw = np.argwhere(fluid)
+    pick = [] if len(hot) == 0 else \
+        [hot[i] for i in rng.choice(len(hot), size=min(k // 2, len(hot)), replace=False)]
+    pick += [anyw[i] for i in rng.choice(len(anyw), size=k - len(pick), replace=False)]
+    return [tuple(int(v) for v in p) for p in pick]
+
+
+def _box(shape, node, h, D):
+    """Periodic index vectors of the box of half-width h around node (z, y, x)."""
+    out = []
+    for a, (n, c) in enumerate(zip(shape, node)):
+        if D == 2 and a == 0:
+            out.append(np.array([c]))
+        else:
+            out.append(np.arange(c - h, c + h + 1) % n)
+    return out
+
+
+def _center_outputs(f, centre, solid_box, c, opp):
+    """Post-collision values computed at the box centre, read from a post-step state:
+    direction i went to centre + c_i, or bounced back into the centre as opp(i)."""
+    Q = c.shape[0]
+    cz, cy, cx = centre
+    out = np.empty((2, Q))
+    for i in range(Q):
+        z, y, x = cz + c[i, 2], cy + c[i, 1], cx + c[i, 0]
+        if solid_box is not None and solid_box[z, y, x]:
+            out[:, i] = f[:, opp[i], cz, cy, cx]
+        else:
+            out[:, i] = f[:, i, z, y, x]
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sampled_nodes_match_the_oracle_at_full_size(name):
+    import torch
+    wl, over, precision, tol = CASES[name]
+    w = case(wl, None, **over)
+    p = w["params"]
+    Q = int(p["Q"])
+    D = 2 if Q == 9 else 3
+    t = tables(Q)
+    c, opp = np.asarray(t["c"]), np.asarray(t["opp"])
+    scale = pop_scale(Q, p["rho_in"])
+    walls = w["solid"] is not None
+    h = 2 if walls else 1
+    _flush(f"[full size] {name} shape={p['shape']} {precision}")
+    sim = gpu_for(w, precision)
+    kernel = sim.kernel_name()
+    sim.step(10)
+    rng = np.random.default_rng(2412)
+    carry = sim.carry.cpu().numpy()
+    nodes = _samples(carry, w["solid"], rng)
+    f0 = sim.populations()
+    boxes = []
+    for node in nodes:
+        iz, iy, ix = _box(p["shape"], node, h, D)
+        tz, ty, tx = (torch.as_tensor(v, device=f0.device) for v in (iz, iy, ix))
+        fb = f0[:, :, tz[:, None, None], ty[None, :, None], tx[None, None, :]].cpu().numpy()
+        sel = np.ix_(iz, iy, ix)
+        boxes.append((node, fb, carry[sel], None if not walls else w["solid"][sel],
+                      None if w["phi_field"] is None else w["phi_field"][sel]))
+    del f0
+    sim.step(1)
+    f1 = sim.populations()
+    worst = 0.0
+    for node, fb, cb, sb, phib in boxes:
+        bp = dict(p, shape=fb.shape[2:])
+        ora = Oracle(bp, solid=sb, phi_field=phib)
+        ora.set_populations(fb)
+        if p.get("site_rule", "grad") == "soft":
+            ora.set_fmag(cb)
+            ora.step(1)
+        elif p.get("site_rule", "grad") == "grad":
+            ora.step(1, masks=cb[None].astype(np.uint8))
+        else:  # |rho^N| < Gamma uses the current state, which the box holds
+            ora.step(1)
+        centre = tuple(v // 2 for v in fb.shape[2:])
+        if D == 2:
+            centre = (0,) + centre[1:]
+        want = _center_outputs(ora.populations(), centre, sb, c, opp)
+        # the same entries of the GPU's post-step state
+        iz, iy, ix = _box(p["shape"], node, h, D)
+        tz, ty, tx = (torch.as_tensor(v, device=f1.device) for v in (iz, iy, ix))
+        gb = f1[:, :, tz[:, None, None], ty[None, :, None], tx[None, None, :]].cpu().numpy()
+        got = _center_outputs(gb, centre, sb, c, opp)
+        e = float(np.max(np.abs(got - want) / scale))
+        worst = max(worst, e)
+        assert e < tol, (name, node, e)
+    _flush(f"  {kernel}: {len(boxes)} nodes, worst e_pop {worst:.3e}")
+    sim.close()
+    del sim, f1
+    torch.cuda.empty_cache()
