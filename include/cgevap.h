@@ -163,33 +163,37 @@ cge_status cge_load_state(cge_ctx* ctx, const void* src);
 
 /* Adjoint (reverse mode) of nsteps steps, for domains without solid nodes and the site rules
  * GRAD_GT (sites held at those of the forward run) and SOFT.  The loss is given through its
- * derivative with respect to the final phase field rho^N_T (e.g. 2 (rho^N_T - target) for a
- * squared mismatch), and the gradients with respect to the flux field phi(x) and the site
+ * derivatives with respect to the final phase field rho^N_T (e.g. 2 (rho^N_T - target) for a
+ * squared mismatch) and the final density rho_T (e.g. rho_T/2 and (1 + rho^N_T)/2 together
+ * for the red mass), and the gradients with respect to the flux field phi(x) and the site
  * threshold Gamma are returned.
  *   cge_forward_ckpt : from the current state, advance nsteps and save the state (as
- *                      cge_save_state) at steps 0, K, 2K, ... into ckpt[0..ceil(nsteps/K)-1],
- *                      each of cge_state_bytes().  At unit relaxation times it steps with the
- *                      split form (CGE_KERNEL_SPLIT), which the backward recomputes with.
- *   cge_backward     : call after cge_forward_ckpt with the same nsteps and K, with the state
- *                      after nsteps current.  seg: cge_segment_bytes(K) bytes for the
+ *                      cge_save_state) at steps 0, K, 2K, ... into ckpt[0..ceil(nsteps/K)-1]
+ *                      and the state after nsteps into ckpt[ceil(nsteps/K)], each buffer of
+ *                      cge_state_bytes().  At unit relaxation times it steps with the split
+ *                      form (CGE_KERNEL_SPLIT), which the backward recomputes with.
+ *   cge_backward     : call after cge_forward_ckpt with the same nsteps, K and checkpoints
+ *                      (again as often as needed, e.g. for another loss).  seg:
+ *                      cge_segment_bytes(K) bytes for the
  *                      recomputed steps of one segment (at unit relaxation times each step's
  *                      phase field, moments and site data, otherwise each state);
  *                      work: cge_adjoint_bytes();
- *                      dL_drhoN: [N] doubles; grad_phi (out): [N] doubles, dL/dphi(x) summed
+ *                      dL_drhoN, dL_drho: [N] doubles, either may be NULL (read as zero) but
+ *                      not both; grad_phi (out): [N] doubles, dL/dphi(x) summed
  *                      over the steps (phi held over time); grad_phi_t (out, nullable):
  *                      [nsteps][N] doubles, dL/dphi(x, t) per step; grad_gamma (host, nullable):
  *                      dL/dGamma (0 for GRAD_GT).  All buffers except grad_gamma are device
- *                      memory.  Forward states are recomputed from the checkpoints; the step
- *                      counter and sink bookkeeping are restored, the populations are not
- *                      (reload a state with cge_load_state).
+ *                      memory.  Forward states are recomputed from the checkpoints; on return
+ *                      the context holds the state after nsteps again, with its step counter
+ *                      and sink bookkeeping.
  * Errors: CGE_EINVAL (missing buffers, nsteps or K < 1), CGE_EUNSUPPORTED (solid nodes,
  * PHASE_LT rule), CGE_EDEVICE. */
 size_t cge_adjoint_bytes(const cge_params* params);
 size_t cge_segment_bytes(const cge_params* params, int K);
 cge_status cge_forward_ckpt(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt);
 cge_status cge_backward(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt, void* seg,
-                        void* work, const double* dL_drhoN, double* grad_phi, double* grad_phi_t,
-                        double* grad_gamma);
+                        void* work, const double* dL_drhoN, const double* dL_drho,
+                        double* grad_phi, double* grad_phi_t, double* grad_gamma);
 
 /* Recompute the site mask from the current state (gradient of its phase field). */
 cge_status cge_reset_sites(cge_ctx* ctx);

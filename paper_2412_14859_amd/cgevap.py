@@ -82,7 +82,7 @@ def lib():
         L.cge_segment_bytes.argtypes = [P(CgeParams), C.c_int]
         L.cge_segment_bytes.restype = C.c_size_t
         L.cge_forward_ckpt.argtypes = [vp, C.c_longlong, C.c_int, P(vp)]
-        L.cge_backward.argtypes = [vp, C.c_longlong, C.c_int, P(vp), vp, vp, vp, vp, vp, dp]
+        L.cge_backward.argtypes = [vp, C.c_longlong, C.c_int, P(vp), vp, vp, vp, vp, vp, vp, dp]
         L.cge_reset_sites.argtypes = [vp]
         L.cge_set_site_threshold.argtypes = [vp, C.c_double, C.c_double]
         L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
@@ -262,34 +262,36 @@ class Simulation:
         return lib().cge_state_bytes(C.byref(make_params(self.params, self.precision)))
 
     def forward_ckpt(self, nsteps, K):
-        """Advance nsteps, keeping the state at steps 0, K, 2K, ... (device tensors)."""
-        nck = (int(nsteps) + K - 1) // K
+        """Advance nsteps, keeping the state at steps 0, K, 2K, ... and the final state
+        (device tensors)."""
+        nck = (int(nsteps) + K - 1) // K + 1
         ck = [self.torch.empty(self._state_bytes(), dtype=self.torch.uint8, device=self.device)
               for _ in range(nck)]
         arr = (C.c_void_p * nck)(*[t.data_ptr() for t in ck])
         self._check(lib().cge_forward_ckpt(self._ctx, int(nsteps), int(K), arr))
         return ck
 
-    def backward(self, ckpt, nsteps, K, dL_drhoN, per_step=False):
-        """Gradients of a loss given by dL/drho^N of the state after nsteps (the current one,
-        reached by forward_ckpt).  Returns grad_phi [shape] (phi held over time), grad_phi_t
-        [nsteps, shape] when per_step, and grad_gamma.  The populations are left at a
-        recomputed state: load a saved one before stepping on."""
+    def backward(self, ckpt, nsteps, K, dL_drhoN=None, per_step=False, dL_drho=None):
+        """Gradients of a loss given by dL/drho^N and/or dL/drho of the state after nsteps
+        (from the checkpoints of forward_ckpt).  Returns grad_phi [shape] (phi held over time),
+        grad_phi_t [nsteps, shape] when per_step, and grad_gamma.  The simulation is left at
+        the state after nsteps."""
         t = self.torch
         nck = len(ckpt)
-        assert nck == (int(nsteps) + K - 1) // K
+        assert nck == (int(nsteps) + K - 1) // K + 1
         cp = make_params(self.params, self.precision)
         seg = t.empty(lib().cge_segment_bytes(C.byref(cp), int(K)), dtype=t.uint8,
                       device=self.device)
         work = t.empty(lib().cge_adjoint_bytes(C.byref(cp)), dtype=t.uint8, device=self.device)
-        g = self._dev64(dL_drhoN).reshape(self.shape).contiguous()
+        g = None if dL_drhoN is None else self._dev64(dL_drhoN).reshape(self.shape).contiguous()
+        gr = None if dL_drho is None else self._dev64(dL_drho).reshape(self.shape).contiguous()
         gphi = t.empty(self.shape, dtype=t.float64, device=self.device)
         gpt = (t.empty((int(nsteps),) + self.shape, dtype=t.float64, device=self.device)
                if per_step else None)
         gg = C.c_double()
         arr = (C.c_void_p * nck)(*[c.data_ptr() for c in ckpt])
         self._check(lib().cge_backward(self._ctx, int(nsteps), int(K), arr, _ptr(seg), _ptr(work),
-                                       _ptr(g), _ptr(gphi), _ptr(gpt), C.byref(gg)))
+                                       _ptr(g), _ptr(gr), _ptr(gphi), _ptr(gpt), C.byref(gg)))
         return {"grad_phi": gphi, "grad_phi_t": gpt, "grad_gamma": gg.value}
 
     def set_counters(self, step=0, site_steps=0, sink_total=0.0):

@@ -87,10 +87,13 @@ static UnitSlot unit_slot(const cge_params* p) {
     return s;
 }
 
-// Seed: lambda of S_T from dL/drho^N_T, rho^N = sum dd / (rho_ref + sum ft) (pre-sink).
+// Seed: lambda of S_T from dL/drho^N_T and dL/drho_T (either may be absent), with
+// rho = rho_ref + sum ft and rho^N = sum dd / rho (pre-sink):
+//     dL/dft_i = dL/drho - dL/drho^N rho^N / rho,    dL/ddd_i = dL/drho^N / rho.
 template <int Q, typename S, typename M, int NMU>
 __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
                                                     const double* __restrict__ g_rhoN,
+                                                    const double* __restrict__ g_rho,
                                                     double* __restrict__ mu, double* __restrict__ ab,
                                                     double* __restrict__ aF, Geo g, Phys<M> P) {
     int x, y, z;
@@ -102,11 +105,12 @@ __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
     moments<Q>(ft, dd, drho, dsum, j);
     const double rho = static_cast<double>(P.rho_ref + drho);
     const double rN = static_cast<double>(dsum) / rho;
-    const double gr = g_rhoN[n];
+    const double gr = g_rhoN ? g_rhoN[n] : 0.0;
+    const double a = (g_rho ? g_rho[n] : 0.0) - gr * rN / rho;
 #pragma unroll
     for (int i = 0; i < NMU; ++i) mu[(long long)i * g.N + n] = 0.0;
-    if (NMU == 4) mu[n] = -gr * rN / rho;  // unit layout: q0 = p0 + a
-    else ab[n] = -gr * rN / rho;
+    if (NMU == 4) mu[n] = a;  // unit layout: q0 = p0 + a
+    else ab[n] = a;
     ab[g.N + n] = gr / rho;
     aF[n] = 0.0;
 }
@@ -399,7 +403,8 @@ __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src
 }
 
 template <int Q, typename S, typename M, bool WALLS>
-static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, AdjWork w, bool unit) {
+static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, const double* g_rho, AdjWork w,
+                            bool unit) {
     if constexpr (WALLS) {
         return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
     } else {
@@ -407,10 +412,10 @@ static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, AdjWork w, bool un
         const S* src = static_cast<const S*>(c->pop[c->cur]);
         if (unit)
             hipLaunchKernelGGL((k_adj_seed<Q, S, M, 4>), gr, bl, 0, c->stream, src, g_rhoN,
-                               w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
+                               g_rho, w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
         else
             hipLaunchKernelGGL((k_adj_seed<Q, S, M, Q>), gr, bl, 0, c->stream, src, g_rhoN,
-                               w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
+                               g_rho, w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
         return check(c, hipGetLastError(), "adjoint seed");
     }
 }
@@ -453,10 +458,10 @@ static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, c
     }
 }
 
-static cge_status adjoint_seed(cge_ctx* c, const double* g_rhoN, void* work, int parity,
-                               bool unit) {
+static cge_status adjoint_seed(cge_ctx* c, const double* g_rhoN, const double* g_rho,
+                               void* work, int parity, bool unit) {
     AdjWork w = adj_work(c, work, parity, unit ? 4 : c->Q);
-    CGE_DISPATCH(c, seed_impl, c, g_rhoN, w, unit);
+    CGE_DISPATCH(c, seed_impl, c, g_rhoN, g_rho, w, unit);
 }
 
 static cge_status adjoint_rstep(cge_ctx* c, const void* pop, const void* rhoN, const void* mom,
@@ -490,21 +495,23 @@ cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ck
     // at unit tau the backward recomputes with the split step, so the forward uses it too and
     // the recomputed trajectory is the forward's bit for bit
     const bool split = unit_tau(&c->p) && !c->flags;
-    for (long long n0 = 0, j = 0; n0 < nsteps; n0 += K, ++j) {
+    const long long nseg = (nsteps + K - 1) / K;
+    for (long long j = 0; j <= nseg; ++j)
         if (!ckpt[j]) return fail(c, CGE_EINVAL, "NULL checkpoint buffer");
+    for (long long n0 = 0, j = 0; n0 < nsteps; n0 += K, ++j) {
         if (cge_status s = cge_save_state(c, ckpt[j])) return s;
         const long long n = nsteps - n0 < K ? nsteps - n0 : K;
         if (cge_status s = split ? split_steps(c, n) : cge_step(c, n)) return s;
     }
-    return CGE_OK;
+    return cge_save_state(c, ckpt[nseg]);  // the final state seeds the backward
 }
 
 cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, void* seg,
-                        void* work, const double* dL_drhoN, double* grad_phi,
-                        double* grad_phi_t, double* grad_gamma) {
+                        void* work, const double* dL_drhoN, const double* dL_drho,
+                        double* grad_phi, double* grad_phi_t, double* grad_gamma) {
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
-    if (nsteps < 1 || K < 1 || !ckpt || !seg || !work || !dL_drhoN || !grad_phi)
+    if (nsteps < 1 || K < 1 || !ckpt || !seg || !work || (!dL_drhoN && !dL_drho) || !grad_phi)
         return fail(c, CGE_EINVAL, "missing argument");
     if (c->flags) return fail(c, CGE_EUNSUPPORTED, "adjoint needs a domain without solid nodes");
     if (c->p.site_rule == CGE_SITE_PHASE_LT)
@@ -535,10 +542,13 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
     AdjWork w0 = adj_work(c, work, 0, c->Q);
     if (zero(grad_phi, N, c->stream) != hipSuccess || zero(w0.gpart, nblk, c->stream) != hipSuccess)
         return fail(c, CGE_EDEVICE, "clearing gradients failed");
-    // seed from the current state (the state after nsteps)
-    int parity = 0;
-    if (cge_status s = adjoint_seed(c, dL_drhoN, work, parity, unit)) return s;
+    // seed from the state after nsteps (the last checkpoint)
     const long long nseg = (nsteps + K - 1) / K;
+    for (long long j = 0; j <= nseg; ++j)
+        if (!ckpt[j]) return fail(c, CGE_EINVAL, "NULL checkpoint buffer");
+    if (cge_status s = cge_load_state(c, ckpt[nseg])) return s;
+    int parity = 0;
+    if (cge_status s = adjoint_seed(c, dL_drhoN, dL_drho, work, parity, unit)) return s;
     for (long long j = nseg - 1; j >= 0; --j) {
         const long long n0 = j * K;
         const long long len = nsteps - n0 < K ? nsteps - n0 : K;
@@ -591,6 +601,8 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
                                                c->acc_len * sizeof(long long),
                                                hipMemcpyHostToDevice, c->stream), "acc restore"))
         return s;
+    // the context is left as the forward run left it: final state, step counter, bookkeeping
+    if (cge_status s = cge_load_state(c, ckpt[nseg])) return s;
     if (cge_status s = check(c, hipStreamSynchronize(c->stream), "sync")) return s;
     c->step = step0;
     double gsum = 0.0;

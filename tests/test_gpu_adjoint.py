@@ -246,6 +246,30 @@ def test_autograd_function_wrapper():
     sim.close()
 
 
+@pytest.mark.parametrize("name", ["d2q9_soft", "d2q9_soft_ratio"])
+def test_backward_is_repeatable_and_restores_the_state(name):
+    """The backward seeds from the final checkpoint and leaves the context at the final state
+    with its counters, so a second backward (another loss) is independent of the first."""
+    import torch
+    w, target = _setup(name)
+    _flush(f"[adjoint] repeat + restore {name}")
+    sim = gpu_for(w, "fp32s")
+    ck = sim.forward_ckpt(20, 6)
+    f_end, obs_end = sim.populations().cpu(), sim.observables()
+    fl = sim.fields()
+    g = 2.0 * (fl["rhoN"] - torch.as_tensor(target, device=sim.device))
+    rho = fl["rho_r"] + fl["rho_b"]
+    a = sim.backward(ck, 20, 6, g)
+    assert torch.equal(sim.populations().cpu(), f_end)
+    obs = sim.observables()
+    for k in ("step", "sink_total", "site_steps", "mass_r"):
+        assert obs[k] == obs_end[k], k
+    sim.backward(ck, 20, 6, dL_drho=torch.ones_like(rho))  # another loss in between
+    b = sim.backward(ck, 20, 6, g)
+    assert torch.equal(a["grad_phi"], b["grad_phi"]) and a["grad_gamma"] == b["grad_gamma"]
+    sim.close()
+
+
 def test_unsupported_configurations_are_rejected():
     import torch
     from paper_2412_14859_amd import cgevap

@@ -134,3 +134,97 @@ def test_sampled_nodes_match_the_oracle_at_full_size(name):
     sim.close()
     del sim, f1
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("site_rule,precision,tol", [("grad", "fp64", 1e-11),
+                                                     ("grad", "fp32s", 1e-11),
+                                                     ("soft", "fp32s", None)])
+def test_full_size_adjoint_mass_covectors(site_rule, precision, tol):
+    """The adjoint workload at full size (D2Q9 512^2 drop, checkpoints every 100 steps over
+    2000 steps), checked through properties that hold at any size.
+    * L = final total mass (dL/drho = 1): every operator conserves it, so dL/dphi = 0.
+    * Hard sites, L = final red mass (dL/drho^N = rho/2, dL/drho = (1 + rho^N)/2): every
+      operator but the sink conserves red mass, so the per-step gradient is exactly
+      dL/dphi(x, t) = -m(x, t)/Sbar, i.e. the values 0 and -1/Sbar at exactly the site-steps of
+      the run, and sum_x phi(x) dL/dphi(x) is minus the mass the sink removed (the forward's
+      FP64 bookkeeping).  The adjoint is the exact transpose of the step at the stored
+      trajectory, so this holds to rounding at every storage precision.  With soft sites the
+      weights depend on the state, so phi also acts through later weights and these
+      identities do not hold."""
+    import torch
+    w = case("adjoint2d", None, site_rule=site_rule, kappa=0.01)
+    p = w["params"]
+    nsteps, K = 2000, 100
+    _flush(f"[full-size adjoint] adjoint2d 512^2 {site_rule} {precision} n={nsteps} K={K}")
+    sim = gpu_for(w, precision)
+    ck = sim.forward_ckpt(nsteps, K)
+    obs = sim.observables()
+    fl = sim.fields()
+    rho = fl["rho_r"] + fl["rho_b"]
+    r0 = sim.backward(ck, nsteps, K, dL_drho=torch.ones_like(rho))
+    z = float(r0["grad_phi"].abs().max())
+    _flush(f"  total-mass covector: max |dL/dphi| = {z:.2e}")
+    assert z < 1e-10 / p["sbar"]
+    if site_rule == "grad":
+        r = sim.backward(ck, nsteps, K, dL_drhoN=rho / 2, dL_drho=(1 + fl["rhoN"]) / 2,
+                         per_step=True)
+        phi = sim.phi_field.to(torch.float64)
+        lhs = float((phi * r["grad_phi"]).sum())
+        rel = abs(lhs + obs["sink_total"]) / obs["sink_total"]
+        _flush(f"  sum phi dL/dphi = {lhs:.12e}, sink total {obs['sink_total']:.12e}, "
+               f"rel {rel:.2e}")
+        assert obs["sink_total"] > 0 and rel < tol
+        g = r["grad_phi_t"]
+        inv = 1.0 / p["sbar"]
+        at_site = (g + inv).abs() < tol * inv
+        assert bool(((g.abs() < tol * inv) | at_site).all())
+        assert int(at_site.sum()) == obs["site_steps"]
+        del g, at_site
+    sim.close()
+    torch.cuda.empty_cache()
+
+
+def test_full_size_adjoint_central_differences():
+    """The adjoint workload at full size with soft sites (D2Q9 512^2, 2000 steps, K = 100, the
+    shape loss L = sum (rho^N_T - target)^2), FP64: the adjoint's directional derivatives along
+    a seeded direction of phi(x) and along Gamma against central differences of the GPU's own
+    forward runs (relative step 1e-3)."""
+    import torch
+    w = case("adjoint2d", None, site_rule="soft", kappa=0.01)
+    p = w["params"]
+    nsteps, K = 2000, 100
+    target = torch.as_tensor(w["target"])
+    _flush("[full-size adjoint FD] adjoint2d 512^2 soft fp64")
+    sim = gpu_for(w, "fp64")
+    start = sim.save_state().clone()
+    dev = sim.device
+    tgt = target.to(dev)
+    ck = sim.forward_ckpt(nsteps, K)
+    rn = sim.fields()["rhoN"]
+    r = sim.backward(ck, nsteps, K, dL_drhoN=2.0 * (rn - tgt))
+    phi0 = sim.phi_field.clone()
+
+    def loss(phi, gamma):
+        sim.phi_field.copy_(phi)
+        sim.set_site_threshold(gamma)
+        sim.load_state(start)
+        sim.set_counters()
+        sim.step(nsteps)
+        v = float(((sim.fields()["rhoN"] - tgt) ** 2).sum())
+        sim.phi_field.copy_(phi0)
+        sim.set_site_threshold(p["gamma"])
+        return v
+
+    gen = torch.Generator(device="cpu").manual_seed(1004)
+    v = (torch.randn(phi0.shape, generator=gen, dtype=torch.float64).to(dev) * phi0)
+    ad = float((r["grad_phi"] * v).sum())
+    eps = 1e-3
+    fd = (loss(phi0 + eps * v, p["gamma"]) - loss(phi0 - eps * v, p["gamma"])) / (2 * eps)
+    _flush(f"  phi: adjoint {ad:.10e} fd {fd:.10e}")
+    assert abs(fd - ad) <= 1e-4 * abs(ad)
+    eg = 1e-3 * p["gamma"]
+    fdg = (loss(phi0, p["gamma"] + eg) - loss(phi0, p["gamma"] - eg)) / (2 * eg)
+    _flush(f"  Gamma: adjoint {r['grad_gamma']:.10e} fd {fdg:.10e}")
+    assert abs(fdg - r["grad_gamma"]) <= 1e-3 * abs(r["grad_gamma"])
+    sim.close()
+    torch.cuda.empty_cache()
