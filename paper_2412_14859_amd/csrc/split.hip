@@ -75,8 +75,10 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
 }
 
 // Pass 2: gradient, equilibrium, perturbation, recolouring, store, next site mask.
+// At least 5 waves per SIMD (the register budget allows it without spills): more stores in
+// flight.
 template <int Q, typename S, typename M, bool WALLS>
-__global__ __launch_bounds__(kTPBX) void k_finish(S* __restrict__ dst,
+__global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_finish(S* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
                                                   void* __restrict__ carry,
                                                   const M* __restrict__ rhoN,
