@@ -33,12 +33,20 @@ STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fu
                 "k_finish": ("k_moments+k_finish", "split")}
 
 
-def sources_sha():
-    """Hash of the HIP sources, to tell whether a stored counter summary still applies."""
-    import glob
+def kernel_sources(tag):
+    """The files a step form's kernels and launches are compiled from."""
+    csrc = os.path.join(ROOT, "paper_2412_14859_amd", "csrc")
+    return [os.path.join(csrc, f) for f in (f"{tag}.hip", "node.hpp", "lattice.hpp",
+                                            "internal.hpp")] + \
+        [os.path.join(ROOT, "include", "cgevap.h")]
+
+
+def sources_sha(tag):
+    """Hash of a step form's sources, to tell whether a stored counter summary still
+    applies."""
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2412_14859_amd", "csrc", "*"))):
+    for p in kernel_sources(tag):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -58,7 +66,7 @@ def stored_traffic(kernel, n, precision):
             if ": " in line and not line.startswith(" "):
                 k, v = line.split(": ", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("sources_sha256") != sources_sha():
+    if kv.get("sources_sha256") != sources_sha(tag):
         return None
     return float(kv["step_traffic_bytes"])
 

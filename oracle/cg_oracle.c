@@ -92,6 +92,9 @@ typedef struct ora_ctx {
     unsigned char *solid;
     long long step, site_steps;
     double sink_total;
+    /* height-dependent flux (Eq. heated): active when hf_every > 0 */
+    long long hf_every;
+    double hf_phi, hf_K, hf_hs;
 } ora_ctx;
 
 /* ------------------------------------------------------------------ lattices */
@@ -496,11 +499,66 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
     s->step += 1;
 }
 
+/* Height-dependent flux (Sec. III, space- and time-varying flux; Eq. heated):
+ * Phi = phi_S / (K + h / h_s), where h is the local drop height above the substrate.  The
+ * substrate normal is the last lattice axis (z for D3Q19, y for D2Q9).  h of a column is
+ * its red thickness, the sum over its fluid nodes of the red fraction (1 + rho^N)/2 of the
+ * current (pre-sink) state; every node of the column gets the column's flux. */
+static void height_flux(ora_ctx* s) {
+    const int Q = s->L.Q;
+    const long long nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
+    const long long ncol = s->L.D == 3 ? nx * ny : nx;   /* columns */
+    const long long len = s->L.D == 3 ? nz : ny;          /* nodes per column */
+    const long long stride = s->L.D == 3 ? nx * ny : nx;  /* node step along the column */
+    for (long long col = 0; col < ncol; ++col) {
+        double h = 0.0;
+        for (long long k = 0; k < len; ++k) {
+            const long long n = col + k * stride;
+            if (is_solid(s, n)) continue;
+            double rr = 0.0, rb = 0.0;
+            for (int i = 0; i < Q; ++i) {
+                rr += F(s, 0, i)[n];
+                rb += F(s, 1, i)[n];
+            }
+            h += 0.5 * (1.0 + (rr - rb) / (rr + rb));
+        }
+        const double phi = s->hf_phi / (s->hf_K + h / s->hf_hs);
+        for (long long k = 0; k < len; ++k) s->phi_field[col + k * stride] = phi;
+    }
+}
+
+/* Switch the height-dependent flux on (every > 0: refresh the flux field from the current
+ * state before every step whose step counter is a multiple of `every`) or off (every <= 0,
+ * which keeps the last field). */
+int ora_set_height_flux(ora_ctx* s, double phi_s, double K, double h_scale, long long every) {
+    if (every > 0 && (!(h_scale > 0.0) || !(K > 0.0) || !isfinite(phi_s) || !isfinite(K)))
+        return 1;
+    if (every > 0 && !s->phi_field) {
+        s->phi_field = (double*)malloc(s->N * sizeof(double));
+        if (!s->phi_field) return 1;
+        for (long long n = 0; n < s->N; ++n) s->phi_field[n] = s->p.phi;
+    }
+    s->hf_every = every;
+    s->hf_phi = phi_s;
+    s->hf_K = K;
+    s->hf_hs = h_scale;
+    return 0;
+}
+
 /* Advance nsteps.  mask_in (nullable, [nsteps][N]) replaces the site selection
  * (frozen-mask runs); mask_log (nullable, [nsteps][N]) records the sites used. */
 int ora_step(ora_ctx* s, long long nsteps, unsigned char* mask_log, const unsigned char* mask_in) {
-    for (long long t = 0; t < nsteps; ++t)
+    for (long long t = 0; t < nsteps; ++t) {
+        if (s->hf_every > 0 && s->step % s->hf_every == 0) height_flux(s);
         one_step(s, mask_in ? mask_in + t * s->N : NULL, mask_log ? mask_log + t * s->N : NULL);
+    }
+    return 0;
+}
+
+/* The flux field in use (N doubles), or 1 when none is bound. */
+int ora_get_phi_field(const ora_ctx* s, double* out) {
+    if (!s->phi_field) return 1;
+    memcpy(out, s->phi_field, s->N * sizeof(double));
     return 0;
 }
 

@@ -58,6 +58,9 @@ def lib():
         L.ora_recompute_fmag.argtypes = [C.c_void_p]
         L.ora_set_counters.argtypes = [C.c_void_p, C.c_longlong, C.c_longlong, C.c_double]
         L.ora_step.argtypes = [C.c_void_p, C.c_longlong, up, up]
+        L.ora_set_height_flux.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                          C.c_longlong]
+        L.ora_get_phi_field.argtypes = [C.c_void_p, dp]
         L.ora_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         L.ora_observables.argtypes = [C.c_void_p, P(OraObs)]
         L.ora_tables.argtypes = [C.c_int, dp, dp, dp, dp, P(C.c_int), P(C.c_int), dp]
@@ -146,6 +149,18 @@ class Oracle:
 
     def recompute_fmag(self):
         lib().ora_recompute_fmag(self._ctx)
+
+    def set_height_flux(self, phi_s, K, h_scale, every=1):
+        """Height-dependent flux phi_s / (K + h / h_scale) from the column heights (Eq.
+        heated), refreshed every `every` steps; every <= 0 switches it off."""
+        if lib().ora_set_height_flux(self._ctx, phi_s, K, h_scale, every) != 0:
+            raise ValueError("invalid height-flux parameters")
+
+    def phi_field(self):
+        out = np.empty(self.shape)
+        if lib().ora_get_phi_field(self._ctx, _dp(out)) != 0:
+            return None
+        return out
 
     def set_counters(self, step=0, site_steps=0, sink_total=0.0):
         lib().ora_set_counters(self._ctx, step, site_steps, sink_total)

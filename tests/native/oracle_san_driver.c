@@ -45,6 +45,7 @@ static int run(int Q, int nx, int ny, int nz, int site_rule, int walls, int fiel
     if (!s) return 1;
     int rc = ora_init_equilibrium(s, rr, rb, NULL);
     unsigned char* log = malloc((size_t)N * 3);
+    if (walls) rc |= ora_set_height_flux(s, 1e-3, 1.0, 4.0, 2);
     rc |= ora_step(s, 3, log, NULL);
     rc |= ora_step(s, 2, NULL, log);
     double* f = malloc(sizeof(double) * 2 * Q * N);
