@@ -204,6 +204,19 @@ cge_status cge_reset_sites(cge_ctx* ctx);
  * it.  CGE_EINVAL for a non-finite value. */
 cge_status cge_set_site_threshold(cge_ctx* ctx, double gamma, double kappa);
 
+/* Height-dependent flux (Sec. III, space- and time-varying flux; Eq. heated): with every > 0
+ * the bound flux field is overwritten, before every step whose step counter is a multiple of
+ * `every`, with phi(x) = phi_s / (K + h / h_scale), where h is the drop height of x's column
+ * along the last lattice axis (z for D3Q19, y for D2Q9; the substrate normal): the sum over the
+ * column's fluid nodes of the red fraction (1 + rho^N)/2 of the current pre-sink state.  The
+ * field depends on the current state only, so resumed runs take the same fluxes.  every <= 0
+ * switches it off (the field keeps its last values).  Each refresh reads the whole state once.
+ * Needs a bound flux field (CGE_ESTATE otherwise); CGE_EINVAL unless K > 0, h_scale > 0 and
+ * phi_s is finite.  The adjoint does not differentiate through the heights: cge_forward_ckpt
+ * and cge_backward return CGE_EUNSUPPORTED while it is on. */
+cge_status cge_set_height_flux(cge_ctx* ctx, double phi_s, double K, double h_scale,
+                               long long every);
+
 /* Restore the step counter and the FP64 sink bookkeeping (checkpoint resume). */
 cge_status cge_set_counters(cge_ctx* ctx, long long step, long long site_steps,
                             double sink_total);

@@ -22,7 +22,8 @@ ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
            "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
            "cge_load_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
-           "cge_reset_sites", "cge_set_site_threshold", "cge_set_counters", "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
+           "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_counters",
+           "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
 
@@ -85,6 +86,7 @@ def lib():
         L.cge_backward.argtypes = [vp, C.c_longlong, C.c_int, P(vp), vp, vp, vp, vp, vp, vp, dp]
         L.cge_reset_sites.argtypes = [vp]
         L.cge_set_site_threshold.argtypes = [vp, C.c_double, C.c_double]
+        L.cge_set_height_flux.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_longlong]
         L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
         L.cge_step.argtypes = [vp, C.c_longlong]
         L.cge_observables.argtypes = [vp, P(CgeObs)]
@@ -250,6 +252,13 @@ class Simulation:
 
     def reset_sites(self):
         self._check(lib().cge_reset_sites(self._ctx))
+
+    def set_height_flux(self, phi_s, K, h_scale, every=1):
+        """Flux phi_s / (K + h / h_scale) from the drop height h of each column normal to the
+        substrate (the last lattice axis), refreshed from the state every `every` steps;
+        every <= 0 switches it off.  Writes the bound flux field (phi_field=...)."""
+        self._check(lib().cge_set_height_flux(self._ctx, float(phi_s), float(K),
+                                              float(h_scale), int(every)))
 
     def set_site_threshold(self, gamma, kappa=0.0):
         self._check(lib().cge_set_site_threshold(self._ctx, float(gamma), float(kappa)))

@@ -4,6 +4,8 @@
 #include <cstring>
 #include <new>
 
+#include <algorithm>
+
 #include "internal.hpp"
 #include "node.hpp"
 
@@ -310,6 +312,22 @@ cge_status cge_reset_sites(cge_ctx* c) {
     return reset_sites(c);
 }
 
+cge_status cge_set_height_flux(cge_ctx* c, double phi_s, double K, double h_scale,
+                               long long every) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (every > 0) {
+        if (!c->phi_field) return fail(c, CGE_ESTATE, "the height flux needs a bound flux field");
+        if (!is_fin(phi_s) || !is_fin(K) || !(K > 0.0) || !is_fin(h_scale) || !(h_scale > 0.0))
+            return fail(c, CGE_EINVAL, "height flux needs finite phi_s, K > 0, h_scale > 0");
+        c->hf_phi = phi_s;
+        c->hf_K = K;
+        c->hf_hs = h_scale;
+    }
+    c->hf_every = every > 0 ? every : 0;
+    return CGE_OK;
+}
+
 cge_status cge_set_site_threshold(cge_ctx* c, double gamma, double kappa) {
     if (!c) return CGE_EINVAL;
     if (!is_fin(gamma) || !is_fin(kappa))
@@ -330,16 +348,30 @@ cge_status cge_set_counters(cge_ctx* c, long long step, long long site_steps, do
     return CGE_OK;
 }
 
-cge_status cge_step(cge_ctx* c, long long nsteps) {
-    if (!c) return CGE_EINVAL;
-    if (nsteps < 0) return fail(c, CGE_EINVAL, "nsteps must be >= 0");
-    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
-    if (nsteps == 0) return CGE_OK;
+static cge_status run_steps(cge_ctx* c, long long nsteps) {
     switch (c->kernel) {
         case CGE_KERNEL_FUSED: return fused_steps(c, nsteps);
         case CGE_KERNEL_SPLIT: return split_steps(c, nsteps);
         default: return twopass_steps(c, nsteps);
     }
+}
+
+cge_status cge_step(cge_ctx* c, long long nsteps) {
+    if (!c) return CGE_EINVAL;
+    if (nsteps < 0) return fail(c, CGE_EINVAL, "nsteps must be >= 0");
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (nsteps == 0) return CGE_OK;
+    if (c->hf_every <= 0) return run_steps(c, nsteps);
+    // height flux: refresh the field before every step whose counter is a multiple of every
+    for (long long done = 0; done < nsteps;) {
+        const long long phase = c->step % c->hf_every;
+        if (phase == 0)
+            if (cge_status s = height_flux(c)) return s;
+        const long long n = std::min(c->hf_every - phase, nsteps - done);
+        if (cge_status s = run_steps(c, n)) return s;
+        done += n;
+    }
+    return CGE_OK;
 }
 
 cge_status cge_observables(cge_ctx* c, cge_obs* out) {

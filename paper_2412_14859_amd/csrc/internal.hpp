@@ -36,6 +36,9 @@ struct cge_ctx {
     double* obs_part = nullptr;     // [CGE_NOBS][obs_blocks]
     long long obs_blocks = 0;
     double* obs_res = nullptr;      // [CGE_NOBS + 2] final values (device)
+    // height-dependent flux (active when hf_every > 0)
+    long long hf_every = 0;
+    double hf_phi = 0.0, hf_K = 1.0, hf_hs = 1.0;
     // counters
     long long step = 0;
     long long sites_offset = 0;
@@ -82,6 +85,9 @@ cge_status init_equilibrium(cge_ctx* c, const double* rr, const double* rb, cons
 cge_status set_populations(cge_ctx* c, const double* f);
 cge_status get_populations(cge_ctx* c, double* f);
 cge_status fields(cge_ctx* c, double* rr, double* rb, double* u, double* rhoN);
+
+// flux field from the column heights of the current state (flux.hip)
+cge_status height_flux(cge_ctx* c);
 
 // adjoint workspace size
 size_t adjoint_bytes(const cge_params* p);

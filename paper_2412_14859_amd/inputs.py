@@ -134,7 +134,8 @@ def workload(name, shape=None, radius=None, phi=None, seed=None):
     flat interface between walls), 'ellipse2d' (D2Q9 1024^2 ellipse 200 x 120),
     'sphere3d' (D3Q19 256^3 sphere R 64), 'sessile3d' (D3Q19 384x384x192 cap on a wall,
     density ratio 10, space-dependent flux), 'adjoint2d' (D2Q9 512^2 drop R 96 with a
-    seeded flux field and target shape)."""
+    seeded flux field and target shape), 'hemisphere3d' / 'hemisphere2d' (drop on a wall for
+    the height-dependent flux, D3Q19 192^3 R 66 / D2Q9 384x192 R 66)."""
     if name == "drop2d":
         shape = shape or (1, 128, 128)
         R = radius or 32.0 * shape[2] / 128.0
@@ -198,6 +199,40 @@ def workload(name, shape=None, radius=None, phi=None, seed=None):
         w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": None, "phi_field": ph,
              "steps": 2000, "radius": R, "target": target_shape(shape, c, 90.0 * s),
              "ckpt_every": 100, "kappa": 0.01}
+    elif name == "flat3d":
+        # flat film on a wall (the paper's flat-interface benchmark in three dimensions):
+        # red below z = nz/2, walls at z = 0 and nz - 1
+        shape = shape or (128, 64, 64)
+        nz = shape[0]
+        p = _base(19, shape)
+        d = flat_distance(shape, nz / 2.0, axis=0)
+        rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
+        solid = wall_layers(shape, 0, [0, nz - 1])
+        rr = np.where(solid == 1, 0.0, rr)
+        rb = np.where(solid == 1, 0.0, rb)
+        w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": solid, "phi_field": None,
+             "height": nz / 2.0}
+    elif name in ("hemisphere3d", "hemisphere2d"):
+        # the height-dependent flux benchmark (Sec. III, space- and time-varying flux): a
+        # hemispherical drop (half disc in 2D) on a neutrally wetting wall at index 0 of the
+        # last lattice axis, unit density ratio, beta 0.99, sigma 0.1, unit relaxation times;
+        # the flux field is computed from the drop height (phi_S 1e-3, K, h_s = R0)
+        three = name == "hemisphere3d"
+        shape = shape or ((192, 192, 192) if three else (1, 192, 384))
+        nz, ny, nx = shape
+        R = radius or (66.0 * nx / 192.0 if three else 66.0 * nx / 384.0)
+        p = _base(19 if three else 9, shape, sigma=0.1, beta=0.99)
+        centre = (nx / 2, ny / 2, 0.5) if three else (nx / 2, 0.5, 0.0)
+        d = sphere_distance(shape, centre, R)
+        rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
+        # walls at both ends of the substrate axis: with one wall layer and periodic wrap,
+        # the wetting value under the drop would average the drop base with the far side
+        solid = wall_layers(shape, 0 if three else 1, [0, (nz if three else ny) - 1])
+        rr = np.where(solid == 1, 0.0, rr)
+        rb = np.where(solid == 1, 0.0, rb)
+        w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": solid,
+             "phi_field": np.full(shape, p["phi"]), "radius": R, "phi_s": 1e-3,
+             "h_scale": R}
     else:
         raise KeyError(name)
     if phi is not None:

@@ -1,0 +1,49 @@
+"""Gamma calibration (Eq. satisfy: Sbar sites per unit interface measure) on drops equilibrated
+on the GPU, with the paper's model parameters (unit density ratio, beta 0.99, sigma 0.1,
+tau 1, Sbar 3).  The paper calibrates Gamma = 0.305 for curved drops and finds that one value
+serves every shape (Sec. III) and varies weakly with beta."""
+import pytest
+
+from paper_2412_14859_amd import calibrate as cal
+from tests.helpers import case
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {
+    "sphere": ("sphere3d", (96, 96, 96), 30.0),
+    "hemisphere": ("hemisphere3d", (72, 128, 128), 40.0),
+    "flat": ("flat3d", (96, 48, 48), None),
+}
+
+
+def _workload(kind, beta):
+    wl, shape, R = SHAPES[kind]
+    kw = dict(beta=beta, sigma=0.1)
+    return case(wl, shape, radius=R, **kw) if R else case(wl, shape, **kw)
+
+
+@pytest.mark.parametrize("kind", list(SHAPES))
+def test_gamma_0305_selects_sbar_sites_per_unit_interface(kind):
+    g, d = cal.calibrate(_workload(kind, 0.99), kind, 3000)
+    ratio = d["sites_at"](0.305) / d["sites"]
+    lo, hi = d["interval"]
+    print(f"[calibrate] {kind}: Gamma* {g:.4f} in [{lo:.4f}, {hi:.4f}], sites at 0.305 / "
+          f"(Sbar A) = {ratio:.4f}", flush=True)
+    assert abs(ratio - 1.0) < 0.02
+    if kind == "flat":  # one gradient magnitude per row: a wide interval around 0.305
+        assert lo < 0.305 < hi
+    else:
+        assert abs(g - 0.305) < 0.01
+
+
+def test_gamma_varies_weakly_with_interface_thickness():
+    gs = {}
+    for beta in (0.99, 0.9, 0.8, 0.7):
+        gs[beta] = {k: cal.calibrate(_workload(k, beta), k, 3000)[0]
+                    for k in ("sphere", "hemisphere")}
+    print(f"[calibrate] Gamma*(beta): {gs}", flush=True)
+    for k in ("sphere", "hemisphere"):
+        vals = [gs[b][k] for b in gs]
+        assert max(vals) - min(vals) < 0.01, (k, vals)
+    for b in gs:  # the same threshold for both curved shapes
+        assert abs(gs[b]["sphere"] - gs[b]["hemisphere"]) < 0.005
