@@ -215,6 +215,115 @@ __device__ __forceinline__ void adj_node(const Phys<double>& P, double rho, doub
     lamF_o[2] = dF[2] + (sF + aFn) * F[2];
 }
 
+// The same transposed Jacobian at unit relaxation times (1/tau = 1 everywhere), arranged by
+// weight class k (rest, axis, diagonal).  Every accumulation above is linear in the inputs
+// (mus_i, etas_i) with coefficients that depend on the direction only through its class and
+// through c_i.u and c_i.F, so each direction adds into a few per-class sums
+//     X0 = sum x2,  E1 = sum etas Fc,  EV = sum etas c,  XV = sum x2 Fc c,  X2 = sum x2 Fc^2,
+//     XC = sum x2 (3 + 9 cu) c        (x2 = mus + rho^N etas, Fc = c.F, cu = c.u)
+// and the class coefficients are applied once per node.  Same outputs as adj_node<Q, true>.
+template <int Q, class In>
+__device__ __forceinline__ void adj_node_unit(const Phys<double>& P, double rho, double rN,
+                                              const double (&u)[3], const double (&F)[3],
+                                              double aF1n, In in, double& drN_o, double& drho_o,
+                                              double (&dj_o)[3], double (&lamF_o)[3]) {
+    constexpr int D = Lat<Q>::D;
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const double pr = 0.5 * (1.0 + rN), pb = 0.5 * (1.0 - rN);
+    const double abar = pr * P.alpha_r + pb * P.alpha_b;
+    const double F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    const bool hg = F2 > 0.0;
+    const double Fn = hg ? sqrt(F2) : 0.0;
+    const double iF = hg ? 1.0 / Fn : 0.0;
+    const double fade = Fn >= 2e-5 ? 1.0 : (Fn > 1e-5 ? Fn * 1e5 - 1.0 : 0.0);
+    const double dfade = (Fn > 1e-5 && Fn < 2e-5) ? 1e5 : 0.0;
+    const double kp = 2.25 * P.sigma;
+    const double sep = 0.5 * P.beta * (1.0 - rN * rN) * rho;
+    // class constants: k = 0 rest, 1 axis, 2 diagonal
+    constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;
+    double t[3], base[3], wr[3], pf[3], kc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = k == 0 ? 0 : (k == 1 ? i1 : i2);
+        const double W = weight<Q>(i);
+        t[k] = restA<Q>(i) + restB<Q>(i) * abar;
+        wr[k] = rho * W;
+        base[k] = rho * t[k] - 1.5 * wr[k] * uu;
+        pf[k] = kp * W * iF;
+        kc[k] = kp * pertC<Q>(i) * Fn;
+    }
+    double drN = 0.0, Sxf = 0.0;
+    double X0[3] = {0.0, 0.0, 0.0}, E1[3] = {0.0, 0.0, 0.0}, X2[3] = {0.0, 0.0, 0.0};
+    double EV[3][3] = {}, XV[3][3] = {}, XC[3][3] = {};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int k = norm2<Q>(i);
+        const int c[3] = {Lat<Q>::cx[i], Lat<Q>::cy[i], Lat<Q>::cz[i]};
+        double mus, etas;
+        in(i, mus, etas);
+        const double x2 = mus + rN * etas;
+        X0[k] += x2;
+        if (k == 0) {
+            const double feq = base[0];
+            drN += (feq - kc[0]) * etas;
+            Sxf += x2 * feq;
+            continue;
+        }
+        double cu = 0.0, Fc = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (c[a]) {
+                cu += c[a] * u[a];
+                Fc += c[a] * F[a];
+            }
+        const double feq = base[k] + wr[k] * cu * (3.0 + 4.5 * cu);
+        drN += (feq + pf[k] * Fc * Fc - kc[k]) * etas;
+        Sxf += x2 * feq;
+        E1[k] += etas * Fc;
+        const double xf = x2 * Fc;
+        X2[k] += xf * Fc;
+        const double xc = x2 * (3.0 + 9.0 * cu);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            if (c[a]) {
+                EV[k][a] += c[a] * etas;
+                XV[k][a] += c[a] * xf;
+                XC[k][a] += c[a] * xc;
+            }
+    }
+    // class coefficients
+    double dsep = 0.0, dab = 0.0, sF = 0.0, dF[3] = {0.0, 0.0, 0.0}, du[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = k == 0 ? 0 : (k == 1 ? i1 : i2);
+        const double il = inv_len<Q>(i), B = restB<Q>(i), C = pertC<Q>(i);
+        const double cw = iF * fade * il;
+        dsep += cw * t[k] * E1[k];
+        dab += sep * B * cw * E1[k] + rho * B * X0[k];
+        sF += sep * t[k] * il * (dfade * iF * iF - fade * iF * iF * iF) * E1[k] -
+              pf[k] * iF * iF * X2[k] - kp * C * iF * X0[k];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dF[a] += sep * t[k] * cw * EV[k][a] + 2.0 * pf[k] * XV[k][a];
+            du[a] += wr[k] * (XC[k][a] - 3.0 * u[a] * X0[k]);
+        }
+    }
+    double drho_p = Sxf / rho;
+    drN += 0.5 * (P.alpha_r - P.alpha_b) * dab;
+    drN += dsep * (-P.beta * rN * rho);
+    drho_p += dsep * 0.5 * P.beta * (1.0 - rN * rN);
+    dj_o[0] = du[0] / rho;
+    dj_o[1] = du[1] / rho;
+    dj_o[2] = du[2] / rho;
+    drho_p -= (du[0] * u[0] + du[1] * u[1] + du[2] * u[2]) / rho;
+    drN_o = drN;
+    drho_o = drho_p;
+    const double aFn = aF1n * iF;
+    lamF_o[0] = dF[0] + (sF + aFn) * F[0];
+    lamF_o[1] = dF[1] + (sF + aFn) * F[1];
+    lamF_o[2] = dF[2] + (sF + aFn) * F[2];
+}
+
 // General relaxation times: recompute from the stored populations.
 template <int Q, typename S, typename M>
 __global__ __launch_bounds__(kTPBX) void k_adj_local(
@@ -292,7 +401,7 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     F[1] *= 3.0;
     F[2] *= 3.0;
     double drN, drho, dj[3], lf[3];
-    adj_node<Q, true>(
+    adj_node_unit<Q>(
         P, rho, rN, u, F, aF1[n],
         [&](int i, double& mus, double& etas) {
             const long long xn = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]] +
@@ -304,7 +413,7 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
             mus = m;
             etas = ab1[g.N + xn];
         },
-        [](int) { return 0.0; }, [](int, double) {}, drN, drho, dj, lf);
+        drN, drho, dj, lf);
     mu0[n] = drho;
     mu0[g.N + n] = dj[0];
     mu0[2 * g.N + n] = dj[1];
