@@ -95,6 +95,10 @@ typedef struct ora_ctx {
     /* height-dependent flux (Eq. heated): active when hf_every > 0 */
     long long hf_every;
     double hf_phi, hf_K, hf_hs;
+    /* pressure outlets for the blue component at the ends of the last axis (Sec. III, density
+       contrast): out_lo, out_hi switch the planes at index 0 and the last index */
+    int out_lo, out_hi;
+    double out_rho;
 } ora_ctx;
 
 /* ------------------------------------------------------------------ lattices */
@@ -399,6 +403,53 @@ static int site_of(ora_ctx* s, long long n) {
     return fabs((rr - rb) / (rr + rb)) < s->p.gamma;
 }
 
+/* Pressure outlet (Zou and He) for the blue component on one end plane of the last lattice
+ * axis a (z for D3Q19, y for D2Q9); hi = 1 for the plane at the last index (outward normal
+ * +a), 0 for index 0 (outward normal -a).  The populations entering through the plane
+ * (c_i . n = -1) are unknown after streaming.  With the blue density held at out_rho and no
+ * tangential velocity:
+ *   u_n = (sum_{c.n=0} f + 2 sum_{c.n=1} f) / rho - 1                       (normal velocity)
+ *   f_i = f_opp(i) - 6 W_i rho u_n - sum_t c_it N_t,  N_t = (1/2) sum_{c.n=0} f_j c_jt
+ * (the odd part of the equilibrium, 6 W_i rho c_i.u, is the same for every alpha; N_t removes
+ * the tangential momentum, two unknowns have c_it != 0 per tangential axis t).  No red fluid
+ * enters: its unknown populations are 0. */
+static void outlet_plane(ora_ctx* s, int hi) {
+    const ora_lattice* L = &s->L;
+    const int Q = L->Q, a = L->D == 3 ? 2 : 1;
+    const int sgn = hi ? 1 : -1;
+    const long long nx = s->p.nx, ny = s->p.ny, nz = s->p.nz;
+    const long long idx = hi ? (a == 2 ? nz : ny) - 1 : 0;
+    for (long long z = 0; z < nz; ++z)
+        for (long long y = 0; y < ny; ++y)
+            for (long long x = 0; x < nx; ++x) {
+                if ((a == 2 ? z : y) != idx) continue;
+                const long long n = x + nx * (y + ny * z);
+                if (is_solid(s, n)) continue;
+                double s0 = 0.0, s1 = 0.0, N[3] = {0.0, 0.0, 0.0};
+                for (int i = 0; i < Q; ++i) {
+                    const int cn = sgn * L->c[i][a];
+                    const double f = F(s, 1, i)[n];
+                    if (cn == 0) {
+                        s0 += f;
+                        for (int t = 0; t < 3; ++t)
+                            if (t != a) N[t] += 0.5 * f * L->c[i][t];
+                    } else if (cn == 1) {
+                        s1 += f;
+                    }
+                }
+                const double rho = s->out_rho;
+                const double un = (s0 + 2.0 * s1) / rho - 1.0;
+                for (int i = 0; i < Q; ++i) {
+                    if (sgn * L->c[i][a] != -1) continue;
+                    double f = F(s, 1, L->opp[i])[n] - 6.0 * L->W[i] * rho * un;
+                    for (int t = 0; t < 3; ++t)
+                        if (t != a) f -= L->c[i][t] * N[t];
+                    F(s, 1, i)[n] = f;
+                    F(s, 0, i)[n] = 0.0;
+                }
+            }
+}
+
 static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* mask_out) {
     const ora_lattice* L = &s->L;
     const int Q = L->Q;
@@ -483,7 +534,8 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
         s->fmag[n] = Fn; /* carried to the next step's site selection */
     }
 
-    /* step 6: streaming (pull form), halfway bounce-back from solid neighbours */
+    /* step 6: streaming (pull form), halfway bounce-back from solid neighbours; then the
+       populations that enter through an outlet plane */
     for (long long n = 0; n < s->N; ++n) {
         for (int i = 0; i < Q; ++i) {
             if (is_solid(s, n)) {
@@ -496,6 +548,8 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
                 F(s, k, i)[n] = is_solid(s, src) ? FP(s, k, L->opp[i])[n] : FP(s, k, i)[src];
         }
     }
+    if (s->out_lo) outlet_plane(s, 0);
+    if (s->out_hi) outlet_plane(s, 1);
     s->step += 1;
 }
 
@@ -552,6 +606,16 @@ int ora_step(ora_ctx* s, long long nsteps, unsigned char* mask_log, const unsign
         if (s->hf_every > 0 && s->step % s->hf_every == 0) height_flux(s);
         one_step(s, mask_in ? mask_in + t * s->N : NULL, mask_log ? mask_log + t * s->N : NULL);
     }
+    return 0;
+}
+
+/* Pressure outlets for the blue component (see outlet_plane): lo, hi switch the planes at
+ * the ends of the last lattice axis; rho_out > 0 is the blue density held there. */
+int ora_set_outlet(ora_ctx* s, int lo, int hi, double rho_out) {
+    if ((lo || hi) && !(rho_out > 0.0 && isfinite(rho_out))) return 1;
+    s->out_lo = lo != 0;
+    s->out_hi = hi != 0;
+    s->out_rho = rho_out;
     return 0;
 }
 

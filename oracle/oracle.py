@@ -61,6 +61,7 @@ def lib():
         L.ora_set_height_flux.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double,
                                           C.c_longlong]
         L.ora_get_phi_field.argtypes = [C.c_void_p, dp]
+        L.ora_set_outlet.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double]
         L.ora_fields.argtypes = [C.c_void_p, dp, dp, dp, dp, dp]
         L.ora_observables.argtypes = [C.c_void_p, P(OraObs)]
         L.ora_tables.argtypes = [C.c_int, dp, dp, dp, dp, P(C.c_int), P(C.c_int), dp]
@@ -155,6 +156,11 @@ class Oracle:
         heated), refreshed every `every` steps; every <= 0 switches it off."""
         if lib().ora_set_height_flux(self._ctx, phi_s, K, h_scale, every) != 0:
             raise ValueError("invalid height-flux parameters")
+
+    def set_outlet(self, lo, hi, rho_out):
+        """Blue pressure outlets on the end planes of the last lattice axis."""
+        if lib().ora_set_outlet(self._ctx, int(bool(lo)), int(bool(hi)), rho_out) != 0:
+            raise ValueError("invalid outlet parameters")
 
     def phi_field(self):
         out = np.empty(self.shape)
