@@ -217,6 +217,18 @@ cge_status cge_set_site_threshold(cge_ctx* ctx, double gamma, double kappa);
 cge_status cge_set_height_flux(cge_ctx* ctx, double phi_s, double K, double h_scale,
                                long long every);
 
+/* Pressure outlets for the blue component (Zou and He; Sec. III, density contrast) on the end
+ * planes of the last lattice axis (z for D3Q19, y for D2Q9): lo switches the plane at index 0,
+ * hi the plane at the last index.  At an outlet node the populations entering through the
+ * plane are replaced by those that hold the blue density at rho_out with no tangential
+ * velocity (normal velocity from the known populations); no red fluid enters (its entering
+ * populations are 0).  The values are taken at once for the current state, after every step,
+ * and after cge_init_equilibrium and cge_set_populations (cge_load_state restores a state as
+ * saved).  Solid nodes on a plane are left alone.  lo = hi = 0 switches the outlets off.
+ * CGE_EINVAL for rho_out <= 0 or not finite, or fewer than 3 planes along the axis.  The
+ * adjoint returns CGE_EUNSUPPORTED while outlets are on. */
+cge_status cge_set_outlet(cge_ctx* ctx, int lo, int hi, double rho_out);
+
 /* Restore the step counter and the FP64 sink bookkeeping (checkpoint resume). */
 cge_status cge_set_counters(cge_ctx* ctx, long long step, long long site_steps,
                             double sink_total);

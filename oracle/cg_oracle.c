@@ -328,6 +328,8 @@ void ora_recompute_fmag(ora_ctx* s) {
 }
 
 /* f_i^k = rho_k [t_i(alpha_k) + W_i (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]  (Eq. feq per component) */
+static void apply_outlets(ora_ctx* s);
+
 int ora_init_equilibrium(ora_ctx* s, const double* rho_r, const double* rho_b, const double* u) {
     int Q = s->L.Q;
     for (long long n = 0; n < s->N; ++n) {
@@ -351,11 +353,13 @@ int ora_init_equilibrium(ora_ctx* s, const double* rho_r, const double* rho_b, c
     s->step = 0;
     s->site_steps = 0;
     s->sink_total = 0.0;
+    apply_outlets(s);
     return 0;
 }
 
 int ora_set_populations(ora_ctx* s, const double* f) {
     memcpy(s->f, f, 2ULL * s->L.Q * s->N * sizeof(double));
+    apply_outlets(s);
     return 0;
 }
 int ora_get_populations(const ora_ctx* s, double* f) {
@@ -448,6 +452,13 @@ static void outlet_plane(ora_ctx* s, int hi) {
                     F(s, 0, i)[n] = 0.0;
                 }
             }
+}
+
+/* The outlet planes hold their values in every state: after streaming, and whenever a
+ * state is set or the outlets are switched on. */
+static void apply_outlets(ora_ctx* s) {
+    if (s->out_lo) outlet_plane(s, 0);
+    if (s->out_hi) outlet_plane(s, 1);
 }
 
 static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* mask_out) {
@@ -548,8 +559,7 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
                 F(s, k, i)[n] = is_solid(s, src) ? FP(s, k, L->opp[i])[n] : FP(s, k, i)[src];
         }
     }
-    if (s->out_lo) outlet_plane(s, 0);
-    if (s->out_hi) outlet_plane(s, 1);
+    apply_outlets(s);
     s->step += 1;
 }
 
@@ -613,9 +623,11 @@ int ora_step(ora_ctx* s, long long nsteps, unsigned char* mask_log, const unsign
  * the ends of the last lattice axis; rho_out > 0 is the blue density held there. */
 int ora_set_outlet(ora_ctx* s, int lo, int hi, double rho_out) {
     if ((lo || hi) && !(rho_out > 0.0 && isfinite(rho_out))) return 1;
+    if ((lo || hi) && (s->L.D == 3 ? s->p.nz : s->p.ny) < 3) return 1;
     s->out_lo = lo != 0;
     s->out_hi = hi != 0;
     s->out_rho = rho_out;
+    apply_outlets(s);  /* the current state takes the outlet values at once */
     return 0;
 }
 

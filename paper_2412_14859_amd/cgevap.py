@@ -22,7 +22,8 @@ ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
            "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
            "cge_load_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
-           "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_counters",
+           "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_outlet",
+           "cge_set_counters",
            "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
@@ -87,6 +88,7 @@ def lib():
         L.cge_reset_sites.argtypes = [vp]
         L.cge_set_site_threshold.argtypes = [vp, C.c_double, C.c_double]
         L.cge_set_height_flux.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_longlong]
+        L.cge_set_outlet.argtypes = [vp, C.c_int, C.c_int, C.c_double]
         L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
         L.cge_step.argtypes = [vp, C.c_longlong]
         L.cge_observables.argtypes = [vp, P(CgeObs)]
@@ -259,6 +261,11 @@ class Simulation:
         every <= 0 switches it off.  Writes the bound flux field (phi_field=...)."""
         self._check(lib().cge_set_height_flux(self._ctx, float(phi_s), float(K),
                                               float(h_scale), int(every)))
+
+    def set_outlet(self, lo, hi, rho_out=1.0):
+        """Blue pressure outlets on the end planes of the last lattice axis."""
+        self._check(lib().cge_set_outlet(self._ctx, int(bool(lo)), int(bool(hi)),
+                                         float(rho_out)))
 
     def set_site_threshold(self, gamma, kappa=0.0):
         self._check(lib().cge_set_site_threshold(self._ctx, float(gamma), float(kappa)))

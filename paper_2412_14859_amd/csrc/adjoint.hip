@@ -601,8 +601,8 @@ cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ck
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps < 1 || K < 1 || !ckpt) return fail(c, CGE_EINVAL, "nsteps >= 1, K >= 1, ckpt");
-    if (c->hf_every > 0)
-        return fail(c, CGE_EUNSUPPORTED, "the adjoint does not support the height flux");
+    if (c->hf_every > 0 || c->out_lo || c->out_hi)
+        return fail(c, CGE_EUNSUPPORTED, "the adjoint supports neither the height flux nor outlets");
     // at unit tau the backward recomputes with the split step, so the forward uses it too and
     // the recomputed trajectory is the forward's bit for bit
     const bool split = unit_tau(&c->p) && !c->flags;
@@ -625,8 +625,8 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
     if (nsteps < 1 || K < 1 || !ckpt || !seg || !work || (!dL_drhoN && !dL_drho) || !grad_phi)
         return fail(c, CGE_EINVAL, "missing argument");
     if (c->flags) return fail(c, CGE_EUNSUPPORTED, "adjoint needs a domain without solid nodes");
-    if (c->hf_every > 0)
-        return fail(c, CGE_EUNSUPPORTED, "the adjoint does not support the height flux");
+    if (c->hf_every > 0 || c->out_lo || c->out_hi)
+        return fail(c, CGE_EUNSUPPORTED, "the adjoint supports neither the height flux nor outlets");
     if (c->p.site_rule == CGE_SITE_PHASE_LT)
         return fail(c, CGE_EUNSUPPORTED, "adjoint supports the gradient site rules only");
     const long long N = c->g.N;

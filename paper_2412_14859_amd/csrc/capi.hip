@@ -253,14 +253,16 @@ cge_status cge_init_equilibrium(cge_ctx* c, const double* rho_r, const double* r
     if (!rho_r || !rho_b) return fail(c, CGE_EINVAL, "rho_r and rho_b required");
     if (cge_status s = init_equilibrium(c, rho_r, rho_b, u)) return s;
     if (cge_status s = reset_sites(c)) return s;
-    return zero_counters(c);
+    if (cge_status s = zero_counters(c)) return s;
+    return apply_outlets(c);
 }
 
 cge_status cge_set_populations(cge_ctx* c, const double* f) {
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (!f) return fail(c, CGE_EINVAL, "f is NULL");
-    return set_populations(c, f);
+    if (cge_status s = set_populations(c, f)) return s;
+    return apply_outlets(c);
 }
 
 cge_status cge_get_populations(cge_ctx* c, double* f) {
@@ -312,6 +314,21 @@ cge_status cge_reset_sites(cge_ctx* c) {
     return reset_sites(c);
 }
 
+cge_status cge_set_outlet(cge_ctx* c, int lo, int hi, double rho_out) {
+    if (!c) return CGE_EINVAL;
+    if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
+    if (lo || hi) {
+        if (!is_fin(rho_out) || !(rho_out > 0.0))
+            return fail(c, CGE_EINVAL, "outlet density must be finite and positive");
+        if ((c->Q == 19 ? c->g.nz : c->g.ny) < 3)
+            return fail(c, CGE_EINVAL, "outlets need at least 3 planes along the last axis");
+    }
+    c->out_lo = lo ? 1 : 0;
+    c->out_hi = hi ? 1 : 0;
+    c->out_rho = rho_out;
+    return apply_outlets(c);
+}
+
 cge_status cge_set_height_flux(cge_ctx* c, double phi_s, double K, double h_scale,
                                long long every) {
     if (!c) return CGE_EINVAL;
@@ -361,14 +378,22 @@ cge_status cge_step(cge_ctx* c, long long nsteps) {
     if (nsteps < 0) return fail(c, CGE_EINVAL, "nsteps must be >= 0");
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps == 0) return CGE_OK;
-    if (c->hf_every <= 0) return run_steps(c, nsteps);
-    // height flux: refresh the field before every step whose counter is a multiple of every
+    const bool outlets = c->out_lo || c->out_hi;
+    if (c->hf_every <= 0 && !outlets) return run_steps(c, nsteps);
+    // height flux: refresh the field before every step whose counter is a multiple of every;
+    // outlets: take the outlet values after every step
     for (long long done = 0; done < nsteps;) {
-        const long long phase = c->step % c->hf_every;
-        if (phase == 0)
-            if (cge_status s = height_flux(c)) return s;
-        const long long n = std::min(c->hf_every - phase, nsteps - done);
+        long long n = nsteps - done;
+        if (c->hf_every > 0) {
+            const long long phase = c->step % c->hf_every;
+            if (phase == 0)
+                if (cge_status s = height_flux(c)) return s;
+            n = std::min(c->hf_every - phase, n);
+        }
+        if (outlets) n = 1;
         if (cge_status s = run_steps(c, n)) return s;
+        if (outlets)
+            if (cge_status s = apply_outlets(c)) return s;
         done += n;
     }
     return CGE_OK;

@@ -36,6 +36,9 @@ struct cge_ctx {
     double* obs_part = nullptr;     // [CGE_NOBS][obs_blocks]
     long long obs_blocks = 0;
     double* obs_res = nullptr;      // [CGE_NOBS + 2] final values (device)
+    // blue pressure outlets on the end planes of the last axis
+    int out_lo = 0, out_hi = 0;
+    double out_rho = 1.0;
     // height-dependent flux (active when hf_every > 0)
     long long hf_every = 0;
     double hf_phi = 0.0, hf_K = 1.0, hf_hs = 1.0;
@@ -88,6 +91,8 @@ cge_status fields(cge_ctx* c, double* rr, double* rb, double* u, double* rhoN);
 
 // flux field from the column heights of the current state (flux.hip)
 cge_status height_flux(cge_ctx* c);
+// outlet values in the current state (outlet.hip); no-op without outlets
+cge_status apply_outlets(cge_ctx* c);
 
 // adjoint workspace size
 size_t adjoint_bytes(const cge_params* p);
