@@ -126,7 +126,7 @@ def _base(Q, shape, **kw):
     return p
 
 
-def workload(name, shape=None, radius=None, phi=None, seed=None):
+def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
     """Workload dict: params (lattice + physics), rho_r, rho_b, solid (or None),
     phi_field (or None), steps.  shape/radius downscale a workload; phi overrides the flux.
 
@@ -135,7 +135,10 @@ def workload(name, shape=None, radius=None, phi=None, seed=None):
     'sphere3d' (D3Q19 256^3 sphere R 64), 'sessile3d' (D3Q19 384x384x192 cap on a wall,
     density ratio 10, space-dependent flux), 'adjoint2d' (D2Q9 512^2 drop R 96 with a
     seeded flux field and target shape), 'hemisphere3d' / 'hemisphere2d' (drop on a wall for
-    the height-dependent flux, D3Q19 192^3 R 66 / D2Q9 384x192 R 66)."""
+    the height-dependent flux, D3Q19 192^3 R 66 / D2Q9 384x192 R 66), 'contrast3d' (D3Q19
+    192^3 drop R 44 at density ratio `ratio`, blue outlets on both z planes) and
+    'contrast_flat3d' (D3Q19 160^3 film of height 80 on a wall at z = 0, 1, blue outlet on
+    the top plane)."""
     if name == "drop2d":
         shape = shape or (1, 128, 128)
         R = radius or 32.0 * shape[2] / 128.0
@@ -233,6 +236,38 @@ def workload(name, shape=None, radius=None, phi=None, seed=None):
         w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": solid,
              "phi_field": np.full(shape, p["phi"]), "radius": R, "phi_s": 1e-3,
              "h_scale": R}
+    elif name in ("contrast3d", "contrast_flat3d"):
+        # density contrast (Sec. III, density contrast): red initialised at gamma, blue at 1,
+        # beta 0.99, sigma 0.1, unit relaxation times, phi = 3e-3; the blue component leaves
+        # through pressure outlets (rho_b = 1) on the end planes of z during evaporation.
+        # Gamma: 0.32 (gamma 2) and 0.33 (gamma 4) for the sphere; for the film the paper
+        # gives only |Gamma_flat - Gamma_sphere| = 0.02 and 0.04.  Taken below the sphere's:
+        # the film then follows h0 - phi t / rho0, with the opposite sign it lags far behind
+        g = float(ratio or 2.0)
+        flat = name == "contrast_flat3d"
+        shape = shape or ((160, 160, 160) if flat else (192, 192, 192))
+        nz, ny, nx = shape
+        gsph = {2.0: 0.32, 4.0: 0.33}.get(g, 0.32)
+        gam = gsph - {2.0: 0.02, 4.0: 0.04}.get(g, 0.02) if flat else gsph
+        p = _base(19, shape, sigma=0.1, beta=0.99, rho_in=(g, 1.0), phi=3e-3, gamma=gam)
+        if flat:
+            # the wall is two layers thick (z = 0, 1; surface at z = 1.5): z = 0 is also the
+            # periodic neighbour of the outlet plane, and with a single layer its wetting value
+            # would average the film with the blue at the outlet, a false gradient under the film
+            h0 = 80.0 * nz / 160.0
+            d = flat_distance(shape, h0 + 1.5, axis=0)
+            rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
+            solid = wall_layers(shape, 0, [0, 1])
+            rr = np.where(solid == 1, 0.0, rr)
+            rb = np.where(solid == 1, 0.0, rb)
+            w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": solid, "phi_field": None,
+                 "height": h0, "outlet": (False, True)}
+        else:
+            R = radius or 44.0 * nx / 192.0
+            d = sphere_distance(shape, (nx / 2, ny / 2, nz / 2), R)
+            rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
+            w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": None, "phi_field": None,
+                 "radius": R, "outlet": (True, True)}
     else:
         raise KeyError(name)
     if phi is not None:

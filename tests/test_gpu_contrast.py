@@ -1,0 +1,83 @@
+"""Density contrast with blue outlets (Sec. III, density contrast), downscaled: an evaporating
+drop and film at density ratio 2 follow the constant-density laws R0 - phi t / rho0 and
+h0 - phi t / rho0.  The full-size runs (192^3 drop R0 = 44, 160^3 film h0 = 80, ratios 2 and
+4, both fluxes) are `bench.py --contrast-benchmark`."""
+import numpy as np
+import pytest
+
+from paper_2412_14859_amd import analytic, cgevap, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+def _evaporate(name, shape, phi, equil, flat):
+    w = inputs.workload(name, shape=shape, ratio=2.0)
+    p = dict(w["params"], phi=0.0)
+    sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                            phi_field=np.zeros(p["shape"]), precision="fp32s")
+
+    def position():
+        rr = sim.fields()["rho_r"]
+        x = analytic.film_height(rr, axis=0, solid_layers=2) if flat else \
+            analytic.sphere_radius(analytic.half_max_volume(rr))
+        return x, float(rr.max())
+
+    sim.step(equil)
+    x0, rho0 = position()
+    sim.set_counters()
+    sim.set_outlet(*w["outlet"], 1.0)
+    sim.phi_field.fill_(phi)
+    t_end = 0.85 * x0 * rho0 / phi
+    chunk = int(t_end / 20)
+    ts, xs = [0.0], [x0]
+    for k in range(1, 21):
+        sim.step(chunk)
+        ts.append(float(k * chunk))
+        xs.append(position()[0])
+    obs = sim.observables()
+    rb = sim.fields()["rho_b"]
+    sim.close()
+    ts, xs = np.array(ts), np.array(xs)
+    law = analytic.flat_height if flat else analytic.sphere_radius_constant
+    ref = law(ts, x0, phi, rho0)
+    tstar = ts * phi / (x0 * rho0)
+    return x0, rho0, tstar, xs, ref, obs, rb
+
+
+def test_drop_at_density_ratio_two_follows_the_radius_law():
+    """96^3, R0 = 22, phi = 3e-3, Gamma = 0.32: within 2 % of R0 - phi t / rho0 while
+    R/R0 >= 0.5 and 7 % while R/R0 >= 0.3 (1.4 % and 5.0 % measured).  Below R ~ 6 the drop
+    is about one interface width across at this size, and the comparison stops there, as
+    at full size (192^3, R0 = 44, t* up to 0.85: 0.2-1.0 % here, 0.17-1.1 % in the paper)."""
+    _flush("[contrast] drop 96^3 R0=22 ratio 2 phi 3e-3")
+    x0, rho0, tstar, xs, ref, obs, rb = _evaporate("contrast3d", (96, 96, 96), 3e-3, 2000,
+                                                   False)
+    err = np.abs(xs - ref) / ref
+    _flush(f"  R0 {x0:.3f} rho0 {rho0:.4f}; error by t*: " +
+           " ".join(f"{a:.2f}:{e:.4f}" for a, e in zip(tstar[::4], err[::4])) +
+           f"; max {err.max():.4f}")
+    assert 1.95 < rho0 < 2.1
+    assert np.all(np.diff(xs) < 0)
+    assert err[xs / x0 >= 0.5].max() < 0.02
+    assert err[xs / x0 >= 0.3].max() < 0.07
+    # the outlets hold the blue at 1: the surplus from the exchange has left
+    assert float(rb.max()) < 1.01
+
+
+def test_film_at_density_ratio_two_follows_the_height_law():
+    """Film 80 x 16 x 16 (h0 = 40, wall z = 0, 1, outlet at the top), phi = 3e-2,
+    Gamma = 0.30: within 8 % of h0 - phi t / rho0 up to t* = 0.85."""
+    _flush("[contrast] film 80x16x16 h0=40 ratio 2 phi 3e-2")
+    x0, rho0, tstar, xs, ref, obs, rb = _evaporate("contrast_flat3d", (80, 16, 16), 3e-2, 2000,
+                                                   True)
+    err = np.abs(xs - ref) / ref
+    _flush(f"  h0 {x0:.3f} rho0 {rho0:.4f}; error by t*: " +
+           " ".join(f"{a:.2f}:{e:.4f}" for a, e in zip(tstar[::4], err[::4])) +
+           f"; max {err.max():.4f}")
+    assert abs(x0 - 40.0) < 1.0
+    assert np.all(np.diff(xs) < 0)
+    assert err.max() < 0.08
