@@ -291,6 +291,85 @@ def contrast_benchmark(cases=((2.0, 3e-3), (2.0, 3e-2), (4.0, 3e-3), (4.0, 3e-2)
                                                 "4,0.03": [0.057, 0.171]}}
 
 
+def cap_benchmark(phis=(3e-3, 3e-4), gammas=(0.305, 0.29), n=192, precision="fp32s",
+                  equil=6000):
+    """Pinned cap on a cylindrical cavity (n^3, ring radii 50 / 53 and height 8 scaled by
+    n / 192), equilibrated without flux, then evaporating at flux phi.  Tracks the apex
+    height above the ring and the contact radius just above it, and compares the height with
+    h0 - 2 phi t / rho0 (and the Laplace-dependent law) at t* = t 2 phi / (h0 rho0) = 0.332
+    and 0.664 and at unpinning (the first sample with a / a0 <= 0.95).  The paper: 2.5 % and
+    8 % (phi 3e-3), 1.2 % and 7 % (phi 3e-4) at Gamma 0.305; 1.9 % and 0.7 % at unpinning
+    with Gamma 0.29."""
+    import numpy as np
+    import torch
+    from paper_2412_14859_amd import analytic, cgevap, inputs
+    out = []
+    for gam in gammas:
+        for phi in phis:
+            w = inputs.workload("cap3d", shape=(n, n, n))
+            p = dict(w["params"], phi=0.0, gamma=gam)
+            top, zp = w["cavity_top"], w["cavity_height"] + 1
+            sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                                    phi_field=np.zeros(p["shape"]), precision=precision)
+
+            def measure():
+                rr = sim.fields()["rho_r"]
+                return (analytic.cap_height(rr, top), analytic.contact_radius(rr, zp),
+                        float(rr.max()))
+
+            sim.step(equil)
+            h0, a0, rho0 = measure()
+            sim.set_counters()
+            sim.phi_field.fill_(phi)
+            te = h0 * rho0 / (2.0 * phi)
+            chunk = max(10, int(0.75 * te / 60))
+            ts, hs, as_, t = [0.0], [h0], [a0], 0
+            t0 = time.perf_counter()
+            while t + chunk <= 0.75 * te:
+                sim.step(chunk)
+                t += chunk
+                h, a, _ = measure()
+                ts.append(float(t))
+                hs.append(h)
+                as_.append(a)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            sim.close()
+            ts, hs, as_ = np.array(ts), np.array(hs), np.array(as_)
+            tstar = ts / te
+            lin = analytic.cap_height_constant(ts, h0, phi, rho0)
+            var = analytic.cap_height_variable(ts, h0, a0, phi, 1.0, p["sigma"])
+            err = np.abs(hs - lin) / lin
+            unp = np.nonzero(as_ / a0 <= 0.95)[0]
+            iu = int(unp[0]) if unp.size else None
+
+            def at(q):
+                return int(np.argmin(np.abs(tstar - q)))
+
+            rec = {"Gamma": gam, "phi": phi, "h0": round(h0, 3), "a0": round(a0, 3),
+                   "rho0": round(rho0, 4), "steps": t,
+                   "error_at_tstar_0.332": round(float(err[at(0.332)]), 4),
+                   "error_at_tstar_0.664": round(float(err[at(0.664)]), 4),
+                   "signed_error_at_tstar_0.332": round(float((hs - lin)[at(0.332)]
+                                                              / lin[at(0.332)]), 4),
+                   "unpinning_tstar": None if iu is None else round(float(tstar[iu]), 3),
+                   "error_at_unpinning": None if iu is None else round(float(err[iu]), 4),
+                   "max_error_variable_law_before_unpinning": round(float(
+                       (np.abs(hs - var) / var)[:iu if iu else None].max()), 4),
+                   "a_over_a0_at_tstar_0.5": round(float(as_[at(0.5)] / a0), 3),
+                   "mlups": round(n ** 3 * t / wall / 1e6, 1)}
+            print(f"cap benchmark {rec}", file=sys.stderr, flush=True)
+            out.append(rec)
+    return {"workload": f"D3Q19 {n}^3 cap pinned on a cylindrical cavity (ring radii "
+                        f"{50 * n / 192:.1f} / {53 * n / 192:.1f}, height "
+                        f"{max(round(8 * n / 192), 2)}), contact angle 120 deg at the start, "
+                        f"beta 0.99, sigma 0.1, tau 1, equilibration {equil} steps, {precision}",
+            "cases": out,
+            "paper": {"0.305,0.003": {"0.332": 0.025, "0.664": 0.08},
+                      "0.305,0.0003": {"0.332": 0.012, "0.664": 0.07},
+                      "0.29,0.003": {"unpinning": 0.019}, "0.29,0.0003": {"unpinning": 0.007}}}
+
+
 def copy_probe_gbs(nbytes=1 << 30, reps=5):
     """Achievable HBM bandwidth: the library's streaming copy kernel over nbytes, timed with
     events on torch's current stream (the stream the probe is launched on); read + write."""
@@ -343,6 +422,9 @@ def main():
     ap.add_argument("--no-legs", action="store_true", help="skip the FP64 and FP16S legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost legs")
+    ap.add_argument("--cap-benchmark", action="store_true",
+                    help="cap pinned on a cylindrical cavity vs the cap height law (runs instead "
+                         "of the bench line)")
     ap.add_argument("--contrast-benchmark", action="store_true",
                     help="density-contrast drop and film with blue outlets vs the radius and "
                          "height laws (runs instead of the bench line)")
@@ -359,6 +441,9 @@ def main():
     import torch
     from paper_2412_14859_amd import inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.cap_benchmark:
+        print(json.dumps(cap_benchmark()), flush=True)
+        return
     if args.contrast_benchmark:
         print(json.dumps(contrast_benchmark()), flush=True)
         return

@@ -14,6 +14,15 @@ Laws (lattice units, c_s^2 = 1/3, rho_b the surrounding blue density):
                                       = R0 - phi t / (gamma rho_b)            (Appendix)
   hemisphere with height flux:      dR/dt = (phi_S R0 / R) ln(K R0 / (R + K R0))
                                                                   (Sec. varying flux)
+  pinned cap, constant density:     h(t) = h0 - 2 phi t / rho0                (Sec. pinned cap)
+  pinned cap, Laplace-dependent density (contact radius a held):
+      h + c [ln((a^2 + h^2) / (a^2 + h0^2)) - a^4 / (a^2 + h^2)^2]
+        = h0 - 2 phi t / (gamma rho_b) - c a^4 / (a^2 + h0^2)^2,  c = 4 sigma / (3 c_s^2 rho_b)
+                                                                  (Appendix B)
+A cap's height is measured on the column through its axis from the top surface of the
+cavity ring to the half-maximum crossing; its contact radius is the radius of the disc of
+equal area to the part of the plane just above the ring where the red density exceeds half
+its maximum.
 """
 import math
 
@@ -97,3 +106,60 @@ def hemisphere_radius_height_flux(t, R0, phi_s, K):
     sol = solve_ivp(lambda _, r: [phi_s * R0 / r[0] * math.log(K * R0 / (r[0] + K * R0))],
                     (0.0, float(t[-1])), [R0], t_eval=t, method="RK45", rtol=1e-9, atol=1e-9)
     return sol.y[0]
+
+
+def cap_height(rho_r, top, centre=None):
+    """Apex height of a cap above the surface at z = top (between node layers): going up the
+    column through `centre` (x, y node indices; default the middle node), the last crossing
+    of half the red maximum, interpolated linearly, minus top."""
+    r = _np(rho_r).astype(np.float64)
+    nz, ny, nx = r.shape
+    cx, cy = centre if centre is not None else (nx // 2, ny // 2)
+    col = r[:, cy, cx]
+    half = 0.5 * r.max()
+    k = int(math.ceil(top))
+    while k + 1 < nz and col[k + 1] > half:
+        k += 1
+    if col[k] <= half or k + 1 >= nz:
+        return 0.0
+    frac = (col[k] - half) / (col[k] - col[k + 1])
+    return k + frac - top
+
+
+def contact_radius(rho_r, z):
+    """Radius of the disc of equal area to the nodes of plane z above half the red
+    maximum."""
+    if hasattr(rho_r, "detach"):
+        half = 0.5 * rho_r.max()
+        return math.sqrt(float((rho_r[z] > half).sum().item()) / math.pi)
+    r = np.asarray(rho_r, dtype=np.float64)
+    return math.sqrt(float((r[z] > 0.5 * r.max()).sum()) / math.pi)
+
+
+def cap_height_constant(t, h0, phi, rho0):
+    return h0 - 2.0 * phi * np.asarray(t, dtype=np.float64) / rho0
+
+
+def cap_height_variable(t, h0, a, phi, gamma, sigma, rho_b=1.0):
+    """Root h of the Laplace-dependent pinned-cap law for each t.  The left side
+    h + c [ln(a^2 + h^2) - a^4 / (a^2 + h^2)^2] increases with h, so the root on (0, h0] is
+    unique."""
+    from scipy.optimize import brentq
+    c = 4.0 * sigma / (3.0 * CS2 * rho_b)
+    a2 = a * a
+
+    def lhs(h):
+        return h + c * (math.log((a2 + h * h) / (a2 + h0 * h0)) - a2 * a2 / (a2 + h * h) ** 2)
+
+    out = []
+    for ti in np.atleast_1d(np.asarray(t, dtype=np.float64)):
+        rhs = h0 - 2.0 * phi * ti / (gamma * rho_b) - c * a2 * a2 / (a2 + h0 * h0) ** 2
+        if ti == 0:
+            out.append(h0)
+            continue
+        lo = 1e-9 * h0
+        if lhs(lo) > rhs:
+            out.append(0.0)  # evaporated
+            continue
+        out.append(brentq(lambda h: lhs(h) - rhs, lo, h0, xtol=1e-12 * h0))
+    return np.array(out)

@@ -138,7 +138,8 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
     the height-dependent flux, D3Q19 192^3 R 66 / D2Q9 384x192 R 66), 'contrast3d' (D3Q19
     192^3 drop R 44 at density ratio `ratio`, blue outlets on both z planes) and
     'contrast_flat3d' (D3Q19 160^3 film of height 80 on a wall at z = 0, 1, blue outlet on
-    the top plane)."""
+    the top plane), 'cap3d' (D3Q19 192^3 cap pinned on a cylindrical cavity, ring radii
+    50 / 53, height 8)."""
     if name == "drop2d":
         shape = shape or (1, 128, 128)
         R = radius or 32.0 * shape[2] / 128.0
@@ -268,6 +269,38 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
             rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
             w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": None, "phi_field": None,
                  "radius": R, "outlet": (True, True)}
+    elif name == "cap3d":
+        # pinned spherical cap (Sec. III, pinned cap): a cylindrical cavity (a ring of solid
+        # nodes, inner radius 50, outer radius 53, height 8) on the bottom wall, filled with
+        # red, and a spherical cap on it whose edge sits on the ring's outer rim with a contact
+        # angle of 120 degrees; unit density ratio, beta 0.99, sigma 0.1, tau 1, walls at both
+        # ends of z.  Downscaled, the ring keeps a thickness of at least 1.5 nodes and a height
+        # of at least 2; `radius` overrides the outer radius
+        shape = shape or (192, 192, 192)
+        nz, ny, nx = shape
+        s = min(nx, ny) / 192.0
+        r_out = radius or 53.0 * s
+        r_in = r_out - max(3.0 * s, 1.5)
+        H = max(int(round(8.0 * s)), 2)
+        theta = math.radians(120.0)
+        Rs = r_out / math.sin(theta)
+        hc = Rs * (1.0 - math.cos(theta))
+        top = H + 0.5  # the ring's top surface
+        zc = top + hc - Rs
+        p = _base(19, shape, sigma=0.1, beta=0.99)
+        z, y, x = grid(shape)
+        r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2)
+        dsph = Rs - np.sqrt(r * r + (z - zc) ** 2)
+        d = np.where(z > top, dsph, np.where(r < r_in, np.maximum(dsph, r_in - r),
+                                             np.minimum(dsph, r_out - r)))
+        rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
+        ring = (z >= 1) & (z <= H) & (r >= r_in) & (r <= r_out)
+        solid = np.where(ring, 1, wall_layers(shape, 0, [0, nz - 1])).astype(np.uint8)
+        rr = np.where(solid == 1, 0.0, rr)
+        rb = np.where(solid == 1, 0.0, rb)
+        w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": solid, "phi_field": None,
+             "radius": r_out, "inner_radius": r_in, "cavity_height": H, "cavity_top": top,
+             "cap_height": hc}
     else:
         raise KeyError(name)
     if phi is not None:

@@ -62,3 +62,41 @@ def test_height_flux_ode_with_a_large_K_is_the_linear_law():
     t = np.linspace(0.0, 1e9, 5)
     R = analytic.hemisphere_radius_height_flux(t, R0, phi_s, K)
     assert np.allclose(R, R0 - phi_s / K * t, rtol=1e-6)
+
+
+def test_pinned_cap_law_solves_its_equation_and_reduces_to_the_linear_law():
+    h0, a, phi, sigma = 90.0, 53.0, 3e-3, 0.1
+    t = np.linspace(0.0, 0.7 * h0 / (2 * phi), 9)
+    h = analytic.cap_height_variable(t, h0, a, phi, 1.0, sigma)
+    c = 4.0 * sigma
+    lhs = h + c * (np.log((a * a + h * h) / (a * a + h0 * h0)) - a ** 4 / (a * a + h * h) ** 2)
+    rhs = h0 - 2 * phi * t - c * a ** 4 / (a * a + h0 * h0) ** 2
+    assert np.allclose(lhs, rhs, atol=1e-9)
+    lin = analytic.cap_height_constant(t, h0, phi, 1.0)
+    assert np.allclose(analytic.cap_height_variable(t, h0, a, phi, 1.0, 0.0), lin, rtol=1e-10)
+    # low curvature: the Laplace correction stays below 3 % up to t* = 0.7 (the paper finds
+    # it insignificant before unpinning, t* ~ 0.63)
+    assert np.max(np.abs(h - lin) / lin) < 0.03
+
+
+def test_cap_height_and_contact_radius_of_the_initial_cap():
+    w = inputs.workload("cap3d", shape=(96, 96, 96))
+    rr = w["rho_r"]
+    h = analytic.cap_height(rr, w["cavity_top"])
+    assert abs(h - w["cap_height"]) < 0.1, (h, w["cap_height"])
+    # just above the ring the cap (contact angle 120 degrees) is wider than the rim by
+    # sqrt(Rs^2 - (zc - z)^2) - a at z = top + 1/2
+    a = w["radius"]
+    Rs = a / math.sin(math.radians(120.0))
+    zc = w["cavity_top"] + w["cap_height"] - Rs
+    z = w["cavity_height"] + 1
+    expect = math.sqrt(Rs * Rs - (zc - z) ** 2)
+    assert abs(analytic.contact_radius(rr, z) - expect) < 0.15
+    # the ring: solid between the radii up to the cavity height, and closed all round
+    s = w["solid"]
+    ring = s[1:w["cavity_height"] + 1].astype(bool)
+    assert ring.all(axis=0).sum() == ring.any(axis=0).sum()
+    n = 96
+    row = s[1, n // 2, :]
+    inside = np.nonzero(row)[0]
+    assert len(inside) >= 2 * 2  # at least two nodes thick on each side

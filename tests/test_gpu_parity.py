@@ -18,6 +18,9 @@ CASES = {
     "d2q9_adjoint_field": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3)),
     "d3q19_grad": ("sphere3d", (14, 16, 70), dict(radius=5.0, phi=1e-3)),
     "d3q19_walls_ratio": ("sessile3d", (14, 18, 70), dict(radius=6.0, phi=1e-3)),
+    # a ring of solid nodes on the bottom wall (the pinned-cap cavity): inner corners, an
+    # enclosed pocket of fluid, and a cap edge on the rim
+    "d3q19_cavity": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
     # several z-chunks and a ragged last tile in x (70 = 64 + 6) and y (10 = 4 + 4 + 2)
     "d3q19_chunks": ("sphere3d", (40, 10, 70), dict(radius=4.5, phi=1e-3)),
     # relaxation times other than 1 (the general collision path of the fused step)
