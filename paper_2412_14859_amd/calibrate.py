@@ -9,6 +9,18 @@ gradient magnitude over the fluid nodes, k = round(Sbar A).
 The harness equilibrates the drop on the GPU without flux (the soft site rule carries ||F||
 per node, so the gradient field is read from the carried site data), then takes that
 threshold on the host.  Geometry measures: `interface_measure`.
+
+`calibrate_dynamic` matches the rates over an evaporating run instead, which is the paper's
+criterion: the mass the sink removes over the run, (phi / Sbar) times the site count summed
+over the steps, must equal phi times the interface measure summed over the steps.  A moving
+interface crosses the lattice, so the site count at a fixed Gamma changes as it moves (for a
+flat film the static count is degenerate).  The run uses soft sites of small width, which
+act as hard sites at a starting threshold while carrying ||F|| of every node; at each of a
+set of evenly spaced snapshots it records ||F|| and the interface measure A(t) from the
+half-maximum contour.  Summed over the snapshots, the site count at Gamma is the number of
+pooled gradient values above Gamma, so the calibrated Gamma is the threshold with
+Sbar * sum_t A(t) pooled values above it.  The trajectory depends weakly on the threshold it
+ran with; `iterations` > 1 runs again from the previous result.
 """
 import math
 
@@ -83,3 +95,82 @@ def calibrate(workload, kind, steps, sbar=3.0, precision="fp64", radius_from_vol
     return 0.5 * (lo + hi), {"sites": k, "measure": A, "radius": R, "volume": v,
                              "interval": (lo, hi),
                              "sites_at": lambda g: int((fmag[fluid] > g).sum())}
+
+
+def gamma_for_rate(snapshots, target):
+    """Thresholds with round(target) values of the pooled snapshots (1-D arrays of gradient
+    magnitudes; values below any floor may be left out) above them: the interval of
+    `gamma_interval` over the pool, and its midpoint."""
+    v = np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in snapshots])
+    lo, hi = gamma_interval(v, np.ones(v.shape, bool), int(round(target)))
+    return 0.5 * (lo + hi), (lo, hi)
+
+
+def _position(sim, kind, dim, solid_layers):
+    from paper_2412_14859_amd import analytic
+    rr = sim.fields()["rho_r"]
+    if kind == "flat":
+        return analytic.film_height(rr, axis=0 if dim == 3 else 1,
+                                    solid_layers=solid_layers), float(rr.max())
+    v = analytic.half_max_volume(rr)
+    return analytic.sphere_radius(v, dim=dim, half=kind == "hemisphere"), float(rr.max())
+
+
+def calibrate_dynamic(workload, kind, phi, equil=4000, t_star=0.8, snapshots=40, sbar=3.0,
+                      gamma0=None, kappa=1e-4, precision="fp32s", outlet=None, solid_layers=1,
+                      floor=0.05, iterations=1, device="cuda:0"):
+    """Gamma matching the mass-loss rate over an evaporating run (see the module notes).
+
+    workload: an `inputs.workload` dict; kind: 'sphere', 'hemisphere' or 'flat' (the
+    interface measure); phi: the flux of the run, which lasts until t* = t phi / (x0 rho0) =
+    t_star (x0 the initial radius or film height, rho0 the equilibrium red density); outlet:
+    (lo, hi) blue outlets switched on for the evaporation; solid_layers: wall thickness under
+    a film.  Returns (Gamma, details)."""
+    from paper_2412_14859_amd import cgevap
+    w = workload
+    p0 = w["params"]
+    dim = 2 if int(p0["Q"]) == 9 else 3
+    shape = p0["shape"]
+    fluid = None if w["solid"] is None else (np.asarray(w["solid"]) == 0)
+    g = float(p0["gamma"] if gamma0 is None else gamma0)
+    history = []
+    for _ in range(iterations):
+        p = dict(p0, phi=0.0, site_rule="soft", kappa=kappa, gamma=g)
+        sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                                phi_field=np.zeros(shape), precision=precision, device=device)
+        sim.step(equil)
+        x0, rho0 = _position(sim, kind, dim, solid_layers)
+        sim.set_counters()
+        if outlet is not None:
+            sim.set_outlet(*outlet, 1.0)
+        sim.phi_field.fill_(phi)
+        t_end = t_star * x0 * rho0 / phi
+        chunk = max(1, int(t_end / snapshots))
+
+        def measure(x):
+            if kind == "flat":  # the film's area: nx * ny (the length nx in 2D)
+                return float(shape[2] * shape[1]) if dim == 3 else float(shape[2])
+            return interface_measure(kind, R=x, dim=dim)
+
+        A0 = measure(x0)
+        pool, measures = [], []
+        for _ in range(snapshots):
+            sim.step(chunk)
+            fm = sim.carry.cpu().numpy()
+            vals = fm if fluid is None else fm[fluid]
+            pool.append(vals[vals > floor].copy())
+            x, _ = _position(sim, kind, dim, solid_layers)
+            measures.append(measure(x))
+        obs = sim.observables()
+        sim.close()
+        target = sbar * float(np.sum(measures))
+        g_new, interval = gamma_for_rate(pool, target)
+        # the realised rate of this run against the analytical one, phi times the integral
+        # of A over the run (trapezoidal rule over the snapshots and the start)
+        integral = chunk * (0.5 * A0 + float(np.sum(measures[:-1])) + 0.5 * measures[-1])
+        realised = obs["sink_total"] / (phi * integral)
+        history.append({"gamma_run": g, "gamma": g_new, "interval": interval,
+                        "realised_rate_ratio": realised, "x0": x0, "rho0": rho0,
+                        "steps": chunk * snapshots, "x_end": x})
+        g = g_new
+    return g, {"history": history, "sites_target": target}

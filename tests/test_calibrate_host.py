@@ -34,3 +34,21 @@ def test_threshold_selects_exactly_k_fluid_nodes():
     assert (lo, hi) == (0.3, 0.4)
     with pytest.raises(ValueError):
         cal.gamma_interval(rows, np.ones(rows.shape, bool), 0)
+
+
+def test_rate_threshold_pools_the_snapshots():
+    """Summed over snapshots, the site count at Gamma is the number of pooled values above
+    it; the calibrated threshold makes that sum Sbar * sum_t A(t)."""
+    rng = np.random.default_rng(5)
+    snaps = [rng.random(200) * 0.6 for _ in range(7)]
+    target = 3.0 * 123.4
+    g, (lo, hi) = cal.gamma_for_rate(snaps, target)
+    assert lo < g < hi
+    total = sum(int((s > g).sum()) for s in snaps)
+    assert total == round(target)
+    # a moving flat interface: rows whose magnitudes shift between snapshots give a narrow
+    # pooled interval where one static snapshot is degenerate
+    rows = [np.repeat(np.array([0.52, 0.45, 0.31, 0.12]) + d, 16) for d in (0.0, 0.01, 0.02)]
+    s_lo, s_hi = cal.gamma_interval(rows[0], np.ones(rows[0].shape, bool), 48)
+    g, (p_lo, p_hi) = cal.gamma_for_rate(rows, 3 * 48)
+    assert p_hi - p_lo < s_hi - s_lo

@@ -47,3 +47,20 @@ def test_gamma_varies_weakly_with_interface_thickness():
         assert max(vals) - min(vals) < 0.01, (k, vals)
     for b in gs:  # the same threshold for both curved shapes
         assert abs(gs[b]["sphere"] - gs[b]["hemisphere"]) < 0.005
+
+
+def test_rate_matched_gamma_of_a_film_at_unit_ratio():
+    """The film of the paper's flat benchmark (128 high, pseudo-one-dimensional, wall two
+    layers thick), phi = 3e-3 up to t* = 0.8: Gamma matched to the mass-loss rate over the
+    run comes out at the paper's 0.31 (within 0.005), and a run at that Gamma removes
+    phi times the integral of the interface area within 1 %."""
+    from paper_2412_14859_amd import inputs
+    w = inputs.workload("contrast_flat3d", shape=(128, 4, 4), ratio=1.0)
+    print("[calibrate dynamic] film 128x4x4 unit ratio", flush=True)
+    g, det = cal.calibrate_dynamic(w, "flat", 3e-3, gamma0=0.30, solid_layers=2,
+                                   iterations=2)
+    h = det["history"]
+    print(f"  Gamma {h[0]['gamma']:.4f} -> {g:.4f}; rate ratio at the second run "
+          f"{h[1]['realised_rate_ratio']:.4f}", flush=True)
+    assert abs(g - 0.31) < 0.005
+    assert abs(h[1]["realised_rate_ratio"] - 1.0) < 0.01

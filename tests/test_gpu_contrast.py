@@ -69,10 +69,10 @@ def test_drop_at_density_ratio_two_follows_the_radius_law():
 
 
 def test_film_at_density_ratio_two_follows_the_height_law():
-    """Film 80 x 16 x 16 (h0 = 40, wall z = 0, 1, outlet at the top), phi = 3e-2,
-    Gamma = 0.30: within 8 % of h0 - phi t / rho0 up to t* = 0.85."""
-    _flush("[contrast] film 80x16x16 h0=40 ratio 2 phi 3e-2")
-    x0, rho0, tstar, xs, ref, obs, rb = _evaporate("contrast_flat3d", (80, 16, 16), 3e-2, 2000,
+    """Film 80 x 16 x 16 (h0 = 40, wall z = 0, 1, outlet at the top), phi = 3e-3, Gamma =
+    0.312 (matched to the mass-loss rate): within 3 % of h0 - phi t / rho0 up to t* = 0.85."""
+    _flush("[contrast] film 80x16x16 h0=40 ratio 2 phi 3e-3")
+    x0, rho0, tstar, xs, ref, obs, rb = _evaporate("contrast_flat3d", (80, 16, 16), 3e-3, 2000,
                                                    True)
     err = np.abs(xs - ref) / ref
     _flush(f"  h0 {x0:.3f} rho0 {rho0:.4f}; error by t*: " +
@@ -80,4 +80,4 @@ def test_film_at_density_ratio_two_follows_the_height_law():
            f"; max {err.max():.4f}")
     assert abs(x0 - 40.0) < 1.0
     assert np.all(np.diff(xs) < 0)
-    assert err.max() < 0.08
+    assert err.max() < 0.03
