@@ -88,6 +88,7 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
     ker_ms, ker_steps = sim.timing()
     sim.set_timing(False)
     obs = sim.observables()
+    site_mask = sim.carry.cpu().numpy().copy()
     N = 1
     for s in p["shape"]:
         N *= s
@@ -105,6 +106,7 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
         "v_mass": obs["v_mass"],
         "site_steps": obs["site_steps"],
         "n_negative": obs["n_negative"],
+        "_site_mask": site_mask,
     }
     sim.close()
     del sim
@@ -541,8 +543,14 @@ def main():
         # drop volume after the same steps, against the FP64 run
         legs[args.precision] = dict(main_leg)
         v64 = legs["fp64"]["v_mass"]
+        m64 = legs["fp64"]["_site_mask"]
         for leg in legs.values():
             leg["v_mass_rel_vs_fp64"] = (leg["v_mass"] - v64) / v64
+            # nodes whose site decision for the next step differs from the FP64 run's
+            leg["site_mask_flips_vs_fp64"] = int((leg["_site_mask"] != m64).sum())
+        for leg in legs.values():
+            leg.pop("_site_mask")
+    main_leg.pop("_site_mask")
     N = n ** 3
     achieved = main_leg["achieved_gbs"]
     step_ms = main_leg["kernel_ms_per_step"]
