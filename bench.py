@@ -439,6 +439,50 @@ def gamma_calibration_benchmark(phi=3e-3, iterations=2, precision="fp32s"):
             "beta_sweep": sweep, "spread_over_beta": spread}
 
 
+def feature_costs(steps=200, precision="fp32s"):
+    """Cost of the height-dependent flux and of the blue outlets on top of the step: wall
+    time per step (synchronised) over `steps` steps of the 192^3 hemisphere on a wall (flux
+    off, refreshed every 10 steps, every step) and of the 192^3 density-ratio-2 drop (outlets
+    off, on), after 20 warm-up steps each."""
+    import numpy as np
+    import torch
+    from paper_2412_14859_amd import cgevap, inputs
+
+    def timed(sim):
+        sim.step(20)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    out = {}
+    w = inputs.workload("hemisphere3d", shape=(192, 192, 192))
+    p = w["params"]
+    for label, every in (("hemisphere_flux_off", 0), ("hemisphere_flux_every_10", 10),
+                         ("hemisphere_flux_every_step", 1)):
+        sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                                phi_field=w["phi_field"], precision=precision)
+        if every:
+            sim.set_height_flux(w["phi_s"], 1.0, w["h_scale"], every=every)
+        out[label] = round(timed(sim), 4)
+        sim.close()
+    w = inputs.workload("contrast3d", shape=(192, 192, 192), ratio=2.0)
+    p = w["params"]
+    for label, on in (("contrast_outlets_off", False), ("contrast_outlets_on", True)):
+        sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], precision=precision)
+        if on:
+            sim.set_outlet(*w["outlet"], 1.0)
+        out[label] = round(timed(sim), 4)
+        sim.close()
+    out["height_flux_overhead_every_10"] = round(
+        out["hemisphere_flux_every_10"] / out["hemisphere_flux_off"] - 1.0, 4)
+    out["height_flux_overhead_every_step"] = round(
+        out["hemisphere_flux_every_step"] / out["hemisphere_flux_off"] - 1.0, 4)
+    out["outlet_overhead"] = round(out["contrast_outlets_on"] / out["contrast_outlets_off"] - 1.0, 4)
+    return {"workload": f"ms per step, 192^3, {precision}, {steps} steps", "costs": out}
+
+
 def copy_probe_gbs(nbytes=1 << 30, reps=5):
     """Achievable HBM bandwidth: the library's streaming copy kernel over nbytes, timed with
     events on torch's current stream (the stream the probe is launched on); read + write."""
@@ -491,6 +535,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true", help="skip the FP64 and FP16S legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost legs")
+    ap.add_argument("--feature-costs", action="store_true",
+                    help="time per step with and without the height flux and the outlets")
     ap.add_argument("--gamma-calibration", action="store_true",
                     help="Gamma from the mass-loss rate over evaporating runs (runs instead of "
                          "the bench line)")
@@ -513,6 +559,9 @@ def main():
     import torch
     from paper_2412_14859_amd import inputs
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.feature_costs:
+        print(json.dumps(feature_costs(steps=args.steps)), flush=True)
+        return
     if args.gamma_calibration:
         print(json.dumps(gamma_calibration_benchmark()), flush=True)
         return

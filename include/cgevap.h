@@ -211,6 +211,8 @@ cge_status cge_set_site_threshold(cge_ctx* ctx, double gamma, double kappa);
  * column's fluid nodes of the red fraction (1 + rho^N)/2 of the current pre-sink state.  The
  * field depends on the current state only, so resumed runs take the same fluxes.  every <= 0
  * switches it off (the field keeps its last values).  Each refresh reads the whole state once.
+ * The first call with every > 0 allocates a library-owned buffer of column sums (8 bytes per
+ * 8 nodes of a column), freed by cge_destroy; CGE_ENOMEM if that fails.
  * Needs a bound flux field (CGE_ESTATE otherwise); CGE_EINVAL unless K > 0, h_scale > 0 and
  * phi_s is finite.  The adjoint does not differentiate through the heights: cge_forward_ckpt
  * and cge_backward return CGE_EUNSUPPORTED while it is on. */

@@ -337,6 +337,11 @@ cge_status cge_set_height_flux(cge_ctx* c, double phi_s, double K, double h_scal
         if (!c->phi_field) return fail(c, CGE_ESTATE, "the height flux needs a bound flux field");
         if (!is_fin(phi_s) || !is_fin(K) || !(K > 0.0) || !is_fin(h_scale) || !(h_scale > 0.0))
             return fail(c, CGE_EINVAL, "height flux needs finite phi_s, K > 0, h_scale > 0");
+        if (!c->hf_part &&
+            hipMalloc(&c->hf_part, height_partial_bytes(c->g, c->Q)) != hipSuccess) {
+            c->hf_part = nullptr;
+            return fail(c, CGE_ENOMEM, "height flux scratch");
+        }
         c->hf_phi = phi_s;
         c->hf_K = K;
         c->hf_hs = h_scale;
@@ -501,6 +506,7 @@ void cge_destroy(cge_ctx* c) {
     if (!c) return;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     (void)hipFree(c->rhoN);
+    (void)hipFree(c->hf_part);
     (void)hipFree(c->carry2);
     (void)hipFree(c->mom);
     (void)hipFree(c->acc_sink);

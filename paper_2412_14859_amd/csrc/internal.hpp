@@ -42,6 +42,7 @@ struct cge_ctx {
     // height-dependent flux (active when hf_every > 0)
     long long hf_every = 0;
     double hf_phi = 0.0, hf_K = 1.0, hf_hs = 1.0;
+    void* hf_part = nullptr;  // per-chunk column sums of the refresh (library-owned)
     // counters
     long long step = 0;
     long long sites_offset = 0;
@@ -91,6 +92,7 @@ cge_status fields(cge_ctx* c, double* rr, double* rb, double* u, double* rhoN);
 
 // flux field from the column heights of the current state (flux.hip)
 cge_status height_flux(cge_ctx* c);
+size_t height_partial_bytes(const Geo& g, int Q);
 // outlet values in the current state (outlet.hip); no-op without outlets
 cge_status apply_outlets(cge_ctx* c);
 
