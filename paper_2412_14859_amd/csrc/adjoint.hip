@@ -72,8 +72,8 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static bool unit_tau(const cge_params* p) { return p->tau[0] == 1.0 && p->tau[1] == 1.0; }
 
-// Slot of one recomputed step at unit tau: post-sink rho^N (arithmetic type), the moment
-// record, the carried site data.
+// Slot of one recomputed step at unit tau: post-sink rho^N and the moment record (both
+// double next to FP64 populations, float otherwise), the carried site data.
 struct UnitSlot {
     size_t rhoN, mom, carry, bytes;
 };
@@ -81,7 +81,7 @@ static UnitSlot unit_slot(const cge_params* p) {
     const size_t N = (size_t)p->nx * p->ny * p->nz;
     UnitSlot s;
     s.rhoN = 0;
-    s.mom = align256(N * (p->precision == CGE_FP16S ? 4 : 8));
+    s.mom = align256(N * (p->precision == CGE_FP64 ? 8 : 4));
     s.carry = s.mom + align256(split_scratch_bytes(p));
     s.bytes = s.carry + align256(carry_bytes(p));
     return s;
@@ -373,7 +373,8 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
 // One block is one x-row segment, so the neighbours' row and plane offsets are uniform.
 template <int Q, typename S, typename M>
 __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
-    const M* __restrict__ rhoNf, const MomT<S>* __restrict__ mom, const double* __restrict__ mu1,
+    const MomT<S>* __restrict__ rhoNf, const MomT<S>* __restrict__ mom,
+    const double* __restrict__ mu1,
     const double* __restrict__ ab1, const double* __restrict__ aF1, double* __restrict__ mu0,
     double* __restrict__ loc, double* __restrict__ lamF, Geo g, Phys<double> P) {
     int x, y, z;
@@ -430,7 +431,8 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
 template <int Q, typename S, typename M, bool UNIT>
 __global__ __launch_bounds__(kTPBX) void k_adj_gather(
     const void* __restrict__ carry, const void* __restrict__ phi_field,
-    const M* __restrict__ rhoNf, const double* __restrict__ loc, const double* __restrict__ lamF,
+    const std::conditional_t<UNIT, MomT<S>, M>* __restrict__ rhoNf,
+    const double* __restrict__ loc, const double* __restrict__ lamF,
     double* __restrict__ q0, double* __restrict__ ab0, double* __restrict__ aF0,
     double* __restrict__ grad_phi, double* __restrict__ grad_phi_t, double* __restrict__ gpart,
     Geo g, Phys<double> P) {
@@ -539,7 +541,6 @@ static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, c
     } else {
         const Phys<double> P = phys<double>(c);
         const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-        const M* rhoN;
         if (pop) {
             M* r = static_cast<M*>(c->rhoN);
             hipLaunchKernelGGL((k_phase_state<Q, S, M>), gr, bl, 0, c->stream,
@@ -548,21 +549,19 @@ static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, c
             hipLaunchKernelGGL((k_adj_local<Q, S, M>), gr, bl, 0, c->stream,
                                static_cast<const S*>(pop), r, w.mu[1], w.ab[1], w.aF[1], w.mu[0],
                                w.loc, w.lamF, c->g, P);
-            rhoN = r;
+            hipLaunchKernelGGL((k_adj_gather<Q, S, M, false>), gr, bl, 0, c->stream, carry,
+                               c->phi_field, r, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
+                               grad_phi, grad_phi_t, w.gpart, c->g, P);
         } else {
-            rhoN = static_cast<const M*>(rhoN_in);
+            // rho^N as the split step stores it (the moment record's type)
+            const MomT<S>* rhoN = static_cast<const MomT<S>*>(rhoN_in);
             hipLaunchKernelGGL((k_adj_local_unit<Q, S, M>), gr, bl, 0, c->stream, rhoN,
                                static_cast<const MomT<S>*>(mom), w.mu[1], w.ab[1], w.aF[1],
                                w.mu[0], w.loc, w.lamF, c->g, P);
-        }
-        if (pop)
-            hipLaunchKernelGGL((k_adj_gather<Q, S, M, false>), gr, bl, 0, c->stream, carry,
-                               c->phi_field, rhoN, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
-                               grad_phi, grad_phi_t, w.gpart, c->g, P);
-        else
             hipLaunchKernelGGL((k_adj_gather<Q, S, M, true>), gr, bl, 0, c->stream, carry,
                                c->phi_field, rhoN, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
                                grad_phi, grad_phi_t, w.gpart, c->g, P);
+        }
         return check(c, hipGetLastError(), "adjoint step");
     }
 }

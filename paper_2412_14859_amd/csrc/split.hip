@@ -3,13 +3,13 @@
 // With 1/tau = 1 at every node, BGK relaxation returns the equilibrium (Eq. collision), so
 // the post-collision populations depend on the pulled ones only through the post-sink
 // moments: rho (via drho = sum ft_i), rho^N and j.  The first pass pulls, applies the sink
-// and writes those moments (rho^N in the arithmetic type, drho and j in the storage type's
-// width: FP64 next to FP64 populations, FP32 otherwise); the second pass reads them back,
+// and writes those moments (rho^N, drho and j in the storage type's width: FP64 next to FP64
+// populations, FP32 otherwise, like the populations themselves); the second pass reads them back,
 // takes the colour gradient from the rho^N field, and runs equilibrium, perturbation and
 // recolouring (Eqs. feq, perturb, recolor) without touching the old populations.
 //
 // Per node: 2Q reads + 2Q writes of populations, plus the moment record written and read
-// once (24 B at FP32 storage) and the neighbours' rho^N (cache hits).  Both kernels are one
+// once (20 B at FP32 storage) and the neighbours' rho^N (cache hits).  Both kernels are one
 // thread per node with no synchronisation, so many waves hide memory latency.
 #include "internal.hpp"
 #include "node.hpp"
@@ -22,7 +22,8 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
                                                    const uint8_t* __restrict__ flags,
                                                    const void* __restrict__ carry,
                                                    const void* __restrict__ phi_field,
-                                                   M* __restrict__ rhoN, MomT<S>* __restrict__ mom,
+                                                   MomT<S>* __restrict__ rhoN,
+                                                   MomT<S>* __restrict__ mom,
                                                    double* __restrict__ acc_sink,
                                                    long long* __restrict__ acc_sites, Geo g,
                                                    Phys<M> P) {
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
         dsum -= M(2) * s;
         v[0] = static_cast<double>(s);
         v[1] = is_site(wgt) ? 1.0 : 0.0;
-        rhoN[n] = dsum / rho;
+        rhoN[n] = static_cast<MomT<S>>(dsum / rho);
         mom[n] = static_cast<MomT<S>>(drho);
         mom[g.N + n] = static_cast<MomT<S>>(j[0]);
         mom[2 * g.N + n] = static_cast<MomT<S>>(j[1]);
@@ -81,13 +82,13 @@ template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_finish(S* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
                                                   void* __restrict__ carry,
-                                                  const M* __restrict__ rhoN,
+                                                  const MomT<S>* __restrict__ rhoN,
                                                   const MomT<S>* __restrict__ mom, Geo g,
                                                   Phys<M> P, uint64_t salt) {
     int x, y, z;
     long long n;
     const bool valid = node_xyz(g, x, y, z, n);
-    const RowOff r = row_offsets<M>(g, x < g.nx ? x : 0);
+    const RowOff r = row_offsets<MomT<S>>(g, x < g.nx ? x : 0);  // x offsets into rho^N
     if (!valid) return;
     if (WALLS && flags[n]) return;
     const M drho = static_cast<M>(mom[n]);
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) v
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const long long rowz = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]];
-            const M v = M(weight<Q>(i)) * ld_at(rhoN + rowz, r.xo[1 + Lat<Q>::cx[i]]);
+            const M v = M(weight<Q>(i)) * static_cast<M>(ld_at(rhoN + rowz, r.xo[1 + Lat<Q>::cx[i]]));
             if (Lat<Q>::cx[i]) F[0] += Lat<Q>::cx[i] * v;
             if (Lat<Q>::cy[i]) F[1] += Lat<Q>::cy[i] * v;
             if (Lat<Q>::cz[i]) F[2] += Lat<Q>::cz[i] * v;
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) v
     // stores at the node itself: the row base is uniform, x is the lane offset
     const long long row = r.yrow[1] + r.zpl[1];
     const uint32_t xb = (uint32_t)x * (uint32_t)sizeof(S);
-    const M Fn = collide<Q, M, true>([](int) { return M(0); }, drho, rho, rhoN[n], u, F, P,
+    const M Fn = collide<Q, M, true>([](int) { return M(0); }, drho, rho, static_cast<M>(rhoN[n]), u, F, P,
                                      [&](int i, M a, M d) {
                                          const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N +
                                                               (uint64_t)n;
@@ -144,7 +145,7 @@ __device__ __forceinline__ int wrapm(int v, int n) { return ((v % n) + n) % n; }
 
 template <typename S, typename M>
 __global__ __launch_bounds__(kTileX* kTileY) __attribute__((amdgpu_waves_per_eu(5, 8))) void
-k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const M* __restrict__ rhoN,
+k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const MomT<S>* __restrict__ rhoN,
               const MomT<S>* __restrict__ mom, Geo g, Phys<M> P, uint64_t salt) {
     constexpr int Q = 19, W = kTileX + 2, H = kTileY + 2, NT = kTileX * kTileY;
     __shared__ M tile[3][H][W];
@@ -205,7 +206,7 @@ static cge_status split_one(cge_ctx* c, const void* carry_in, void* carry_out, v
                             void* mom_out) {
     const Phys<M> P = phys<M>(c);
     const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-    M* rhoN = static_cast<M*>(rhoN_out);
+    MomT<S>* rhoN = static_cast<MomT<S>*>(rhoN_out);  // stored like the moment record
     MomT<S>* mom = static_cast<MomT<S>*>(mom_out);
     const S* src = static_cast<const S*>(c->pop[c->cur]);
     S* dst = static_cast<S*>(c->pop[1 - c->cur]);
@@ -213,7 +214,7 @@ static cge_status split_one(cge_ctx* c, const void* carry_in, void* carry_out, v
     timing_begin(c);
     hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
                        carry_in, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
-    if (WALLS) hipLaunchKernelGGL((k_wet<Q, M>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+    if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
     if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
         const dim3 tb(kTileX, kTileY, 1);
         const dim3 tg((c->g.nx + kTileX - 1) / kTileX, (c->g.ny + kTileY - 1) / kTileY, c->g.nz);
