@@ -79,9 +79,12 @@ def phase_field(f):
     return (rr - rb) / (rr + rb)
 
 
-def step(L, p, f, fprev, phi, weight):
+def step(L, p, f, fprev, phi, weight, stored=None):
     """One step.  f: [2, Q, nz, ny, nx] pre-sink state; fprev: ||F_{n-1}|| [nz, ny, nx];
-    phi: flux field of this step; weight: site weights m.  Returns (next state, ||F_n||)."""
+    phi: flux field of this step; weight: site weights m.  Returns (next state, ||F_n||).
+    stored: optional function of the post-sink moments (rho, [j_x, j_y, j_z], rho^N) returning
+    the values the rest of the step uses instead (a test uses it to reproduce a storage
+    rounding); by default they are used as computed."""
     Q = L["Q"]
     s = weight * phi / p["sbar"]
     fr = torch.cat([(f[0, 0] - s)[None], f[0, 1:]])
@@ -89,9 +92,13 @@ def step(L, p, f, fprev, phi, weight):
     rr, rb = fr.sum(0), fb.sum(0)
     rho = rr + rb
     fcb = fr + fb
-    u = [sum(L["c"][i][a] * fcb[i] for i in range(Q) if L["c"][i][a]) / rho for a in range(3)]
-    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+    j = [sum(L["c"][i][a] * fcb[i] for i in range(Q) if L["c"][i][a]) for a in range(3)]
     rhoN = (rr - rb) / rho
+    if stored is not None:
+        rho, j, rhoN = stored(rho, j, rhoN)
+        rr, rb = rho * (1.0 + rhoN) / 2.0, rho * (1.0 - rhoN) / 2.0
+    u = [j[a] / rho for a in range(3)]
+    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
     F = phase_gradient(L, rhoN)
     F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2]
     pos = F2 > 0
