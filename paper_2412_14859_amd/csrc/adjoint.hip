@@ -327,9 +327,10 @@ __device__ __forceinline__ void adj_node_unit(const Phys<double>& P, double rho,
 // General relaxation times: recompute from the stored populations.
 template <int Q, typename S, typename M>
 __global__ __launch_bounds__(kTPBX) void k_adj_local(
-    const S* __restrict__ src, const M* __restrict__ rhoNf, const double* __restrict__ mu1,
-    const double* __restrict__ ab1, const double* __restrict__ aF1, double* __restrict__ mu0,
-    double* __restrict__ loc, double* __restrict__ lamF, Geo g, Phys<double> P) {
+    const S* __restrict__ src, const MomT<S>* __restrict__ rhoNf,
+    const double* __restrict__ mu1, const double* __restrict__ ab1,
+    const double* __restrict__ aF1, double* __restrict__ mu0, double* __restrict__ loc,
+    double* __restrict__ lamF, Geo g, Phys<double> P) {
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
@@ -431,7 +432,7 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
 template <int Q, typename S, typename M, bool UNIT>
 __global__ __launch_bounds__(kTPBX) void k_adj_gather(
     const void* __restrict__ carry, const void* __restrict__ phi_field,
-    const std::conditional_t<UNIT, MomT<S>, M>* __restrict__ rhoNf,
+    const MomT<S>* __restrict__ rhoNf,
     const double* __restrict__ loc, const double* __restrict__ lamF,
     double* __restrict__ q0, double* __restrict__ ab0, double* __restrict__ aF0,
     double* __restrict__ grad_phi, double* __restrict__ grad_phi_t, double* __restrict__ gpart,
@@ -495,12 +496,14 @@ static hipError_t zero(double* p, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-// post-sink rho^N of a stored state (same arithmetic as the forward first pass)
+// post-sink rho^N of a stored state (same arithmetic as the forward first pass, stored at
+// the same precision)
 template <int Q, typename S, typename M>
 __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src,
                                                        const void* __restrict__ carry,
                                                        const void* __restrict__ phi_field,
-                                                       M* __restrict__ rhoN, Geo g, Phys<M> P) {
+                                                       MomT<S>* __restrict__ rhoN, Geo g,
+                                                       Phys<M> P) {
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
@@ -510,7 +513,7 @@ __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src
     moments<Q>(ft, dd, drho, dsum, j);
     const M rho = P.rho_ref + drho;
     dsum -= M(2) * site_sink<S>(P, carry, phi_field, n, rho, dsum);
-    rhoN[n] = dsum / rho;
+    rhoN[n] = static_cast<MomT<S>>(dsum / rho);
 }
 
 template <int Q, typename S, typename M, bool WALLS>
@@ -542,7 +545,7 @@ static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, c
         const Phys<double> P = phys<double>(c);
         const dim3 gr = node_grid(c->g), bl = node_block(c->g);
         if (pop) {
-            M* r = static_cast<M*>(c->rhoN);
+            MomT<S>* r = static_cast<MomT<S>*>(c->rhoN);
             hipLaunchKernelGGL((k_phase_state<Q, S, M>), gr, bl, 0, c->stream,
                                static_cast<const S*>(pop), carry, c->phi_field, r, c->g,
                                phys<M>(c));

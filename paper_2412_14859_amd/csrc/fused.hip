@@ -128,7 +128,8 @@ struct Pulled {
 
 // Pull (Eq. Stream) of the node whose plane offsets are `pl`, at plane z: direction i comes
 // from (x, y, z) - c_i.  zoff[1 + d] is the byte offset of plane z + d (wrapped).  Returns
-// the post-sink rho^N; with FULL, also fills the reduced node for the collision.
+// the post-sink rho^N (rounded to the storage precision, as the other step forms store it);
+// with FULL, also fills the reduced node for the collision.
 template <int Q, typename S, typename M, bool FULL, bool UNIT>
 __device__ __forceinline__ M pull_node(__amdgpu_buffer_rsrc_t rft, __amdgpu_buffer_rsrc_t rdd,
                                        const Plane9<S>& pl, const uint32_t (&zoff)[3],
@@ -166,7 +167,8 @@ __device__ __forceinline__ M pull_node(__amdgpu_buffer_rsrc_t rft, __amdgpu_buff
         pn.j[2] = j[2];
         pn.s = s;
     }
-    return dpost / rho;
+    // rho^N as a stored field holds it: float next to FP32 or FP16 populations
+    return static_cast<M>(static_cast<MomT<S>>(dpost / rho));
 }
 
 template <int Q, typename S, typename M, bool UNIT>
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
             const M rho = P.rho_ref + cur.drho;
             const M inv_rho = M(1) / rho;
             const M u[3] = {cur.j[0] * inv_rho, cur.j[1] * inv_rho, cur.j[2] * inv_rho};
-            const M rN = cur.dsum * inv_rho;
+            const M rN = static_cast<M>(static_cast<MomT<S>>(cur.dsum / rho));  // as in the ring
             // gradient from the LDS ring: planes pc-1, pc, pc+1 are slots of p-2, p-1, p
             const int sl[3] = {(p - z0 + 2) % 3, (p - z0) % 3, slot};  // cz = -1, 0, +1
             M F[3] = {M(0), M(0), M(0)};

@@ -1,21 +1,23 @@
 // Two-pass step: k_phase writes the post-sink phase field rho^N of every fluid node,
 // k_wet fills solid nodes with the neutral-wetting value, k_collide pulls again, applies
-// the sink, takes the colour gradient from the rho^N field, collides, perturbs, recolours,
-// stores, and writes the next step's site mask.  One thread per node; works for any
-// domain and any solid geometry.
+// the sink, takes rho^N and the colour gradient from the rho^N field, collides, perturbs,
+// recolours, stores, and writes the next step's site mask.  One thread per node; works for
+// any domain and any solid geometry.  The rho^N field is stored like the populations (float
+// next to FP32 or FP16 populations, double next to FP64 ones).
 #include "internal.hpp"
 #include "node.hpp"
 
 namespace cge {
 
 
-// Pass 1: post-sink rho^N of fluid nodes (apply_sink = 0: pre-sink, for the step-0 mask).
-template <int Q, typename S, typename M, bool WALLS>
+// Pass 1: post-sink rho^N of fluid nodes (apply_sink = 0: pre-sink, for the step-0 mask),
+// stored in type R.
+template <int Q, typename S, typename M, bool WALLS, typename R>
 __global__ __launch_bounds__(kTPBX) void k_phase(const S* __restrict__ src,
                                                  const uint8_t* __restrict__ flags,
                                                  const void* __restrict__ carry,
                                                  const void* __restrict__ phi_field,
-                                                 M* __restrict__ rhoN, Geo g, Phys<M> P,
+                                                 R* __restrict__ rhoN, Geo g, Phys<M> P,
                                                  int apply_sink) {
     int x, y, z;
     long long n;
@@ -27,7 +29,7 @@ __global__ __launch_bounds__(kTPBX) void k_phase(const S* __restrict__ src,
     moments<Q>(ft, dd, drho, dsum, j);
     const M rho = P.rho_ref + drho;
     if (apply_sink) dsum -= M(2) * site_sink<S>(P, carry, phi_field, n, rho, dsum);
-    rhoN[n] = dsum / rho;
+    rhoN[n] = static_cast<R>(dsum / rho);
 }
 
 // Site data (mask byte, or ||F|| for the soft rule) from the rho^N field, without
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
                                                    const uint8_t* __restrict__ flags,
                                                    void* __restrict__ carry,
                                                    const void* __restrict__ phi_field,
-                                                   const M* __restrict__ rhoN,
+                                                   const MomT<S>* __restrict__ rhoN,
                                                    double* __restrict__ acc_sink,
                                                    long long* __restrict__ acc_sites, Geo g,
                                                    Phys<M> P, uint64_t salt) {
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         v[1] = is_site(w) ? 1.0 : 0.0;
         const M inv_rho = M(1) / rho;
         const M u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
-        const M rN = dsum * inv_rho;
+        const M rN = static_cast<M>(rhoN[n]);  // as stored by the first pass
         M F[3];
         gradient<Q>(rhoN, g, b, x, y, z, F);
         const M Fn = collide<Q>([&](int i) { return ft[i]; }, drho, rho, rN, u, F, P,
@@ -108,17 +110,17 @@ template <int Q, typename S, typename M, bool WALLS>
 static cge_status twopass_impl(cge_ctx* c, long long nsteps) {
     const Phys<M> P = phys<M>(c);
     const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-    M* rhoN = static_cast<M*>(c->rhoN);
+    MomT<S>* rhoN = static_cast<MomT<S>*>(c->rhoN);  // stored like the populations
     const uint64_t seedmix = mix64(c->p.seed);
     for (long long t = 0; t < nsteps; ++t) {
         const S* src = static_cast<const S*>(c->pop[c->cur]);
         S* dst = static_cast<S*>(c->pop[1 - c->cur]);
         const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
         timing_begin(c);
-        hipLaunchKernelGGL((k_phase<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
-                           c->carry, c->phi_field, rhoN, c->g, P, 1);
+        hipLaunchKernelGGL((k_phase<Q, S, M, WALLS, MomT<S>>), gr, bl, 0, c->stream, src,
+                           c->flags, c->carry, c->phi_field, rhoN, c->g, P, 1);
         if (WALLS)
-            hipLaunchKernelGGL((k_wet<Q, M>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+            hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
         hipLaunchKernelGGL((k_collide<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, dst, c->flags,
                            c->carry, c->phi_field, rhoN, c->acc_sink, c->acc_sites, c->g, P,
                            salt);
@@ -137,7 +139,7 @@ static cge_status reset_impl(cge_ctx* c) {
     const Phys<M> P = phys<M>(c);
     const dim3 gr = node_grid(c->g), bl = node_block(c->g);
     M* rhoN = static_cast<M*>(c->rhoN);
-    hipLaunchKernelGGL((k_phase<Q, S, M, WALLS>), gr, bl, 0, c->stream,
+    hipLaunchKernelGGL((k_phase<Q, S, M, WALLS, M>), gr, bl, 0, c->stream,
                        static_cast<const S*>(c->pop[c->cur]), c->flags, c->carry, c->phi_field,
                        rhoN, c->g, P, 0);
     if (WALLS) hipLaunchKernelGGL((k_wet<Q, M>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);

@@ -122,10 +122,11 @@ def test_checkpoint_interval_does_not_change_the_gradients():
 def _reference_fp32_storage(w, target, nsteps):
     """The autograd reference on the trajectory of FP32 storage: after every step the state is
     rounded to nearest float32 in the stored encoding (ft_i = f_i^r + f_i^b - rho_b^in
-    t_i(alpha_b), dd_i = f_i^r - f_i^b), as is the flux field.  At unit relaxation times the
-    split step also stores the post-sink moments in float32 (rho - rho_b^in, j, and rho^N
-    computed with the unrounded rho) and finishes the step from them; that is reproduced
-    too.  The roundings pass gradients through unchanged."""
+    t_i(alpha_b), dd_i = f_i^r - f_i^b), as is the flux field.  Within a step the phase
+    field rho^N is stored in float32 too, and the step continues from the stored value; at
+    unit relaxation times the split step also stores rho - rho_b^in and j (rho^N computed
+    with the unrounded rho).  All of that is reproduced.  The roundings pass gradients
+    through unchanged."""
     import torch
     DT = torch.float64
     p = w["params"]
@@ -142,9 +143,23 @@ def _reference_fp32_storage(w, target, nsteps):
 
     rho_ref = float(p["rho_in"][1])
 
+    def stored_rhoN(rhoN, rho, rho_lin):
+        # the value rounded to float32; the derivatives those of D / rho (D = rho_r - rho_b)
+        # taken at the stored value, 1 / rho and -rhoN_stored / rho with rho = rho_lin: the
+        # adjoint linearises the stored field, as the exact quotient is not kept
+        D = rho * rhoN
+        c = rhoN.float().double().detach()
+        r0 = rho_lin.detach()
+        e = D - c * rho_lin
+        return c + e / r0 - e.detach() / r0
+
     def split_moments(rho, j, rhoN):  # (j_z of D2Q9 is the constant 0)
-        return (rho_ref + rnd(rho - rho_ref), [rnd(a) if torch.is_tensor(a) else a for a in j],
-                rnd(rhoN))
+        rho_s = rho_ref + rnd(rho - rho_ref)
+        return (rho_s, [rnd(a) if torch.is_tensor(a) else a for a in j],
+                stored_rhoN(rhoN, rho, rho_s))
+
+    def stored_phase(rho, j, rhoN):
+        return rho, j, stored_rhoN(rhoN, rho, rho)
 
     unit = tuple(p["tau"]) == (1.0, 1.0)
     ph = torch.as_tensor(w["phi_field"], dtype=torch.float32).double().requires_grad_(True)
@@ -154,7 +169,8 @@ def _reference_fp32_storage(w, target, nsteps):
     fprev = A.gradient_magnitude(L, f).detach()
     for _ in range(nsteps):
         m = torch.sigmoid((fprev - g) / p["kappa"])
-        f, fprev = A.step(L, p, f, fprev, ph, m, stored=split_moments if unit else None)
+        f, fprev = A.step(L, p, f, fprev, ph, m,
+                          stored=split_moments if unit else stored_phase)
         f = store(f)
     A.loss_rhoN(f, torch.as_tensor(target, dtype=DT)).backward()
     return ph.grad.numpy(), float(g.grad)
