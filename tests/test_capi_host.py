@@ -63,6 +63,10 @@ def test_null_arguments():
         args = (None, 1) if fn == "cge_step" else (None,)
         assert getattr(L, fn)(*args) == cgevap.EINVAL
     assert L.cge_last_error(None) == b"NULL context"
+    assert L.cge_set_outlet(None, 1, 1, C.c_double(1.0)) == cgevap.EINVAL
+    assert L.cge_set_height_flux(None, C.c_double(1e-3), C.c_double(1.0), C.c_double(1.0),
+                                 C.c_longlong(1)) == cgevap.EINVAL
+    assert L.cge_set_site_threshold(None, C.c_double(0.3), C.c_double(0.0)) == cgevap.EINVAL
     L.cge_destroy(None)
 
 

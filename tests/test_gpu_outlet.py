@@ -126,3 +126,48 @@ def test_outlet_fp32_storage_frozen_mask():
     _flush(f"  e_pop after 40 steps {e:.3e}")
     assert e < 1e-5
     sim.close()
+
+
+def test_feature_setters_reject_bad_arguments_and_the_adjoint_refuses_them():
+    """Outlets: a non-positive or non-finite outlet density, or fewer than 3 planes along the
+    last axis, is EINVAL.  Height flux: without a bound flux field ESTATE, K <= 0 or h_s <= 0
+    EINVAL.  A non-finite site threshold is EINVAL.  The checkpointed forward refuses
+    outlets and the height flux (EUNSUPPORTED).  Nothing is changed by a rejected call."""
+    from paper_2412_14859_amd import cgevap
+    Q, shape, R, wall = CASES["d3q19"]
+    w = _drop(Q, shape, R)
+    sim = gpu_for(w, "fp64")
+    f0 = sim.populations().cpu().numpy()
+    for rho_out in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(cgevap.CgeError) as e:
+            sim.set_outlet(True, True, rho_out)
+        assert e.value.status == cgevap.EINVAL
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.set_site_threshold(float("nan"))
+    assert e.value.status == cgevap.EINVAL
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.set_height_flux(1e-3, 1.0, 4.0, every=1)  # no flux field bound
+    assert e.value.status == cgevap.ESTATE
+    assert np.array_equal(sim.populations().cpu().numpy(), f0)
+    sim.set_outlet(True, True, 1.0)
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.forward_ckpt(4, 2)
+    assert e.value.status == cgevap.EUNSUPPORTED
+    sim.close()
+    thin = _drop(Q, (2, 12, 14), 3.0)
+    sim = gpu_for(thin, "fp64")
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.set_outlet(True, True, 1.0)
+    assert e.value.status == cgevap.EINVAL
+    sim.close()
+    wf = dict(w, phi_field=np.full(shape, 1e-3))
+    sim = gpu_for(wf, "fp64")
+    for K, hs in ((0.0, 4.0), (-1.0, 4.0), (1.0, 0.0), (float("nan"), 4.0)):
+        with pytest.raises(cgevap.CgeError) as e:
+            sim.set_height_flux(1e-3, K, hs, every=1)
+        assert e.value.status == cgevap.EINVAL
+    sim.set_height_flux(1e-3, 1.0, 4.0, every=1)
+    with pytest.raises(cgevap.CgeError) as e:
+        sim.forward_ckpt(4, 2)
+    assert e.value.status == cgevap.EUNSUPPORTED
+    sim.close()
