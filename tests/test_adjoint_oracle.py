@@ -28,13 +28,19 @@ def test_tables_agree_with_the_c_oracle(Q):
                                  kappa=0.01)),
     ("drop2d", (1, 20, 26), dict(radius=6.0, phi=1e-3, tau=(1.0, 0.7), beta=0.5,
                                  site_rule="grad", gamma=0.305)),
+    # solid nodes: a film between walls; a cap on a wall at density ratio 10 with a flux field
+    ("flat2d", (1, 20, 26), dict(phi=1e-3)),
+    ("sessile3d", (8, 12, 14), dict(radius=4.0, phi=1e-3)),
+    ("hemisphere3d", (10, 12, 12), dict(radius=4.0, phi=1e-3, site_rule="soft", kappa=0.02)),
 ])
 def test_forward_equals_the_c_oracle(wl, shape, over):
     w = case(wl, shape, **over)
     p = w["params"]
     ora = oracle_for(w)
     ora.step(8)
-    f = A.run(p, w["rho_r"], w["rho_b"], torch.full(shape, p["phi"], dtype=DT), 8)
+    phi = torch.full(shape, p["phi"], dtype=DT) if w["phi_field"] is None else \
+        torch.as_tensor(w["phi_field"], dtype=DT)
+    f = A.run(p, w["rho_r"], w["rho_b"], phi, 8, solid=w["solid"])
     assert np.abs(f.detach().numpy() - ora.populations()).max() < 1e-14
 
 
@@ -96,4 +102,22 @@ def test_red_mass_sensitivity_is_minus_mask_over_sbar():
     f[0].sum().backward()
     expect = -masks / p["sbar"]
     assert masks.sum() > 0
+    assert float((ph.grad - expect).abs().max()) < 1e-13
+
+
+def test_red_mass_sensitivity_with_walls():
+    """With solid nodes too (a film between walls: bounce-back and wetting), every operator but
+    the sink conserves red mass, so dM_r(T)/dphi(x, t) = -m(x, t)/Sbar exactly, and 0 at solid
+    nodes."""
+    w = case("flat2d", (1, 20, 22), phi=3e-3)
+    p = w["params"]
+    phi = torch.full(p["shape"], 3e-3, dtype=DT)
+    n = 10
+    _, masks = A.run(p, w["rho_r"], w["rho_b"], phi, n, return_masks=True, solid=w["solid"])
+    ph = phi.expand((n,) + phi.shape).clone().requires_grad_(True)
+    f = A.run(p, w["rho_r"], w["rho_b"], ph, n, masks=masks, solid=w["solid"])
+    f[0].sum().backward()
+    fl = torch.as_tensor(w["solid"] == 0, dtype=DT)
+    expect = -masks * fl / p["sbar"]
+    assert float((masks * fl).sum()) > 0
     assert float((ph.grad - expect).abs().max()) < 1e-13
