@@ -161,8 +161,9 @@ size_t cge_state_bytes(const cge_params* params);
 cge_status cge_save_state(cge_ctx* ctx, void* dst);
 cge_status cge_load_state(cge_ctx* ctx, const void* src);
 
-/* Adjoint (reverse mode) of nsteps steps, for domains without solid nodes and the site rules
- * GRAD_GT (sites held at those of the forward run) and SOFT.  The loss is given through its
+/* Adjoint (reverse mode) of nsteps steps, for the site rules GRAD_GT (sites held at those of
+ * the forward run) and SOFT, with or without solid nodes (the transposes of the halfway
+ * bounce-back and of the neutral-wetting value are included).  The loss is given through its
  * derivatives with respect to the final phase field rho^N_T (e.g. 2 (rho^N_T - target) for a
  * squared mismatch) and the final density rho_T (e.g. rho_T/2 and (1 + rho^N_T)/2 together
  * for the red mass), and the gradients with respect to the flux field phi(x) and the site
@@ -179,15 +180,16 @@ cge_status cge_load_state(cge_ctx* ctx, const void* src);
  *                      phase field, moments and site data, otherwise each state);
  *                      work: cge_adjoint_bytes();
  *                      dL_drhoN, dL_drho: [N] doubles, either may be NULL (read as zero) but
- *                      not both; grad_phi (out): [N] doubles, dL/dphi(x) summed
+ *                      not both; their values at solid nodes are ignored (solid nodes hold no
+ *                      state); grad_phi (out): [N] doubles, dL/dphi(x) summed
  *                      over the steps (phi held over time); grad_phi_t (out, nullable):
  *                      [nsteps][N] doubles, dL/dphi(x, t) per step; grad_gamma (host, nullable):
  *                      dL/dGamma (0 for GRAD_GT).  All buffers except grad_gamma are device
  *                      memory.  Forward states are recomputed from the checkpoints; on return
  *                      the context holds the state after nsteps again, with its step counter
  *                      and sink bookkeeping.
- * Errors: CGE_EINVAL (missing buffers, nsteps or K < 1), CGE_EUNSUPPORTED (solid nodes,
- * PHASE_LT rule), CGE_EDEVICE. */
+ * Errors: CGE_EINVAL (missing buffers, nsteps or K < 1), CGE_EUNSUPPORTED (PHASE_LT rule,
+ * height flux or outlets on), CGE_EDEVICE. */
 size_t cge_adjoint_bytes(const cge_params* params);
 size_t cge_segment_bytes(const cge_params* params, int K);
 cge_status cge_forward_ckpt(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt);

@@ -90,8 +90,9 @@ static UnitSlot unit_slot(const cge_params* p) {
 // Seed: lambda of S_T from dL/drho^N_T and dL/drho_T (either may be absent), with
 // rho = rho_ref + sum ft and rho^N = sum dd / rho (pre-sink):
 //     dL/dft_i = dL/drho - dL/drho^N rho^N / rho,    dL/ddd_i = dL/drho^N / rho.
-template <int Q, typename S, typename M, int NMU>
+template <int Q, typename S, typename M, int NMU, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
+                                                    const uint8_t* __restrict__ flags,
                                                     const double* __restrict__ g_rhoN,
                                                     const double* __restrict__ g_rho,
                                                     double* __restrict__ mu, double* __restrict__ ab,
@@ -99,9 +100,17 @@ __global__ __launch_bounds__(kTPBX) void k_adj_seed(const S* __restrict__ src,
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
+    if (WALLS && flags[n]) {  // a solid node has no state and no adjoint; loss seeds there are ignored
+#pragma unroll
+        for (int i = 0; i < NMU; ++i) mu[(long long)i * g.N + n] = 0.0;
+        if (NMU != 4) ab[n] = 0.0;
+        ab[g.N + n] = 0.0;
+        aF[n] = 0.0;
+        return;
+    }
     const Nb b = wrap(g, x, y, z);
     M ft[Q], dd[Q], j[3], drho, dsum;
-    pull<Q, false>(src, nullptr, g, b, x, y, z, n, ft, dd);
+    pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
     moments<Q>(ft, dd, drho, dsum, j);
     const double rho = static_cast<double>(P.rho_ref + drho);
     const double rN = static_cast<double>(dsum) / rho;
@@ -325,18 +334,26 @@ __device__ __forceinline__ void adj_node_unit(const Phys<double>& P, double rho,
 }
 
 // General relaxation times: recompute from the stored populations.
-template <int Q, typename S, typename M>
+template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_adj_local(
-    const S* __restrict__ src, const MomT<S>* __restrict__ rhoNf,
+    const S* __restrict__ src, const uint8_t* __restrict__ flags, const MomT<S>* __restrict__ rhoNf,
     const double* __restrict__ mu1, const double* __restrict__ ab1,
     const double* __restrict__ aF1, double* __restrict__ mu0, double* __restrict__ loc,
     double* __restrict__ lamF, Geo g, Phys<double> P) {
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
+    if (WALLS && flags[n]) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) mu0[(long long)i * g.N + n] = 0.0;
+        loc[n] = 0.0;
+        loc[g.N + n] = 1.0;
+        lamF[n] = lamF[g.N + n] = lamF[2 * g.N + n] = 0.0;
+        return;
+    }
     const Nb nb = wrap(g, x, y, z);
     M ftm[Q], ddm[Q], jm[3], drhom, dsumm;
-    pull<Q, false>(src, nullptr, g, nb, x, y, z, n, ftm, ddm);
+    pull<Q, WALLS>(src, flags, g, nb, x, y, z, n, ftm, ddm);
     moments<Q>(ftm, ddm, drhom, dsumm, jm);
     const double rho = P.rho_ref + static_cast<double>(drhom);
     const double rN = static_cast<double>(rhoNf[n]);
@@ -349,9 +366,15 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
     adj_node<Q, false>(
         P, rho, rN, u, F, aF1[n],
         [&](int i, double& mus, double& etas) {
+            // f*_i(x) is pulled by x + c_i, or bounced back into x as direction opp(i)
             const long long xn = shifted<Q, 1>(g, nb, x, y, z, i);
-            mus = mu1[(long long)i * g.N + xn] + ab1[xn];
-            etas = ab1[g.N + xn];
+            if (WALLS && flags[xn]) {
+                mus = mu1[(long long)Lat<Q>::opp[i] * g.N + n] + ab1[n];
+                etas = ab1[g.N + n];
+            } else {
+                mus = mu1[(long long)i * g.N + xn] + ab1[xn];
+                etas = ab1[g.N + xn];
+            }
         },
         [&](int i) {
             return static_cast<double>(ftm[i]) +
@@ -372,9 +395,10 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local(
 // Unit relaxation times: the forward's phase field and moments of this step are given; the
 // adjoint of a node is (q0, dj, b) with dL/dft_i = q0 + c_i . dj (q0 = p0 + a) and dL/ddd_i = b.
 // One block is one x-row segment, so the neighbours' row and plane offsets are uniform.
-template <int Q, typename S, typename M>
+template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
-    const MomT<S>* __restrict__ rhoNf, const MomT<S>* __restrict__ mom,
+    const uint8_t* __restrict__ flags, const MomT<S>* __restrict__ rhoNf,
+    const MomT<S>* __restrict__ mom,
     const double* __restrict__ mu1,
     const double* __restrict__ ab1, const double* __restrict__ aF1, double* __restrict__ mu0,
     double* __restrict__ loc, double* __restrict__ lamF, Geo g, Phys<double> P) {
@@ -383,6 +407,15 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     const bool valid = node_xyz(g, x, y, z, n);
     const RowOff r = row_offsets<char>(g, x < g.nx ? x : 0);  // element offsets
     if (!valid) return;
+    if (WALLS && flags[n]) {
+        mu0[n] = mu0[g.N + n] = mu0[2 * g.N + n] = 0.0;
+        if (Lat<Q>::D == 3) mu0[3 * g.N + n] = 0.0;
+        loc[n] = 0.0;
+        loc[g.N + n] = 1.0;
+        lamF[n] = lamF[g.N + n] = 0.0;
+        if (Lat<Q>::D == 3) lamF[2 * g.N + n] = 0.0;
+        return;
+    }
     const double rho = P.rho_ref + static_cast<double>(static_cast<M>(mom[n]));
     const double rN = static_cast<double>(rhoNf[n]);
     const double ir = 1.0 / rho;
@@ -406,12 +439,16 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     adj_node_unit<Q>(
         P, rho, rN, u, F, aF1[n],
         [&](int i, double& mus, double& etas) {
-            const long long xn = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]] +
-                                 r.xo[1 + Lat<Q>::cx[i]];
+            long long xn = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]] +
+                           r.xo[1 + Lat<Q>::cx[i]];
+            // pulled by x + c_i as direction i, or bounced back into x as direction opp(i),
+            // whose adjoint is q0(x) + c_opp(i) . dj(x) = q0(x) - c_i . dj(x)
+            const double sgn = (WALLS && flags[xn]) ? -1.0 : 1.0;
+            if (WALLS && flags[xn]) xn = n;
             double m = mu1[xn];
-            if (Lat<Q>::cx[i]) m += Lat<Q>::cx[i] * mu1[g.N + xn];
-            if (Lat<Q>::cy[i]) m += Lat<Q>::cy[i] * mu1[2 * g.N + xn];
-            if (Lat<Q>::cz[i]) m += Lat<Q>::cz[i] * mu1[3 * g.N + xn];
+            if (Lat<Q>::cx[i]) m += sgn * Lat<Q>::cx[i] * mu1[g.N + xn];
+            if (Lat<Q>::cy[i]) m += sgn * Lat<Q>::cy[i] * mu1[2 * g.N + xn];
+            if (Lat<Q>::cz[i]) m += sgn * Lat<Q>::cz[i] * mu1[3 * g.N + xn];
             mus = m;
             etas = ab1[g.N + xn];
         },
@@ -427,11 +464,42 @@ __global__ __launch_bounds__(kTPBX) void k_adj_local_unit(
     if (Lat<Q>::D == 3) lamF[2 * g.N + n] = lf[2];
 }
 
+// Adjoint of the neutral-wetting value at solid nodes: the solid node s's rho^N enters the
+// gradient of its fluid neighbours, so dL/drho^N(s) = sum_i 3 W_i c_i . dL/dF(s - c_i); its
+// value is sum_k W_k rho^N(s + c_k) / den_s over fluid neighbours, so the gather adds
+// W_k dL/drho^N(s) / den_s to fluid node s + c_k.  Writes dL/drho^N(s) / den_s into loc[s].
+template <int Q>
+__global__ __launch_bounds__(kTPBX) void k_adj_wet(const uint8_t* __restrict__ flags,
+                                                   double* __restrict__ loc,
+                                                   const double* __restrict__ lamF, Geo g) {
+    int x, y, z;
+    long long n;
+    const bool valid = node_xyz(g, x, y, z, n);
+    const RowOff r = row_offsets<char>(g, x < g.nx ? x : 0);  // element offsets
+    if (!valid || !flags[n]) return;
+    double G = 0.0, den = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const long long m = r.yrow[1 - Lat<Q>::cy[i]] + r.zpl[1 - Lat<Q>::cz[i]] +
+                            r.xo[1 - Lat<Q>::cx[i]];  // s - c_i
+        double v = 0.0;
+        if (Lat<Q>::cx[i]) v += Lat<Q>::cx[i] * lamF[m];
+        if (Lat<Q>::cy[i]) v += Lat<Q>::cy[i] * lamF[g.N + m];
+        if (Lat<Q>::cz[i]) v += Lat<Q>::cz[i] * lamF[2 * g.N + m];
+        G += 3.0 * weight<Q>(i) * v;
+        const long long k = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]] +
+                            r.xo[1 + Lat<Q>::cx[i]];  // s + c_i
+        if (!flags[k]) den += weight<Q>(i);
+    }
+    loc[n] = den > 0.0 ? G / den : 0.0;
+}
+
 // Transposed gradient stencil, assembly of (a, b), and the sink adjoint.
 // At unit tau the result a is folded into q0 = p0 + a (mu0, written by the local kernel).
-template <int Q, typename S, typename M, bool UNIT>
+template <int Q, typename S, typename M, bool UNIT, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_adj_gather(
-    const void* __restrict__ carry, const void* __restrict__ phi_field,
+    const uint8_t* __restrict__ flags, const void* __restrict__ carry,
+    const void* __restrict__ phi_field,
     const MomT<S>* __restrict__ rhoNf,
     const double* __restrict__ loc, const double* __restrict__ lamF,
     double* __restrict__ q0, double* __restrict__ ab0, double* __restrict__ aF0,
@@ -442,7 +510,12 @@ __global__ __launch_bounds__(kTPBX) void k_adj_gather(
     const bool valid = node_xyz(g, x, y, z, n);
     const RowOff r = row_offsets<char>(g, x < g.nx ? x : 0);  // element offsets
     double gg = 0.0;
-    if (valid) {
+    if (valid && WALLS && flags[n]) {  // solid: no sink, no adjoint state
+        if constexpr (!UNIT) ab0[n] = 0.0;
+        ab0[g.N + n] = 0.0;
+        aF0[n] = 0.0;
+        if (grad_phi_t) grad_phi_t[n] = 0.0;
+    } else if (valid) {
         double G = loc[n];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {  // F(x - c_i) contains 3 W_i c_i rho^N(x)
@@ -453,6 +526,8 @@ __global__ __launch_bounds__(kTPBX) void k_adj_gather(
             if (Lat<Q>::cy[i]) v += Lat<Q>::cy[i] * lamF[g.N + m];
             if (Lat<Q>::cz[i]) v += Lat<Q>::cz[i] * lamF[2 * g.N + m];
             G += 3.0 * weight<Q>(i) * v;
+            // the wetting value of a solid x - c_i is a mean that includes rho^N(x)
+            if (WALLS && flags[m]) G += weight<Q>(i) * loc[m];
         }
         const double rho = loc[g.N + n];
         const double rN = static_cast<double>(rhoNf[n]);
@@ -498,8 +573,9 @@ static hipError_t zero(double* p, long long n, hipStream_t s) {
 
 // post-sink rho^N of a stored state (same arithmetic as the forward first pass, stored at
 // the same precision)
-template <int Q, typename S, typename M>
+template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src,
+                                                       const uint8_t* __restrict__ flags,
                                                        const void* __restrict__ carry,
                                                        const void* __restrict__ phi_field,
                                                        MomT<S>* __restrict__ rhoN, Geo g,
@@ -507,9 +583,10 @@ __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src
     int x, y, z;
     long long n;
     if (!node_xyz(g, x, y, z, n)) return;
+    if (WALLS && flags[n]) return;  // the wetting value follows (k_wet)
     const Nb b = wrap(g, x, y, z);
     M ft[Q], dd[Q], j[3], drho, dsum;
-    pull<Q, false>(src, nullptr, g, b, x, y, z, n, ft, dd);
+    pull<Q, WALLS>(src, flags, g, b, x, y, z, n, ft, dd);
     moments<Q>(ft, dd, drho, dsum, j);
     const M rho = P.rho_ref + drho;
     dsum -= M(2) * site_sink<S>(P, carry, phi_field, n, rho, dsum);
@@ -519,54 +596,55 @@ __global__ __launch_bounds__(kTPBX) void k_phase_state(const S* __restrict__ src
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status seed_impl(cge_ctx* c, const double* g_rhoN, const double* g_rho, AdjWork w,
                             bool unit) {
-    if constexpr (WALLS) {
-        return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
-    } else {
-        const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-        const S* src = static_cast<const S*>(c->pop[c->cur]);
-        if (unit)
-            hipLaunchKernelGGL((k_adj_seed<Q, S, M, 4>), gr, bl, 0, c->stream, src, g_rhoN,
-                               g_rho, w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
-        else
-            hipLaunchKernelGGL((k_adj_seed<Q, S, M, Q>), gr, bl, 0, c->stream, src, g_rhoN,
-                               g_rho, w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
-        return check(c, hipGetLastError(), "adjoint seed");
-    }
+    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+    const S* src = static_cast<const S*>(c->pop[c->cur]);
+    if (unit)
+        hipLaunchKernelGGL((k_adj_seed<Q, S, M, 4, WALLS>), gr, bl, 0, c->stream, src, c->flags,
+                           g_rhoN, g_rho, w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
+    else
+        hipLaunchKernelGGL((k_adj_seed<Q, S, M, Q, WALLS>), gr, bl, 0, c->stream, src, c->flags,
+                           g_rhoN, g_rho, w.mu[1], w.ab[1], w.aF[1], c->g, phys<M>(c));
+    return check(c, hipGetLastError(), "adjoint seed");
 }
 
 // One reverse step, adjoint 1 -> 0.  General tau: from the stored state (pop, carry).  Unit
-// tau: from the step's phase field, moments and carry (pop unused).
+// tau: from the step's phase field, moments and carry (pop unused).  With solid nodes the
+// phase field holds the wetting values there, as in the forward.
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status rstep_impl(cge_ctx* c, const void* pop, const void* rhoN_in, const void* mom,
                              const void* carry, AdjWork w, double* grad_phi, double* grad_phi_t) {
-    if constexpr (WALLS) {
-        return fail(c, CGE_EUNSUPPORTED, "adjoint needs a periodic domain without solid nodes");
+    const Phys<double> P = phys<double>(c);
+    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+    if (pop) {
+        MomT<S>* r = static_cast<MomT<S>*>(c->rhoN);
+        hipLaunchKernelGGL((k_phase_state<Q, S, M, WALLS>), gr, bl, 0, c->stream,
+                           static_cast<const S*>(pop), c->flags, carry, c->phi_field, r, c->g,
+                           phys<M>(c));
+        if (WALLS)
+            hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, r, c->g);
+        hipLaunchKernelGGL((k_adj_local<Q, S, M, WALLS>), gr, bl, 0, c->stream,
+                           static_cast<const S*>(pop), c->flags, r, w.mu[1], w.ab[1], w.aF[1],
+                           w.mu[0], w.loc, w.lamF, c->g, P);
+        if (WALLS)
+            hipLaunchKernelGGL((k_adj_wet<Q>), gr, bl, 0, c->stream, c->flags, w.loc, w.lamF,
+                               c->g);
+        hipLaunchKernelGGL((k_adj_gather<Q, S, M, false, WALLS>), gr, bl, 0, c->stream, c->flags,
+                           carry, c->phi_field, r, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
+                           grad_phi, grad_phi_t, w.gpart, c->g, P);
     } else {
-        const Phys<double> P = phys<double>(c);
-        const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-        if (pop) {
-            MomT<S>* r = static_cast<MomT<S>*>(c->rhoN);
-            hipLaunchKernelGGL((k_phase_state<Q, S, M>), gr, bl, 0, c->stream,
-                               static_cast<const S*>(pop), carry, c->phi_field, r, c->g,
-                               phys<M>(c));
-            hipLaunchKernelGGL((k_adj_local<Q, S, M>), gr, bl, 0, c->stream,
-                               static_cast<const S*>(pop), r, w.mu[1], w.ab[1], w.aF[1], w.mu[0],
-                               w.loc, w.lamF, c->g, P);
-            hipLaunchKernelGGL((k_adj_gather<Q, S, M, false>), gr, bl, 0, c->stream, carry,
-                               c->phi_field, r, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
-                               grad_phi, grad_phi_t, w.gpart, c->g, P);
-        } else {
-            // rho^N as the split step stores it (the moment record's type)
-            const MomT<S>* rhoN = static_cast<const MomT<S>*>(rhoN_in);
-            hipLaunchKernelGGL((k_adj_local_unit<Q, S, M>), gr, bl, 0, c->stream, rhoN,
-                               static_cast<const MomT<S>*>(mom), w.mu[1], w.ab[1], w.aF[1],
-                               w.mu[0], w.loc, w.lamF, c->g, P);
-            hipLaunchKernelGGL((k_adj_gather<Q, S, M, true>), gr, bl, 0, c->stream, carry,
-                               c->phi_field, rhoN, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
-                               grad_phi, grad_phi_t, w.gpart, c->g, P);
-        }
-        return check(c, hipGetLastError(), "adjoint step");
+        // rho^N as the split step stores it (the moment record's type)
+        const MomT<S>* rhoN = static_cast<const MomT<S>*>(rhoN_in);
+        hipLaunchKernelGGL((k_adj_local_unit<Q, S, M, WALLS>), gr, bl, 0, c->stream, c->flags,
+                           rhoN, static_cast<const MomT<S>*>(mom), w.mu[1], w.ab[1], w.aF[1],
+                           w.mu[0], w.loc, w.lamF, c->g, P);
+        if (WALLS)
+            hipLaunchKernelGGL((k_adj_wet<Q>), gr, bl, 0, c->stream, c->flags, w.loc, w.lamF,
+                               c->g);
+        hipLaunchKernelGGL((k_adj_gather<Q, S, M, true, WALLS>), gr, bl, 0, c->stream, c->flags,
+                           carry, c->phi_field, rhoN, w.loc, w.lamF, w.mu[0], w.ab[0], w.aF[0],
+                           grad_phi, grad_phi_t, w.gpart, c->g, P);
     }
+    return check(c, hipGetLastError(), "adjoint step");
 }
 
 static cge_status adjoint_seed(cge_ctx* c, const double* g_rhoN, const double* g_rho,
@@ -606,8 +684,8 @@ cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ck
     if (c->hf_every > 0 || c->out_lo || c->out_hi)
         return fail(c, CGE_EUNSUPPORTED, "the adjoint supports neither the height flux nor outlets");
     // at unit tau the backward recomputes with the split step, so the forward uses it too and
-    // the recomputed trajectory is the forward's bit for bit
-    const bool split = unit_tau(&c->p) && !c->flags;
+    // the recomputed trajectory is the forward's bit for bit (with or without solid nodes)
+    const bool split = unit_tau(&c->p);
     const long long nseg = (nsteps + K - 1) / K;
     for (long long j = 0; j <= nseg; ++j)
         if (!ckpt[j]) return fail(c, CGE_EINVAL, "NULL checkpoint buffer");
@@ -626,7 +704,6 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps < 1 || K < 1 || !ckpt || !seg || !work || (!dL_drhoN && !dL_drho) || !grad_phi)
         return fail(c, CGE_EINVAL, "missing argument");
-    if (c->flags) return fail(c, CGE_EUNSUPPORTED, "adjoint needs a domain without solid nodes");
     if (c->hf_every > 0 || c->out_lo || c->out_hi)
         return fail(c, CGE_EUNSUPPORTED, "the adjoint supports neither the height flux nor outlets");
     if (c->p.site_rule == CGE_SITE_PHASE_LT)

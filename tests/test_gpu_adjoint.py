@@ -39,6 +39,13 @@ CASES = {
     "d3q19_hard": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3), 3.3),
     # relaxation times other than 1: the reverse step recomputes from stored populations
     "d3q19_tau": ("sphere3d", (8, 9, 10), dict(radius=3.0, phi=3e-3, tau=(1.0, 0.8)), 3.3),
+    # solid nodes: bounce-back pairs and wetting values in the transpose
+    "d2q9_walls_hard": ("flat2d", (1, 20, 22), dict(phi=3e-3, site_rule="grad"), 6.0),
+    "d2q9_walls_soft_tau": ("flat2d", (1, 20, 22), dict(phi=3e-3, site_rule="soft", kappa=0.02,
+                                                        tau=(1.0, 0.8)), 6.0),
+    "d3q19_walls_ratio": ("sessile3d", (8, 12, 14), dict(radius=4.0, phi=3e-3), 4.0),
+    "d3q19_walls_soft": ("hemisphere3d", (10, 12, 12), dict(radius=4.0, phi=3e-3,
+                                                            site_rule="soft", kappa=0.02), 4.5),
 }
 
 
@@ -57,7 +64,10 @@ def _gpu_gradients(w, target, nsteps, K, precision="fp64", per_step=False, kerne
     ck = sim.forward_ckpt(nsteps, K)
     rn = sim.fields()["rhoN"]
     g = 2.0 * (rn - torch.as_tensor(target, device=rn.device))
-    loss = float(((rn.cpu().numpy() - target) ** 2).sum())
+    d2 = (rn.cpu().numpy() - target) ** 2
+    if w["solid"] is not None:  # the loss runs over the fluid nodes (seeds at solid ones are ignored)
+        d2 = np.where(w["solid"] != 0, 0.0, d2)
+    loss = float(d2.sum())
     r = sim.backward(ck, nsteps, K, g, per_step=per_step)
     step = sim.observables()["step"]
     out = {"loss": loss, "grad_phi": r["grad_phi"].cpu().numpy(), "grad_gamma": r["grad_gamma"],
@@ -78,7 +88,8 @@ def test_fp64_gradients_match_the_autograd_reference(name):
     nsteps, K = 25, 7  # segments 7, 7, 7, 4
     _flush(f"[adjoint fp64] {name} {w['rho_r'].shape} n={nsteps} K={K}")
     got = _gpu_gradients(w, target, nsteps, K)
-    ref = A.gradients(p, w["rho_r"], w["rho_b"], w["phi_field"], nsteps, target)
+    ref = A.gradients(p, w["rho_r"], w["rho_b"], w["phi_field"], nsteps, target,
+                      solid=w["solid"])
     assert abs(got["loss"] - ref["loss"]) <= 1e-12 * ref["loss"]
     gr = ref["grad_phi"].numpy()
     assert np.abs(gr).max() > 0
@@ -293,19 +304,49 @@ def test_backward_is_repeatable_and_restores_the_state(name):
 
 
 def test_unsupported_configurations_are_rejected():
+    """The |rho^N| < Gamma site rule has no adjoint (the outlets and the height flux are
+    refused by the checkpointed forward: tests/test_gpu_outlet.py)."""
     import torch
     from paper_2412_14859_amd import cgevap
-    w = case("flat2d", (1, 12, 16), phi=1e-3)  # solid walls
-    sim = gpu_for(w, "fp64")
-    ck = sim.forward_ckpt(2, 2)
-    with pytest.raises(cgevap.CgeError) as e:
-        sim.backward(ck, 2, 2, torch.zeros(sim.shape, dtype=torch.float64, device=sim.device))
-    assert e.value.status == cgevap.EUNSUPPORTED
-    sim.close()
     w = case("drop2d", (1, 12, 16), radius=4.0, phi=1e-3)  # |rho^N| < Gamma site rule
     sim = gpu_for(w, "fp64")
     ck = sim.forward_ckpt(2, 2)
     with pytest.raises(cgevap.CgeError) as e:
         sim.backward(ck, 2, 2, torch.zeros(sim.shape, dtype=torch.float64, device=sim.device))
     assert e.value.status == cgevap.EUNSUPPORTED
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_red_mass_covector_with_walls(precision):
+    """A hemispherical drop on a wall (64^3, walls at both ends, 300 steps, K = 50, hard
+    sites).  Every operator but the sink conserves red mass, bounce-back and wetting
+    included, so for L = final red mass the per-step gradient is exactly dL/dphi(x, t) =
+    -m(x, t)/Sbar: 0 or -1/Sbar at fluid nodes, 0 at solid ones, and sum_x phi dL/dphi is
+    minus the mass the sink removed."""
+    import torch
+    w = case("hemisphere3d", (64, 64, 64), radius=20.0, phi=3e-3)
+    p = w["params"]
+    nsteps, K = 300, 50
+    _flush(f"[adjoint walls] hemisphere 64^3 red-mass covector {precision}")
+    sim = gpu_for(w, precision)
+    ck = sim.forward_ckpt(nsteps, K)
+    obs = sim.observables()
+    fl = sim.fields()
+    rho = fl["rho_r"] + fl["rho_b"]
+    r = sim.backward(ck, nsteps, K, dL_drhoN=rho / 2, dL_drho=(1 + fl["rhoN"]) / 2,
+                     per_step=True)
+    gt = r["grad_phi_t"].cpu().numpy() * p["sbar"]
+    solid = w["solid"] != 0
+    assert np.abs(gt[:, solid]).max() == 0.0
+    vals = gt[:, ~solid]
+    dist = np.minimum(np.abs(vals), np.abs(vals + 1.0))
+    _flush(f"  |Sbar dL/dphi - {{0, -1}}| max {dist.max():.2e}; sites {int((vals < -0.5).sum())}")
+    assert dist.max() < 1e-11
+    assert (vals < -0.5).sum() > 0
+    phi = sim.phi_field.to(torch.float64)
+    lhs = float((phi * r["grad_phi"]).sum())
+    rel = abs(lhs + obs["sink_total"]) / obs["sink_total"]
+    _flush(f"  sum phi dL/dphi {lhs:.12e}, sink total {obs['sink_total']:.12e}, rel {rel:.2e}")
+    assert rel < 1e-11
     sim.close()
