@@ -127,6 +127,10 @@ def calibrate_dynamic(workload, kind, phi, equil=4000, t_star=0.8, snapshots=40,
     (lo, hi) blue outlets switched on for the evaporation; solid_layers: wall thickness under
     a film.  Returns (Gamma, details)."""
     from paper_2412_14859_amd import cgevap
+    if snapshots < 1 or iterations < 1 or not phi > 0:
+        raise ValueError("snapshots and iterations must be >= 1 and phi > 0")
+    if kind not in ("sphere", "hemisphere", "flat"):
+        raise ValueError(kind)
     w = workload
     p0 = w["params"]
     dim = 2 if int(p0["Q"]) == 9 else 3

@@ -52,3 +52,13 @@ def test_rate_threshold_pools_the_snapshots():
     s_lo, s_hi = cal.gamma_interval(rows[0], np.ones(rows[0].shape, bool), 48)
     g, (p_lo, p_hi) = cal.gamma_for_rate(rows, 3 * 48)
     assert p_hi - p_lo < s_hi - s_lo
+
+
+def test_rate_calibration_rejects_bad_arguments_before_any_device_work():
+    from paper_2412_14859_amd import inputs
+    w = inputs.workload("contrast_flat3d", shape=(16, 4, 4), ratio=1.0)
+    for kw in (dict(snapshots=0), dict(iterations=0), dict(phi=0.0), dict(kind="torus")):
+        args = dict(kind="flat", phi=3e-3)
+        args.update(kw)
+        with pytest.raises(ValueError):
+            cal.calibrate_dynamic(w, **args)
