@@ -183,7 +183,8 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     c->kernel = CGE_KERNEL_TWOPASS;  // resolved at cge_bind
     // the moment record also serves the checkpointed forward run of the adjoint at unit tau
     const bool need_mom = unit;
-    const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type
+    const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type (the
+                                                                   // widest use of rhoN)
     c->acc_len = twopass_blocks(c);
     if (c->Q == 19 && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
     c->obs_blocks = twopass_blocks(c);

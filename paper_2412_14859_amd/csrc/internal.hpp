@@ -27,7 +27,9 @@ struct cge_ctx {
     const void* phi_field = nullptr;
     bool bound = false;
     // library scratch
-    void* rhoN = nullptr;           // N elements of the arithmetic type
+    void* rhoN = nullptr;           // N elements of the arithmetic type: the step forms keep
+                                    // their rho^N field here at storage precision, the step-0
+                                    // site data computes from it in the arithmetic type
     unsigned char* carry2 = nullptr;  // second site-mask buffer of the fused step (N bytes)
     void* mom = nullptr;              // moment record of the split step ([4][N])
     double* acc_sink = nullptr;     // per-block cumulative sink (FP64)
