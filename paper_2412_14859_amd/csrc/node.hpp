@@ -33,21 +33,31 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 // Round v to half precision stochastically: the neighbour above |v| is taken with
 // probability proportional to the distance from the one below, so the rounding is
 // unbiased in expectation (needed for per-step sinks far below one half-precision ulp).
+// Where half has a spacing coarser than float's (|v| >= 2^-24), the float bits below the
+// half spacing are dropped after adding that many random bits: a carry out of them (to the
+// next half number, possibly across a power of two) happens with probability equal to
+// their value over the spacing, so the expectation is exact.  Below 2^-24 the result is 0
+// or 2^-24, up with probability |v| 2^24 on a 2^-24 grid (bias at most 2^-48).  At and
+// above the largest half (65504), and for inf and nan, it is rounded to nearest.
 __device__ __forceinline__ _Float16 sr_half(float v, uint32_t r) {
-    const _Float16 h = static_cast<_Float16>(v);
-    const float b = static_cast<float>(h);
-    if (b == v || !(fabsf(v) < 65504.0f)) return h;
-    const uint16_t hb = __builtin_bit_cast(uint16_t, h);
-    const bool h_is_hi = fabsf(b) > fabsf(v);
-    const uint16_t ob = h_is_hi ? (uint16_t)(hb - 1) : (uint16_t)(hb + 1);
-    const _Float16 o = __builtin_bit_cast(_Float16, ob);
-    const float of = static_cast<float>(o);
-    const float lo = h_is_hi ? fabsf(of) : fabsf(b);
-    const float hi = h_is_hi ? fabsf(b) : fabsf(of);
-    // up with probability (|v| - lo) / (hi - lo), compared without the division
-    const float u = static_cast<float>(r >> 8) * 5.9604644775390625e-8f;  // 2^-24
-    const bool up = u * (hi - lo) < fabsf(v) - lo;
-    return up == h_is_hi ? h : o;
+    const uint32_t u = __builtin_bit_cast(uint32_t, v);
+    const uint32_t a = u & 0x7FFFFFFFu;
+    if (!(a < 0x477FE000u)) return static_cast<_Float16>(v);  // |v| >= 65504, inf, nan
+    const int e = static_cast<int>(a >> 23);                  // biased float exponent
+    uint32_t t;
+    if (e >= 103) {
+        // bits of the float fraction below the half spacing: 13 for normal halves, up to 23
+        // in the subnormal range where the spacing stays 2^-24
+        const int drop = e < 113 ? 126 - e : 13;
+        const uint32_t mask = (1u << drop) - 1u;
+        t = (a + (r & mask)) & ~mask;
+    } else {
+        const float p = __builtin_bit_cast(float, a) * 16777216.0f;             // |v| 2^24
+        const float q = static_cast<float>(r >> 8) * 5.9604644775390625e-8f;   // k 2^-24
+        t = q < p ? 0x33800000u : 0u;                                           // 2^-24 or 0
+    }
+    // t is a half number, so this conversion is exact
+    return static_cast<_Float16>(__builtin_bit_cast(float, t | (u & 0x80000000u)));
 }
 
 // 32-bit finaliser of MurmurHash3 (Appleby): a bijection with full avalanche, used to turn a
