@@ -29,14 +29,25 @@ def algorithmic_bytes_per_node(Q, precision, walls=False, phi_field=False):
     return 2 * Q * 2 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
 
 
+def record_bytes_per_node(precision, walls=False, phi_field=False):
+    """What the record form stores between steps: the 14-value post-collision record read
+    once and written once (FP64 at FP64 storage, FP32 otherwise), plus the site data, the
+    flux field and the solid flag as above."""
+    elem = 8 if precision == "fp64" else 4
+    return 2 * 14 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
+
+
 STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fused", "fused"),
-                "k_finish": ("k_moments+k_finish", "split")}
+                "k_finish": ("k_moments+k_finish", "split"),
+                "k_pull_record": ("k_pull_record+k_finish_record", "record")}
+# source file of each step form (the record form's kernels live beside the split form's)
+FORM_FILE = {"twopass": "twopass", "fused": "fused", "split": "split", "record": "split"}
 
 
 def kernel_sources(tag):
     """The files a step form's kernels and launches are compiled from."""
     csrc = os.path.join(ROOT, "paper_2412_14859_amd", "csrc")
-    return [os.path.join(csrc, f) for f in (f"{tag}.hip", "node.hpp", "lattice.hpp",
+    return [os.path.join(csrc, f) for f in (f"{FORM_FILE[tag]}.hip", "node.hpp", "lattice.hpp",
                                             "internal.hpp")] + \
         [os.path.join(ROOT, "include", "cgevap.h")]
 
@@ -95,14 +106,18 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
     bpn = algorithmic_bytes_per_node(p["Q"], precision, w["solid"] is not None,
                                      w["phi_field"] is not None)
     per_launch_ms = ker_ms / max(ker_steps, 1)
+    kname = sim.kernel_name()
     res = {
         "precision": precision,
-        "kernel": sim.kernel_name(),
+        "kernel": kname,
         "mlups": N * steps / wall / 1e6,
         "ms_per_step": wall * 1e3 / steps,
         "kernel_ms_per_step": per_launch_ms,
         "bytes_per_node": bpn,
         "achieved_gbs": bpn * N / (per_launch_ms * 1e-3) / 1e9,
+        "stored_state_bytes_per_node": (record_bytes_per_node(
+            precision, w["solid"] is not None, w["phi_field"] is not None)
+            if kname == "k_pull_record" else bpn),
         "v_mass": obs["v_mass"],
         "site_steps": obs["site_steps"],
         "n_negative": obs["n_negative"],
@@ -530,7 +545,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32s", choices=["fp64", "fp32s", "fp16s"])
-    ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused", "split"])
+    ap.add_argument("--kernel", default="auto",
+                    choices=["auto", "twopass", "fused", "split", "record"])
     ap.add_argument("--size", type=int, default=256, help="edge of the cubic box")
     ap.add_argument("--no-legs", action="store_true", help="skip the FP64 and FP16S legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -631,6 +647,12 @@ def main():
                      "kernel": STEP_KERNELS[main_leg["kernel"]][0],
                      "kernel_ms_per_step": round(main_leg["kernel_ms_per_step"], 4),
                      "bytes_per_node": main_leg["bytes_per_node"],
+                     # bytes the step form stores between steps (the record form: 14 values
+                     # per node instead of 2Q populations), and the HBM fraction they give
+                     "stored_state_bytes_per_node": main_leg["stored_state_bytes_per_node"],
+                     "stored_state_frac": round(
+                         main_leg["stored_state_bytes_per_node"] * N
+                         / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "copy_probe_gbs": round(copy_gbs, 1),
                      "frac_of_copy": round(achieved / copy_gbs, 4)},
         "legs": {k: {kk: (float(f"{vv:.9g}") if isinstance(vv, float) else vv)

@@ -66,13 +66,25 @@ typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } 
  *   SPLIT:   unit relaxation times (tau[0] == tau[1] == 1, else CGE_EUNSUPPORTED at
  *            cge_create), any lattice and geometry; the first pass writes the post-sink
  *            moments, the second finishes the step from them without re-reading populations.
- *   AUTO:    SPLIT where supported, else FUSED where supported, else TWOPASS.
+ *   RECORD:  SPLIT's two passes, but between the steps of one cge_step call each node keeps
+ *            a record of 14 values from which its post-collision populations follow at unit
+ *            relaxation (post-sink density and phase field, velocity, colour gradient and
+ *            the per-class coefficients of the equilibrium, perturbation (Eq. perturb) and
+ *            recolouring (Eq. recolor)) instead of its 2Q populations.  The first step of
+ *            a call pulls populations and the last writes them, so between calls the state
+ *            is populations as for every other form; a call of one step is SPLIT's step.
+ *            Same support as SPLIT; needs 14 N values of library scratch (FP64 at FP64
+ *            storage, FP32 otherwise; rows padded to 256 B), allocated at cge_create for
+ *            RECORD, and for AUTO at FP64 and FP32 storage.
+ *   AUTO:    at unit relaxation times RECORD (SPLIT at FP16 storage, whose state between
+ *            steps then stays in half precision), else FUSED where supported, else TWOPASS.
  * All give the same results up to rounding. */
 typedef enum {
     CGE_KERNEL_AUTO = 0,
     CGE_KERNEL_TWOPASS = 1,
     CGE_KERNEL_FUSED = 2,
-    CGE_KERNEL_SPLIT = 3
+    CGE_KERNEL_SPLIT = 3,
+    CGE_KERNEL_RECORD = 4
 } cge_kernel;
 
 typedef struct {

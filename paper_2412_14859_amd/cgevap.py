@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libcgevap.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 PRECISIONS = {"fp64": 0, "fp32s": 1, "fp16s": 2}
-KERNELS = {"auto": 0, "twopass": 1, "fused": 2, "split": 3}
+KERNELS = {"auto": 0, "twopass": 1, "fused": 2, "split": 3, "record": 4}
 SITE_RULES = {"grad": 0, "phase": 1, "soft": 2}
 ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 

@@ -142,7 +142,7 @@ static const char* validate(const cge_params* p) {
         return "unknown site rule";
     if (p->site_rule == CGE_SITE_SOFT && !(is_fin(p->kappa) && p->kappa > 0.0))
         return "kappa must be > 0 for the soft site rule";
-    if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_SPLIT) return "unknown kernel";
+    if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_RECORD) return "unknown kernel";
     return nullptr;
 }
 
@@ -176,13 +176,17 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     const bool unit = split_supported(c);
     const bool soft = params->site_rule == CGE_SITE_SOFT;
     if ((params->kernel == CGE_KERNEL_FUSED && (c->Q != 19 || soft)) ||
-        (params->kernel == CGE_KERNEL_SPLIT && !unit)) {
+        ((params->kernel == CGE_KERNEL_SPLIT || params->kernel == CGE_KERNEL_RECORD) && !unit)) {
         delete c;
         return CGE_EUNSUPPORTED;
     }
     c->kernel = CGE_KERNEL_TWOPASS;  // resolved at cge_bind
     // the moment record also serves the checkpointed forward run of the adjoint at unit tau
     const bool need_mom = unit;
+    // records for the record form, which auto selects at unit tau with FP64 or FP32 storage
+    const bool need_rec =
+        unit && (params->kernel == CGE_KERNEL_RECORD ||
+                 (params->kernel == CGE_KERNEL_AUTO && params->precision != CGE_FP16S));
     const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type (the
                                                                    // widest use of rhoN)
     c->acc_len = twopass_blocks(c);
@@ -190,6 +194,7 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     c->obs_blocks = twopass_blocks(c);
     bool ok = (c->Q != 19 || hipMalloc(&c->carry2, c->g.N) == hipSuccess) &&
               (!need_mom || hipMalloc(&c->mom, split_scratch_bytes(params)) == hipSuccess) &&
+              (!need_rec || hipMalloc(&c->rec, record_bytes(params)) == hipSuccess) &&
               hipMalloc(&c->rhoN, c->g.N * mbytes) == hipSuccess &&
               hipMalloc(&c->acc_sink, c->acc_len * sizeof(double)) == hipSuccess &&
               hipMalloc(&c->acc_sites, c->acc_len * sizeof(long long)) == hipSuccess &&
@@ -229,8 +234,9 @@ cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
             c->kernel = fused_supported(c) ? CGE_KERNEL_FUSED : CGE_KERNEL_TWOPASS;
             break;
         case CGE_KERNEL_SPLIT: c->kernel = CGE_KERNEL_SPLIT; break;
+        case CGE_KERNEL_RECORD: c->kernel = CGE_KERNEL_RECORD; break;
         default:
-            c->kernel = split_supported(c) ? CGE_KERNEL_SPLIT
+            c->kernel = split_supported(c) ? (c->rec ? CGE_KERNEL_RECORD : CGE_KERNEL_SPLIT)
                                : (fused_supported(c) ? CGE_KERNEL_FUSED : CGE_KERNEL_TWOPASS);
     }
     c->bound = true;
@@ -375,6 +381,7 @@ static cge_status run_steps(cge_ctx* c, long long nsteps) {
     switch (c->kernel) {
         case CGE_KERNEL_FUSED: return fused_steps(c, nsteps);
         case CGE_KERNEL_SPLIT: return split_steps(c, nsteps);
+        case CGE_KERNEL_RECORD: return record_steps(c, nsteps);
         default: return twopass_steps(c, nsteps);
     }
 }
@@ -467,6 +474,7 @@ const char* cge_kernel_name(const cge_ctx* c) {
     switch (c->kernel) {
         case CGE_KERNEL_FUSED: return "k_fused";
         case CGE_KERNEL_SPLIT: return "k_finish";
+        case CGE_KERNEL_RECORD: return "k_pull_record";
         default: return "k_collide";
     }
 }
@@ -510,6 +518,7 @@ void cge_destroy(cge_ctx* c) {
     (void)hipFree(c->hf_part);
     (void)hipFree(c->carry2);
     (void)hipFree(c->mom);
+    (void)hipFree(c->rec);
     (void)hipFree(c->acc_sink);
     (void)hipFree(c->acc_sites);
     (void)hipFree(c->obs_part);

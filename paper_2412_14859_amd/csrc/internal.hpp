@@ -32,6 +32,7 @@ struct cge_ctx {
                                     // site data computes from it in the arithmetic type
     unsigned char* carry2 = nullptr;  // second site-mask buffer of the fused step (N bytes)
     void* mom = nullptr;              // moment record of the split step ([4][N])
+    void* rec = nullptr;              // post-collision records of the record step ([14][N])
     double* acc_sink = nullptr;     // per-block cumulative sink (FP64)
     long long* acc_sites = nullptr; // per-block cumulative site count
     long long acc_len = 0;
@@ -74,6 +75,10 @@ cge_status fused_steps(cge_ctx* c, long long nsteps);
 cge_status split_steps(cge_ctx* c, long long nsteps);
 bool split_supported(const cge_ctx* c);
 size_t split_scratch_bytes(const cge_params* p);
+// record form of the split step: the state between the steps of one call is kept as
+// per-node post-collision records
+cge_status record_steps(cge_ctx* c, long long nsteps);
+size_t record_bytes(const cge_params* p);
 // one split step with explicit site-data, phase-field and moment buffers
 cge_status split_step_into(cge_ctx* c, const void* carry_in, void* carry_out, void* rhoN,
                            void* mom);

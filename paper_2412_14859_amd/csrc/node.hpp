@@ -159,6 +159,57 @@ __device__ __forceinline__ RowOff row_offsets(const Geo& g, int x) {
     return r;
 }
 
+// XCD-aware placement of the one-thread-per-node blocks.  Workgroups are dealt to the 8 XCDs
+// round-robin by linear block id, and each XCD has its own L2.  Kernels whose nodes read
+// their neighbours' rows (a stencil with reuse) renumber the blocks: rows are taken in bands
+// of kBandY consecutive y, each band walking z (all x-blocks of a row, then the band's rows
+// of a plane, then the next plane), and XCD k takes a contiguous run of that order.  The rows
+// an XCD works on at one time then form a patch of kBandY rows by a few planes, whose
+// neighbours (the patch plus one row and one plane around it) stay in its L2.  The map is a
+// bijection of [0, blocks).
+constexpr int kXcds = 8, kBandY = 16;
+struct RowPos {
+    int bx, y, z;  // x-block, row and plane of this block (uniform)
+};
+__device__ __forceinline__ RowPos xcd_row(const Geo& g) {
+    const unsigned gx = gridDim.x, ny = gridDim.y, nz = gridDim.z;
+    const unsigned nb = gx * ny * nz;
+    const unsigned b = blockIdx.x + gx * (blockIdx.y + ny * blockIdx.z);
+    const unsigned q = nb / kXcds, rem = nb % kXcds, k = b % kXcds, l = b / kXcds;
+    const unsigned r = k * q + (k < rem ? k : rem) + l;  // position in band order
+    const unsigned band_blocks = kBandY * nz * gx;       // blocks of one full band
+    const unsigned band = r / band_blocks;
+    const unsigned h = ny - band * kBandY < (unsigned)kBandY ? ny - band * kBandY : kBandY;
+    const unsigned t = r - band * band_blocks;           // within the band
+    RowPos p;
+    p.bx = __builtin_amdgcn_readfirstlane((int)(t % gx));
+    const unsigned yz = t / gx;
+    p.y = __builtin_amdgcn_readfirstlane((int)(band * kBandY + yz % h));
+    p.z = __builtin_amdgcn_readfirstlane((int)(yz / h));
+    return p;
+}
+__device__ __forceinline__ bool node_xyz_at(const Geo& g, const RowPos& p, int& x, int& y, int& z,
+                                            long long& n) {
+    x = p.bx * blockDim.x + threadIdx.x;
+    y = p.y;
+    z = p.z;
+    n = lin(g, x, y, z);
+    return x < g.nx;
+}
+template <typename T>
+__device__ __forceinline__ RowOff row_offsets_at(const Geo& g, const RowPos& p, int x) {
+    RowOff r;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int yo = __builtin_amdgcn_readfirstlane(wrapc(p.y - 1 + d, g.ny) * g.nx);
+        const int zo = __builtin_amdgcn_readfirstlane(wrapc(p.z - 1 + d, g.nz));
+        r.yrow[d] = yo;
+        r.zpl[d] = (long long)zo * ((long long)g.nx * g.ny);
+        r.xo[d] = (uint32_t)wrapc(x - 1 + d, g.nx) * (uint32_t)sizeof(T);
+    }
+    return r;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
@@ -353,6 +404,94 @@ __device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M
         store(i, f1, rhoN * full + gs[k] * Fc);
     }
     return Fn;
+}
+
+// Post-collision record of a node at unit relaxation times (omega_r = omega_b = 1).  BGK
+// relaxation then returns the equilibrium, so collide()'s populations of the node are, per
+// weight class k and direction i of that class (h_k = W_k / W_1),
+//   ft_i* = b_k + h_k A (c_i.u)(1 + 1.5 c_i.u) + h_k P (F.c_i)^2
+//   dd_i* = rho^N (ft_i* + t_ref,k) + g_k (F.c_i)
+// with A = 3 W_1 rho, P = W_1 kp / |F|, b_k = base_k - kc_k and g_k = gs_k formed as in
+// collide (t_ref,k = rho_ref t_k(alpha_ref)).  The record is b_0, b_1, b_2, A, P, u, F,
+// rho^N, g_1, g_2: 14 values instead of 2Q populations.  Returns ||F||.
+constexpr int kRec = 14;
+enum RecSlot { kB0 = 0, kB1, kB2, kA3, kP1, kUx, kUy, kUz, kFx, kFy, kFz, kRhoN, kG1, kG2 };
+
+template <int Q, typename M>
+__device__ __forceinline__ M record_values(M drho, M rho, M rhoN, const M (&u)[3],
+                                          const M (&F)[3], const Phys<M>& P, M (&r)[kRec]) {
+    const M pr = M(0.5) * (M(1) + rhoN);
+    const M pb = M(0.5) * (M(1) - rhoN);
+    const M omega = pr * P.omega_r + pb * P.omega_b;
+    const M abar = pr * P.alpha_r + pb * P.alpha_b;
+    const M dB = rho * (abar - P.alpha_ref) + drho * P.alpha_ref;
+    const M uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const M F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    const bool hg = F2 > M(0);
+    const M Fn = hg ? sqrt(F2) : M(0);
+    const M invFn = hg ? M(1) / Fn : M(0);
+    const M kp = M(2.25) * P.sigma * omega;
+    const M sep = M(0.5) * P.beta * (M(1) - rhoN * rhoN) * rho;
+    const M fade = Fn >= M(2e-5) ? M(1) : (Fn > M(1e-5) ? Fn * M(1e5) - M(1) : M(0));
+    const M cosw = invFn * fade;
+    constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = k == 0 ? 0 : (k == 1 ? i1 : i2);
+        const M A = M(restA<Q>(i)), B = M(restB<Q>(i)), W = M(weight<Q>(i));
+        const M base = A * drho + B * dB - M(1.5) * (W * rho) * uu;
+        r[kB0 + k] = base - kp * M(pertC<Q>(i)) * Fn;
+        if (k > 0) r[kG1 + k - 1] = sep * cosw * M(inv_len<Q>(i)) * (A + B * abar);
+    }
+    const M W1 = M(weight<Q>(i1));
+    r[kA3] = M(3) * W1 * rho;
+    r[kP1] = W1 * (kp * invFn);
+    r[kUx] = u[0];
+    r[kUy] = u[1];
+    r[kUz] = u[2];
+    r[kFx] = F[0];
+    r[kFy] = F[1];
+    r[kFz] = F[2];
+    r[kRhoN] = rhoN;
+    return Fn;
+}
+
+// ft_i* and the colour difference of direction i (sgn = -1: of the opposite direction, for
+// the bounce-back) from the record, in the record's precision E; L(slot) loads one record
+// value of the source node.  dd_i* is returned in two parts, dd_i* = dp + rn t_ref,k:
+// dp = rho^N ft_i* + g_k (F.c_i) and the source's rn = rho^N.  The caller adds rn t_ref,k in
+// its arithmetic type: formed in E, the rounding of t_ref,k would repeat at every node and
+// step and move red mass steadily between the bulks.  Only the values direction i needs are
+// loaded.
+template <int Q, typename E, typename Load>
+__device__ __forceinline__ void record_dir(int i, E sgn, Load&& L, E& a, E& dp, E& rn) {
+    const int k = norm2<Q>(i);
+    rn = L(kRhoN);
+    if (k == 0) {
+        a = L(kB0);
+        dp = rn * a;
+        return;
+    }
+    E cu = E(0), Fc = E(0);
+    if (Lat<Q>::cx[i]) {
+        cu += E(Lat<Q>::cx[i]) * L(kUx);
+        Fc += E(Lat<Q>::cx[i]) * L(kFx);
+    }
+    if (Lat<Q>::cy[i]) {
+        cu += E(Lat<Q>::cy[i]) * L(kUy);
+        Fc += E(Lat<Q>::cy[i]) * L(kFy);
+    }
+    if (Lat<Q>::cz[i]) {
+        cu += E(Lat<Q>::cz[i]) * L(kUz);
+        Fc += E(Lat<Q>::cz[i]) * L(kFz);
+    }
+    cu *= sgn;
+    Fc *= sgn;
+    constexpr double h = weight<Q>(Q == 9 ? 5 : 7) / weight<Q>(1);  // W_2 / W_1
+    const E hk = k == 1 ? E(1) : E(h);
+    a = L(k == 1 ? kB1 : kB2) + L(kA3) * (cu * (hk + E(1.5) * hk * cu));
+    a += (hk * L(kP1)) * (Fc * Fc);
+    dp = rn * a + L(k == 1 ? kG1 : kG2) * Fc;
 }
 
 // Neutral wetting: a solid node takes the W-weighted mean of rho^N over its fluid neighbours.

@@ -1,4 +1,6 @@
-// Split step for unit relaxation times (tau_r = tau_b = 1): two passes, populations read once.
+// Split step for unit relaxation times (tau_r = tau_b = 1): two passes, populations read once,
+// and its record form, which keeps a per-node post-collision record between the steps of
+// one call instead of the populations.
 //
 // With 1/tau = 1 at every node, BGK relaxation returns the equilibrium (Eq. collision), so
 // the post-collision populations depend on the pulled ones only through the post-sink
@@ -87,8 +89,9 @@ __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) v
                                                   Phys<M> P, uint64_t salt) {
     int x, y, z;
     long long n;
-    const bool valid = node_xyz(g, x, y, z, n);
-    const RowOff r = row_offsets<MomT<S>>(g, x < g.nx ? x : 0);  // x offsets into rho^N
+    const RowPos pos = xcd_row(g);  // the rho^N rows around a block stay in one L2
+    const bool valid = node_xyz_at(g, pos, x, y, z, n);
+    const RowOff r = row_offsets_at<MomT<S>>(g, pos, x < g.nx ? x : 0);  // offsets into rho^N
     if (!valid) return;
     if (WALLS && flags[n]) return;
     const M drho = static_cast<M>(mom[n]);
@@ -191,6 +194,324 @@ k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const MomT<S>* __re
     carry_store(P, carry, n, Fn);
 }
 
+// ---------------------------------------------------------------- record form
+//
+// Between the steps of one call the state is the post-collision record of every node
+// (record_values) instead of its 2Q populations: k_finish_record stores the 14 record
+// values where k_finish stores the populations, and k_pull_record rebuilds each pulled
+// population from the source node's record (record_dir) where k_moments loads it.  The
+// first step of a call pulls populations and the last stores them, so callers only see
+// populations.  Per node and step: 14 values read and 14 written (FP32 next to FP32 or FP16
+// populations, FP64 next to FP64) instead of 2Q and 2Q.  A pulled population is rebuilt in
+// the record's precision (a few operations per direction, record_dir) and summed into the
+// moments in the arithmetic type.
+
+// Record layout: rows of nodes (y, z) one after the other; within a row, chunks of kRecW
+// nodes (256 B of one value), and within a chunk the 14 values one after the other.  A
+// node's values are then at one offset plus the value index times 256 B, which the load
+// instruction takes as its immediate offset, and the rows around a node are 9 scalar bases.
+template <typename R>
+struct RecLayout {
+    static constexpr int W = 256 / (int)sizeof(R);  // nodes per chunk
+    __host__ __device__ static long long row_len(int nx) {  // elements per row of nodes
+        return (long long)((nx + W - 1) / W) * W * kRec;
+    }
+    __host__ __device__ static uint32_t in_row(int x) {  // element offset of x within its row
+        return (uint32_t)(x / W) * (uint32_t)(W * kRec) + (uint32_t)(x % W);
+    }
+};
+
+// Sum over the weight classes of t_ref,k times the pulled rho^N of that class (the part of
+// the colour differences record_dir leaves to the arithmetic type).
+template <int Q, typename M>
+__device__ __forceinline__ M ref_part(const Phys<M>& P, const M (&rn)[3]) {
+    constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;
+    M s = M(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int i = k == 0 ? 0 : (k == 1 ? i1 : i2);
+        s += P.rho_ref * (M(restA<Q>(i)) + M(restB<Q>(i)) * P.alpha_ref) * rn[k];
+    }
+    return s;
+}
+
+// Pass 1 from records: pull (Eq. Stream) with every population rebuilt from the record of
+// x - c_i (of x itself, opposite direction, where x - c_i is solid), then the sink and the
+// moments exactly as k_moments.
+template <int Q, typename S, typename M, bool WALLS>
+__global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict__ rec,
+                                                       const uint8_t* __restrict__ flags,
+                                                       const void* __restrict__ carry,
+                                                       const void* __restrict__ phi_field,
+                                                       MomT<S>* __restrict__ rhoN,
+                                                       MomT<S>* __restrict__ mom,
+                                                       double* __restrict__ acc_sink,
+                                                       long long* __restrict__ acc_sites, Geo g,
+                                                       Phys<M> P) {
+    using R = MomT<S>;
+    using L = RecLayout<R>;
+    int x, y, z;
+    long long n;
+    const RowPos pos = xcd_row(g);
+    const bool valid = node_xyz_at(g, pos, x, y, z, n);
+    const long long rlen = L::row_len(g.nx);
+    // rows y-1..y+1 and planes z-1..z+1 (row index y + ny z), x-1..x+1 within a row
+    long long yr[3], zr[3];
+    uint32_t xo[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        yr[d] = (long long)__builtin_amdgcn_readfirstlane(wrapc(pos.y - 1 + d, g.ny)) * rlen;
+        zr[d] = (long long)__builtin_amdgcn_readfirstlane(wrapc(pos.z - 1 + d, g.nz)) * g.ny * rlen;
+        xo[d] = L::in_row(wrapc((x < g.nx ? x : 0) - 1 + d, g.nx)) * (uint32_t)sizeof(R);
+    }
+    double v[2] = {0.0, 0.0};
+    if (valid && !(WALLS && flags[n])) {
+        M j[3] = {M(0), M(0), M(0)}, drho = M(0), dsum = M(0), rn[3] = {M(0), M(0), M(0)};
+        const Nb b = WALLS ? wrap(g, x, y, z) : Nb{};
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            R ar, dr, rr;
+            if constexpr (WALLS) {
+                const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
+                int sx = cx == 1 ? b.xm : (cx == -1 ? b.xp : x);
+                int sy = cy == 1 ? b.ym : (cy == -1 ? b.yp : y);
+                int sz = cz == 1 ? b.zm : (cz == -1 ? b.zp : z);
+                R sgn = R(1);
+                if (i != 0 && flags[lin(g, sx, sy, sz)]) {  // halfway bounce-back: f_opp(i)*(x)
+                    sx = x;
+                    sy = y;
+                    sz = z;
+                    sgn = R(-1);
+                }
+                const R* base = rec + ((long long)sy + (long long)g.ny * sz) * rlen + L::in_row(sx);
+                record_dir<Q, R>(i, sgn, [&](int sl) { return base[sl * L::W]; }, ar, dr, rr);
+            } else {
+                const R* base = rec + yr[1 - Lat<Q>::cy[i]] + zr[1 - Lat<Q>::cz[i]];
+                const uint32_t o = xo[1 - Lat<Q>::cx[i]];
+                record_dir<Q, R>(i, R(1), [&](int sl) { return ld_at(base + sl * L::W, o); },
+                                 ar, dr, rr);
+            }
+            const M a = static_cast<M>(ar);
+            drho += a;
+            dsum += static_cast<M>(dr);
+            rn[norm2<Q>(i)] += static_cast<M>(rr);
+            if (Lat<Q>::cx[i]) j[0] += Lat<Q>::cx[i] * a;
+            if (Lat<Q>::cy[i]) j[1] += Lat<Q>::cy[i] * a;
+            if (Lat<Q>::cz[i]) j[2] += Lat<Q>::cz[i] * a;
+        }
+        dsum += ref_part<Q, M>(P, rn);
+        const M rho = P.rho_ref + drho;
+        M wgt;
+        const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum, wgt);
+        dsum -= M(2) * s;
+        v[0] = static_cast<double>(s);
+        v[1] = is_site(wgt) ? 1.0 : 0.0;
+        rhoN[n] = static_cast<R>(dsum / rho);
+        mom[n] = static_cast<R>(drho);
+        mom[g.N + n] = static_cast<R>(j[0]);
+        mom[2 * g.N + n] = static_cast<R>(j[1]);
+        mom[3 * g.N + n] = static_cast<R>(j[2]);
+    }
+    const bool is_max[2] = {false, false};
+    double out[2];
+    block_reduce<2>(v, is_max, threadIdx.x, blockDim.x, out);
+    if (threadIdx.x == 0) {
+        const long long bid =
+            blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        acc_sink[bid] += out[0];
+        acc_sites[bid] += static_cast<long long>(out[1]);
+    }
+}
+
+// Pass 1 from records for D3Q19 without solid nodes, FP32 records: a block takes a 64 x 4
+// tile of nodes through kZmZ consecutive planes.  The records of three planes (the tile
+// and one node around it) sit in an LDS ring; the next plane is loaded into registers while
+// the current one is computed, then stored over the plane that is no longer needed.  Each
+// record value then passes through L1 about (kZmZ + 2) / kZmZ x 66 x 6 / (64 x 4) times
+// instead of once per pulling neighbour.  The arithmetic is k_pull_record's.
+constexpr int kZmX = 64, kZmY = 4, kZmZ = 32;
+constexpr int kZmW = kZmX + 2, kZmH = kZmY + 2;
+constexpr int kZmP = kRec * kZmH * kZmW;  // staged values per plane
+constexpr int kZmT = kZmX * kZmY;
+constexpr int kZmSeg = kRec * kZmH;     // 64-node row segments of a staged plane
+constexpr int kZmSegW = kZmSeg / 4;      // segments per wave
+constexpr int kZmPer = kZmSegW + 1;      // staged values per thread and plane (+ halo)
+static_assert(kZmSeg % 4 == 0 && 2 * kZmSeg <= kZmT, "staging layout");
+
+template <typename S, typename M>
+__global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pull_record_zm(const float* __restrict__ rec,
+                                                         const void* __restrict__ carry,
+                                                         const void* __restrict__ phi_field,
+                                                         float* __restrict__ rhoN,
+                                                         float* __restrict__ mom,
+                                                         double* __restrict__ acc_sink,
+                                                         long long* __restrict__ acc_sites,
+                                                         Geo g, Phys<M> P) {
+    constexpr int Q = 19;
+    using L = RecLayout<float>;
+    __shared__ float ring[3 * kZmP];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kZmX * ty;
+    const int x0 = blockIdx.x * kZmX, y0 = blockIdx.y * kZmY;
+    const int z0 = blockIdx.z * kZmZ, z1 = min(z0 + kZmZ, g.nz);
+    const long long rlen = L::row_len(g.nx);
+    const long long plane = (long long)g.ny * rlen;
+    // Staging of one plane: the tile's rows (value sl, row ry) are kZmSeg segments of 64
+    // nodes; wave w loads segments w, w + 4, ... with one lane per node (the segment base is
+    // uniform), and threads tid < 2 kZmSeg load the two halo columns x0 - 1 and x0 + 64.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const uint32_t xin = L::in_row(wrapm(x0 + lane, g.nx)) * (uint32_t)sizeof(float);
+    const int hseg = tid >> 1, hside = tid & 1;
+    const bool halo = tid < 2 * kZmSeg;
+    const uint32_t hoff =
+        halo ? (uint32_t)(((long long)wrapm(y0 - 1 + hseg % kZmH, g.ny) * rlen +
+                           L::in_row(wrapm(hside ? x0 + kZmX : x0 - 1, g.nx)) +
+                           (hseg / kZmH) * L::W) * (long long)sizeof(float))
+             : 0u;
+    const int hlds = hseg * kZmW + (hside ? kZmW - 1 : 0);
+    // plane-relative byte offsets of the segments (below 2^31: checked at launch), read back
+    // as LDS broadcasts
+    __shared__ int segoff[kZmSeg];
+    if (tid < kZmSeg)
+        segoff[tid] = (int)(((long long)wrapm(y0 - 1 + tid % kZmH, g.ny) * rlen +
+                             (tid / kZmH) * L::W) * (long long)sizeof(float));
+    __syncthreads();
+    auto load_plane = [&](int zp, float (&buf)[kZmPer]) {
+        const float* base = rec + (long long)wrapc(zp, g.nz) * plane;
+#pragma unroll
+        for (int m = 0; m < kZmSegW; ++m) buf[m] = ld_at(base, (uint32_t)segoff[wave + 4 * m] + xin);
+        if (halo) buf[kZmSegW] = ld_at(base, hoff);
+    };
+    auto store_plane = [&](int slot, const float (&buf)[kZmPer]) {
+        float* r = ring + slot * kZmP;
+#pragma unroll
+        for (int m = 0; m < kZmSegW; ++m) r[(wave + 4 * m) * kZmW + 1 + lane] = buf[m];
+        if (halo) r[hlds] = buf[kZmSegW];
+    };
+    float buf[kZmPer];
+    load_plane(z0 - 1, buf);
+    store_plane(0, buf);
+    load_plane(z0, buf);
+    store_plane(1, buf);
+    load_plane(z0 + 1, buf);
+    store_plane(2, buf);
+    __syncthreads();
+    const int x = x0 + tx, y = y0 + ty;
+    const bool valid = x < g.nx && y < g.ny;
+    double v[2] = {0.0, 0.0};
+    int sm = 0, sc = 1, sp = 2;  // ring slots of planes z - 1, z, z + 1
+    for (int z = z0; z < z1; ++z) {
+        const bool next = z + 1 < z1;
+        if (next) load_plane(z + 2, buf);
+        if (valid) {
+            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+            M j[3] = {M(0), M(0), M(0)}, drho = M(0), dsum = M(0), rn[3] = {M(0), M(0), M(0)};
+            const int slot[3] = {sp, sc, sm};  // plane of x - c_i by c_z = -1, 0, +1
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
+                const float* src =
+                    ring + slot[1 + cz] * kZmP + (ty + 1 - cy) * kZmW + (tx + 1 - cx);
+                float ar, dr, rr;
+                record_dir<Q, float>(i, 1.0f, [&](int sl) { return src[sl * kZmH * kZmW]; }, ar,
+                                     dr, rr);
+                const M a = static_cast<M>(ar);
+                drho += a;
+                dsum += static_cast<M>(dr);
+                rn[norm2<Q>(i)] += static_cast<M>(rr);
+                if (cx) j[0] += cx * a;
+                if (cy) j[1] += cy * a;
+                if (cz) j[2] += cz * a;
+                // one direction at a time: keeps the LDS reads of later directions from being
+                // hoisted into registers (the block's LDS already limits it to 2 waves per SIMD)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            dsum += ref_part<Q, M>(P, rn);
+            const M rho = P.rho_ref + drho;
+            M wgt;
+            const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum, wgt);
+            dsum -= M(2) * s;
+            v[0] += static_cast<double>(s);
+            v[1] += is_site(wgt) ? 1.0 : 0.0;
+            rhoN[n] = static_cast<float>(dsum / rho);
+            mom[n] = static_cast<float>(drho);
+            mom[g.N + n] = static_cast<float>(j[0]);
+            mom[2 * g.N + n] = static_cast<float>(j[1]);
+            mom[3 * g.N + n] = static_cast<float>(j[2]);
+        }
+        __syncthreads();  // every read of plane z - 1 is done
+        if (next) store_plane(sm, buf);
+        __syncthreads();
+        const int t = sm;
+        sm = sc;
+        sc = sp;
+        sp = t;
+    }
+    const bool is_max[2] = {false, false};
+    double out[2];
+    block_reduce<2>(v, is_max, tid, kZmT, out);
+    if (tid == 0) {
+        const long long bid =
+            blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+        acc_sink[bid] += out[0];
+        acc_sites[bid] += static_cast<long long>(out[1]);
+    }
+}
+
+static dim3 zm_grid(const Geo& g) {
+    return dim3((g.nx + kZmX - 1) / kZmX, (g.ny + kZmY - 1) / kZmY, (g.nz + kZmZ - 1) / kZmZ);
+}
+
+// Pass 2 to records: gradient and moments as k_finish, then the node's record instead of its
+// populations, and the next site data.
+template <int Q, typename S, typename M, bool WALLS>
+__global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) void
+k_finish_record(MomT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
+                void* __restrict__ carry, const MomT<S>* __restrict__ rhoN,
+                const MomT<S>* __restrict__ mom, Geo g, Phys<M> P) {
+    using R = MomT<S>;
+    int x, y, z;
+    long long n;
+    const RowPos pos = xcd_row(g);
+    const bool valid = node_xyz_at(g, pos, x, y, z, n);
+    const RowOff r = row_offsets_at<R>(g, pos, x < g.nx ? x : 0);
+    if (!valid) return;
+    if (WALLS && flags[n]) return;
+    const M drho = static_cast<M>(mom[n]);
+    const M rho = P.rho_ref + drho;
+    const M inv_rho = M(1) / rho;
+    const M u[3] = {static_cast<M>(mom[g.N + n]) * inv_rho,
+                    static_cast<M>(mom[2 * g.N + n]) * inv_rho,
+                    static_cast<M>(mom[3 * g.N + n]) * inv_rho};
+    M F[3];
+    if constexpr (WALLS) {
+        const Nb b = wrap(g, x, y, z);
+        gradient<Q>(rhoN, g, b, x, y, z, F);
+    } else {  // F = 3 sum_i W_i rho^N(x + c_i) c_i, as k_finish
+        F[0] = F[1] = F[2] = M(0);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const long long rowz = r.yrow[1 + Lat<Q>::cy[i]] + r.zpl[1 + Lat<Q>::cz[i]];
+            const M v = M(weight<Q>(i)) * static_cast<M>(ld_at(rhoN + rowz, r.xo[1 + Lat<Q>::cx[i]]));
+            if (Lat<Q>::cx[i]) F[0] += Lat<Q>::cx[i] * v;
+            if (Lat<Q>::cy[i]) F[1] += Lat<Q>::cy[i] * v;
+            if (Lat<Q>::cz[i]) F[2] += Lat<Q>::cz[i] * v;
+        }
+        F[0] *= M(3);
+        F[1] *= M(3);
+        F[2] *= M(3);
+    }
+    M rv[kRec];
+    const M Fn = record_values<Q, M>(drho, rho, static_cast<M>(rhoN[n]), u, F, P, rv);
+    using L = RecLayout<R>;
+    R* at = rec + ((long long)y + (long long)g.ny * z) * L::row_len(g.nx) + L::in_row(x);
+#pragma unroll
+    for (int sl = 0; sl < kRec; ++sl) {
+        if (Q == 9 && (sl == kUz || sl == kFz)) continue;  // no z component in 2D
+        __builtin_nontemporal_store(static_cast<R>(rv[sl]), at + sl * L::W);
+    }
+    carry_store(P, carry, n, Fn);
+}
+
 bool split_supported(const cge_ctx* c) { return c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0; }
 
 size_t split_scratch_bytes(const cge_params* p) {
@@ -242,6 +563,86 @@ static cge_status split_impl(cge_ctx* c, long long nsteps) {
 }
 
 cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_impl, c, nsteps); }
+
+// The z-marching pass 1 serves D3Q19 without solid nodes with FP32 records (checked where
+// it is launched) when its blocks fit the per-block sink accumulators and a plane of
+// records is addressable with 32-bit offsets.
+static bool zm_ok(const cge_ctx* c) {
+    const dim3 gz = zm_grid(c->g);
+    const long long blocks = (long long)gz.x * gz.y * gz.z;
+    const long long plane = (long long)c->g.ny * RecLayout<float>::row_len(c->g.nx) * 4;
+    return blocks <= c->acc_len && plane < (1ll << 31);
+}
+
+// One step of the record form: pass 1 from populations (first step of a call) or records,
+// pass 2 to populations (last step) or records.
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status record_one(cge_ctx* c, bool first, bool last) {
+    if (first && last) return split_one<Q, S, M, WALLS>(c, c->carry, c->carry, c->rhoN, c->mom);
+    const Phys<M> P = phys<M>(c);
+    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
+    MomT<S>* rhoN = static_cast<MomT<S>*>(c->rhoN);
+    MomT<S>* mom = static_cast<MomT<S>*>(c->mom);
+    MomT<S>* rec = static_cast<MomT<S>*>(c->rec);
+    const S* src = static_cast<const S*>(c->pop[c->cur]);
+    S* dst = static_cast<S*>(c->pop[1 - c->cur]);
+    const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
+    timing_begin(c);
+    if (first)
+        hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
+                           c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
+    else {
+        bool marched = false;
+        if constexpr (Q == 19 && !WALLS && std::is_same<MomT<S>, float>::value) {
+            if (zm_ok(c)) {
+                hipLaunchKernelGGL((k_pull_record_zm<S, M>), zm_grid(c->g), dim3(kZmX, kZmY, 1),
+                                   0, c->stream, rec, c->carry, c->phi_field, rhoN, mom,
+                                   c->acc_sink, c->acc_sites, c->g, P);
+                marched = true;
+            }
+        }
+        if (!marched)
+            hipLaunchKernelGGL((k_pull_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec,
+                               c->flags, c->carry, c->phi_field, rhoN, mom, c->acc_sink,
+                               c->acc_sites, c->g, P);
+    }
+    if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+    if (!last) {
+        hipLaunchKernelGGL((k_finish_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec, c->flags,
+                           c->carry, rhoN, mom, c->g, P);
+    } else if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
+        const dim3 tb(kTileX, kTileY, 1);
+        const dim3 tg((c->g.nx + kTileX - 1) / kTileX, (c->g.ny + kTileY - 1) / kTileY, c->g.nz);
+        hipLaunchKernelGGL((k_finish_tile<S, M>), tg, tb, 0, c->stream, dst, c->carry, rhoN, mom,
+                           c->g, P, salt);
+    } else {
+        hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
+                           c->carry, rhoN, mom, c->g, P, salt);
+    }
+    timing_end(c);
+    if (cge_status s = check(c, hipGetLastError(), "record step launch")) return s;
+    c->cur = 1 - c->cur;  // the populations of the last step land where the split step's would
+    c->step += 1;
+    return CGE_OK;
+}
+
+template <int Q, typename S, typename M, bool WALLS>
+static cge_status record_impl(cge_ctx* c, long long nsteps) {
+    if (!split_supported(c)) return fail(c, CGE_EUNSUPPORTED, "record step needs tau = 1");
+    if (!c->mom || !c->rec) return fail(c, CGE_ESTATE, "record scratch missing");
+    for (long long t = 0; t < nsteps; ++t)
+        if (cge_status s = record_one<Q, S, M, WALLS>(c, t == 0, t == nsteps - 1)) return s;
+    return CGE_OK;
+}
+
+cge_status record_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, record_impl, c, nsteps); }
+
+size_t record_bytes(const cge_params* p) {
+    const size_t rows = (size_t)p->ny * p->nz;
+    return p->precision == CGE_FP64 ? rows * RecLayout<double>::row_len(p->nx) * sizeof(double)
+                                    : rows * RecLayout<float>::row_len(p->nx) * sizeof(float);
+}
+
 
 cge_status split_step_into(cge_ctx* c, const void* carry_in, void* carry_out, void* rhoN,
                            void* mom) {

@@ -245,3 +245,42 @@ def test_full_size_adjoint_central_differences():
     assert abs(fdg - r["grad_gamma"]) <= 1e-3 * abs(r["grad_gamma"])
     sim.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name,precision,tol", [("sphere3d", "fp32s", 1e-6),
+                                                ("sphere3d", "fp64", 1e-13),
+                                                ("cap3d", "fp32s", 1e-6)])
+def test_record_calls_equal_split_steps_at_full_size(name, precision, tol):
+    """The benchmark runs the record form (the automatic choice at unit relaxation times) in
+    calls of many steps, whose intermediate states never leave the library.  At the full
+    size, a call of 6 steps equals 6 split steps (which the sampled test above pins to the
+    oracle) within the rounding of the record, with identical site data in FP64."""
+    import torch
+    from tests.helpers import e_pop
+    w = case(name, None)
+    p = w["params"]
+    _flush(f"[full size record vs split] {name} shape={p['shape']} {precision}")
+    a = gpu_for(w, precision)
+    assert a.kernel_name() == "k_pull_record"
+    a.step(6)
+    fa = a.populations().cpu().numpy()
+    ca = a.carry.cpu().numpy()
+    oa = a.observables()
+    a.close()
+    del a
+    torch.cuda.empty_cache()
+    b = gpu_for(w, precision, kernel="split")
+    b.step(6)
+    fb = b.populations().cpu().numpy()
+    cb = b.carry.cpu().numpy()
+    ob = b.observables()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    e = e_pop(fa, fb, int(p["Q"]), p["rho_in"], w["solid"])
+    _flush(f"  e_pop(record, split) = {e:.3e}")
+    assert e < tol, e
+    if precision == "fp64":
+        assert np.array_equal(ca, cb)
+        assert oa["site_steps"] == ob["site_steps"]
+    assert abs(oa["sink_total"] - ob["sink_total"]) <= 1e-9 * abs(ob["sink_total"])

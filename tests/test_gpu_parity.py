@@ -268,7 +268,10 @@ def test_determinism_and_resume_bitwise():
     assert bool(torch.equal(got[0], ref[0]))
     for k in ("mass_r", "mass_b", "n_sites", "site_steps", "step"):
         assert got[1][k] == ref[1][k], k
-    assert abs(got[1]["sink_total"] - ref[1]["sink_total"]) <= 1e-15 * ref[1]["sink_total"]
+    # the FP64 sink total sums per-block partials whose grouping depends on how the steps
+    # fall into calls (the record form's first step of a call runs on the node grid, the
+    # others on the z-marching blocks): equal up to the rounding of that order
+    assert abs(got[1]["sink_total"] - ref[1]["sink_total"]) <= 1e-14 * ref[1]["sink_total"]
     sim2.close()
 
 

@@ -1,0 +1,132 @@
+"""The record form of the unit-relaxation step (kernel "record", CGE_KERNEL_RECORD).
+
+Between the steps of one call each node keeps a 14-value post-collision record instead of
+its 2Q populations; the first step of a call pulls populations and the last writes them.
+A call of n steps therefore computes the same arithmetic as n steps of the split form, up to
+the rounding of the record and of the rebuilt populations:
+  * FP64: against the FP64 oracle within 1e-12 (the parity bar), calls of several steps;
+    against the split form within 1e-13 with identical site masks and counters;
+  * FP32 storage: against the split form within 1e-6 of the population scale (the record's
+    FP32 values and the FP32 rebuild of each pulled population, against the split form's
+    FP32-stored populations), the same sites and sink total to 1e-9 (1e-7 with the soft
+    site rule, whose logistic weights amplify rounding differences of ||F|| by 1 / kappa).
+Shapes cover the z-marching pull of D3Q19 without solid nodes (64 x 4 tiles, 32-plane
+chunks) with ragged tiles and chunks, one and two planes, and the general pull: D2Q9, solid
+nodes, the |rho^N| < Gamma and soft site rules."""
+import numpy as np
+import pytest
+
+from tests.helpers import case, e_pop, gpu_for, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+ORACLE_CASES = {
+    # name: (workload, shape (z, y, x), overrides)
+    "d3q19_sphere": ("sphere3d", (20, 12, 40), dict(radius=4.5, phi=1e-3)),
+    "d2q9_phase": ("drop2d", (1, 40, 52), dict(radius=11.0, phi=1e-3)),
+    # a ring of solid nodes on the bottom wall (the pinned-cap cavity)
+    "d3q19_walls": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
+    "d2q9_walls_field": ("flat2d", (1, 40, 70), dict(phi=1e-3)),
+    "d2q9_soft": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3, site_rule="soft",
+                                                 gamma=0.1, kappa=0.01)),
+}
+
+
+@pytest.mark.parametrize("name", list(ORACLE_CASES))
+def test_record_calls_match_the_oracle_fp64(name):
+    wl, shape, over = ORACLE_CASES[name]
+    w = case(wl, shape, **over)
+    Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
+    _flush(f"[record fp64 vs oracle] {name} shape={shape}")
+    ora = oracle_for(w)
+    sim = gpu_for(w, "fp64", kernel="record")
+    assert sim.kernel_name() == "k_pull_record"
+    for calls in range(3):
+        sim.step(4)
+        ora.step(4)
+        e = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in, w["solid"])
+        assert e < 1e-12, (calls, e)
+        if w["params"]["site_rule"] == "grad":
+            mask = (ora.fmag() > w["params"]["gamma"]).astype(np.uint8)
+            assert np.array_equal(sim.carry.cpu().numpy(), mask), calls
+    og, oo = sim.observables(), ora.observables()
+    for k in ("n_sites", "site_steps", "step"):
+        assert og[k] == oo[k], k
+    for k in ("mass_r", "mass_b", "sink_total"):
+        assert abs(og[k] - oo[k]) <= 1e-12 * max(1.0, abs(oo[k])), (k, og[k], oo[k])
+    assert og["site_steps"] > 0
+    sim.close()
+
+
+SPLIT_CASES = {
+    # z-marching pull: ragged x, y and z tiles; chunks 32 + 32 + 6; one and two planes
+    "zm_ragged": ("sphere3d", (70, 10, 70), dict(radius=4.0, phi=1e-3)),
+    "zm_aligned": ("sphere3d", (33, 8, 64), dict(radius=3.5, phi=1e-3)),
+    "zm_one_plane": ("sphere3d", (1, 24, 64), dict(radius=6.0, phi=1e-3)),
+    "zm_two_planes": ("sphere3d", (2, 20, 66), dict(radius=6.0, phi=1e-3)),
+    # general pull
+    "d2q9": ("drop2d", (1, 40, 52), dict(radius=11.0, phi=1e-3)),
+    "walls": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
+    "soft": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3, site_rule="soft",
+                                            gamma=0.1, kappa=0.01)),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+@pytest.mark.parametrize("name", list(SPLIT_CASES))
+def test_record_call_equals_split_steps(name, precision):
+    wl, shape, over = SPLIT_CASES[name]
+    w = case(wl, shape, **over)
+    Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
+    _flush(f"[record vs split] {name} {precision} shape={shape}")
+    a = gpu_for(w, precision, kernel="record")
+    b = gpu_for(w, precision, kernel="split")
+    for n in (7, 1, 5):  # calls of several steps, and one (the split step itself)
+        a.step(n)
+        b.step(n)
+        e = e_pop(a.populations().cpu().numpy(), b.populations().cpu().numpy(), Q, rho_in,
+                  w["solid"])
+        tol = 1e-13 if precision == "fp64" else 1e-6
+        assert e < tol, (n, e)
+    oa, ob = a.observables(), b.observables()
+    assert oa["step"] == ob["step"] == 13
+    soft = w["params"]["site_rule"] == "soft"
+    if precision == "fp64":
+        if soft:  # the carried ||F||, rounded in a different order
+            assert float((a.carry - b.carry).abs().max()) < 1e-12
+        else:
+            assert bool((a.carry == b.carry).all())
+        for k in ("n_sites", "site_steps"):
+            assert oa[k] == ob[k], k
+        assert abs(oa["sink_total"] - ob["sink_total"]) <= 1e-13 * abs(ob["sink_total"])
+    else:
+        assert oa["site_steps"] == ob["site_steps"]
+        # soft weights pass rounding differences of ||F|| on amplified by 1 / kappa = 100
+        rel = 1e-7 if soft else 1e-9
+        assert abs(oa["sink_total"] - ob["sink_total"]) <= rel * abs(ob["sink_total"])
+    a.close()
+    b.close()
+
+
+def test_automatic_choice_of_the_step_form():
+    from paper_2412_14859_amd import cgevap
+    w = case("sphere3d", (8, 8, 64), radius=3.0, phi=1e-3)
+    for precision, want in (("fp64", "k_pull_record"), ("fp32s", "k_pull_record"),
+                            ("fp16s", "k_finish")):
+        s = gpu_for(w, precision)
+        assert s.kernel_name() == want, precision
+        s.close()
+    s = gpu_for(w, "fp16s", kernel="record")
+    assert s.kernel_name() == "k_pull_record"
+    s.close()
+    w2 = case("sphere3d", (8, 8, 64), radius=3.0, phi=1e-3, tau=(1.0, 0.8))
+    s = gpu_for(w2, "fp32s")
+    assert s.kernel_name() != "k_pull_record"
+    s.close()
+    with pytest.raises(cgevap.CgeError):
+        gpu_for(w2, "fp32s", kernel="record")
