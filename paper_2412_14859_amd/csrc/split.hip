@@ -89,7 +89,11 @@ __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) v
                                                   Phys<M> P, uint64_t salt) {
     int x, y, z;
     long long n;
-    const RowPos pos = xcd_row(g);  // the rho^N rows around a block stay in one L2
+    // banded block order: the rho^N rows around a block stay in one L2 (FP32 storage 14 %
+    // faster); at FP16 storage the pass is bound by the stochastic rounding and the plain
+    // order measured faster
+    constexpr bool banded = !std::is_same<S, _Float16>::value;
+    const RowPos pos = banded ? xcd_row(g) : RowPos{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
     const bool valid = node_xyz_at(g, pos, x, y, z, n);
     const RowOff r = row_offsets_at<MomT<S>>(g, pos, x < g.nx ? x : 0);  // offsets into rho^N
     if (!valid) return;
