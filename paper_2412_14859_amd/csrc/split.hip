@@ -355,8 +355,18 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     using L = RecLayout<float>;
     __shared__ float ring[3 * kZmP];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kZmX * ty;
-    const int x0 = blockIdx.x * kZmX, y0 = blockIdx.y * kZmY;
-    const int z0 = blockIdx.z * kZmZ, z1 = min(z0 + kZmZ, g.nz);
+    // tiles in XCD-contiguous order: XCD k (blocks are dealt round-robin by id) takes a run of
+    // consecutive tiles, x fastest, then y, then the z-chunk, so tiles that share halo rows and
+    // columns read them through the same L2 at about the same time
+    const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+    const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned xq = nb / kXcds, xrem = nb % kXcds, xk = bid % kXcds;
+    const unsigned tile = xk * xq + (xk < xrem ? xk : xrem) + bid / kXcds;
+    const int bx = __builtin_amdgcn_readfirstlane((int)(tile % gridDim.x));
+    const int by = __builtin_amdgcn_readfirstlane((int)((tile / gridDim.x) % gridDim.y));
+    const int bz = __builtin_amdgcn_readfirstlane((int)(tile / (gridDim.x * gridDim.y)));
+    const int x0 = bx * kZmX, y0 = by * kZmY;
+    const int z0 = bz * kZmZ, z1 = min(z0 + kZmZ, g.nz);
     const long long rlen = L::row_len(g.nx);
     const long long plane = (long long)g.ny * rlen;
     // Staging of one plane: the tile's rows (value sl, row ry) are kZmSeg segments of 64
@@ -454,8 +464,6 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     double out[2];
     block_reduce<2>(v, is_max, tid, kZmT, out);
     if (tid == 0) {
-        const long long bid =
-            blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
         acc_sink[bid] += out[0];
         acc_sites[bid] += static_cast<long long>(out[1]);
     }
