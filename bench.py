@@ -41,7 +41,8 @@ STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fu
                 "k_finish": ("k_moments+k_finish", "split"),
                 "k_pull_record": ("k_pull_record+k_finish_record", "record")}
 # source file of each step form (the record form's kernels live beside the split form's)
-FORM_FILE = {"twopass": "twopass", "fused": "fused", "split": "split", "record": "split"}
+FORM_FILE = {"twopass": "twopass", "fused": "fused", "split": "split", "record": "split",
+             "adjoint": "adjoint"}
 
 
 def kernel_sources(tag):
