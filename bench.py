@@ -640,7 +640,12 @@ def main():
                                "Gamma=0.305, Sbar=3",
                    "nodes": N, "storage": {"fp32s": "fp32 shifted", "fp64": "fp64",
                                            "fp16s": "fp16 shifted, stochastic rounding"}[args.precision],
-                   "kernel": main_leg["kernel"]},
+                   "kernel": main_leg["kernel"],
+                   "arithmetic": ("FP64 collision and moment sums; pulled populations rebuilt "
+                                  "from the FP32 post-collision record in FP32"
+                                  if main_leg["kernel"] == "k_pull_record" and args.precision != "fp64"
+                                  else {"fp32s": "FP64", "fp64": "FP64",
+                                        "fp16s": "FP32"}[args.precision])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
