@@ -342,6 +342,30 @@ constexpr int kZmSegW = kZmSeg / 4;      // segments per wave
 constexpr int kZmPer = kZmSegW + 1;      // staged values per thread and plane (+ halo)
 static_assert(kZmSeg % 4 == 0 && 2 * kZmSeg <= kZmT, "staging layout");
 
+// Site data of a node read ahead of its pull: the carried mask byte or ||F|| (as site_weight
+// reads it) and the node's flux (node_phi).  The z-marching pass issues these loads before
+// a plane's record loads, so their latency overlaps the pull instead of following it.
+template <typename S, typename M>
+__device__ __forceinline__ void site_ahead(const Phys<M>& P, const void* __restrict__ carry,
+                                           const void* __restrict__ phi_field, long long n,
+                                           double& c, M& phi) {
+    c = P.site_rule == 2 ? static_cast<const double*>(carry)[n]
+                         : (P.site_rule == 0 ? static_cast<double>(static_cast<const uint8_t*>(carry)[n])
+                                             : 0.0);
+    phi = node_phi<S, M>(P, phi_field, n);
+}
+
+// site_sink on the data site_ahead read: the same weight and sink arithmetic.
+template <typename M>
+__device__ __forceinline__ M site_sink_ahead(const Phys<M>& P, double c, M phi, M rho, M dsum,
+                                             M& w) {
+    if (P.site_rule == 2) w = M(1) / (M(1) + exp(-(static_cast<M>(c) - P.gamma) * P.inv_kappa));
+    else if (P.site_rule == 0) w = c != 0.0 ? M(1) : M(0);
+    else w = fabs(dsum / rho) < P.gamma ? M(1) : M(0);
+    if (w == M(0)) return M(0);
+    return w * (phi * P.inv_sbar);
+}
+
 template <typename S, typename M>
 __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pull_record_zm(const float* __restrict__ rec,
                                                          const void* __restrict__ carry,
@@ -415,9 +439,12 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     int sm = 0, sc = 1, sp = 2;  // ring slots of planes z - 1, z, z + 1
     for (int z = z0; z < z1; ++z) {
         const bool next = z + 1 < z1;
+        const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+        double cpre = 0.0;
+        M phin = M(0);
+        if (valid) site_ahead<S, M>(P, carry, phi_field, n, cpre, phin);
         if (next) load_plane(z + 2, buf);
         if (valid) {
-            const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
             M j[3] = {M(0), M(0), M(0)}, drho = M(0), dsum = M(0), rn[3] = {M(0), M(0), M(0)};
             const int slot[3] = {sp, sc, sm};  // plane of x - c_i by c_z = -1, 0, +1
 #pragma unroll
@@ -442,7 +469,7 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
             dsum += ref_part<Q, M>(P, rn);
             const M rho = P.rho_ref + drho;
             M wgt;
-            const M s = site_sink<S>(P, carry, phi_field, n, rho, dsum, wgt);
+            const M s = site_sink_ahead<M>(P, cpre, phin, rho, dsum, wgt);
             dsum -= M(2) * s;
             v[0] += static_cast<double>(s);
             v[1] += is_site(wgt) ? 1.0 : 0.0;
