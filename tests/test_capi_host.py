@@ -42,6 +42,7 @@ def _params(**over):
 @pytest.mark.parametrize("over", [dict(lattice=7), dict(nx=0), dict(nz=2), dict(tau=0.5),
                                   dict(rho_in=0.0), dict(beta=1.5), dict(sbar=0.5),
                                   dict(precision=3), dict(site_rule=3), dict(kernel=9),
+                                  dict(kernel=5), dict(kernel=-1),
                                   dict(site_rule=2, kappa=0.0), dict(site_rule=2, kappa=float("nan")),
                                   dict(sigma=-1.0), dict(phi=float("nan")),
                                   dict(gamma=float("inf"))])
@@ -52,6 +53,16 @@ def test_invalid_parameters_are_rejected_on_the_host(over):
     assert L.cge_create(C.byref(p), None, C.byref(ctx)) == cgevap.EINVAL
     assert ctx.value is None
     assert L.cge_population_bytes(C.byref(p)) == 0
+
+
+@pytest.mark.parametrize("kernel", ["auto", "twopass", "fused", "split", "record"])
+def test_every_step_form_passes_host_validation(kernel):
+    """The binding's kernel names map onto the header's enumeration: each passes the host
+    check (cge_population_bytes returns the population size without a device)."""
+    L = cgevap.lib()
+    p = _params(kernel=cgevap.KERNELS[kernel])
+    assert L.cge_population_bytes(C.byref(p)) == 2 * 9 * 8 * 8 * 8
+    assert cgevap.KERNELS["record"] == 4
 
 
 def test_null_arguments():
