@@ -210,7 +210,7 @@ k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const MomT<S>* __re
 // the record's precision (a few operations per direction, record_dir) and summed into the
 // moments in the arithmetic type.
 
-// Record layout: rows of nodes (y, z) one after the other; within a row, chunks of kRecW
+// Record layout: rows of nodes (y, z) one after the other; within a row, chunks of W
 // nodes (256 B of one value), and within a chunk the 14 values one after the other.  A
 // node's values are then at one offset plus the value index times 256 B, which the load
 // instruction takes as its immediate offset, and the rows around a node are 9 scalar bases.
@@ -327,12 +327,13 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
     }
 }
 
-// Pass 1 from records for D3Q19 without solid nodes, FP32 records: a block takes a 64 x 4
-// tile of nodes through kZmZ consecutive planes.  The records of three planes (the tile
-// and one node around it) sit in an LDS ring; the next plane is loaded into registers while
-// the current one is computed, then stored over the plane that is no longer needed.  Each
-// record value then passes through L1 about (kZmZ + 2) / kZmZ x 66 x 6 / (64 x 4) times
-// instead of once per pulling neighbour.  The arithmetic is k_pull_record's.
+// Pass 1 from records for D3Q19 with FP32 records: a block takes a 64 x 4 tile of nodes
+// through kZmZ consecutive planes.  The records of three planes (the tile and one node
+// around it) sit in an LDS ring, with their solid flags beside them when there are walls;
+// the next plane is loaded into registers while the current one is computed, then stored
+// over the plane that is no longer needed.  Each record value then passes through L1 about
+// (kZmZ + 2) / kZmZ x 66 x 6 / (64 x 4) times instead of once per pulling neighbour.  The
+// arithmetic is k_pull_record's, bounce-back included.
 constexpr int kZmX = 64, kZmY = 4, kZmZ = 32;
 constexpr int kZmW = kZmX + 2, kZmH = kZmY + 2;
 constexpr int kZmP = kRec * kZmH * kZmW;  // staged values per plane
@@ -340,7 +341,8 @@ constexpr int kZmT = kZmX * kZmY;
 constexpr int kZmSeg = kRec * kZmH;     // 64-node row segments of a staged plane
 constexpr int kZmSegW = kZmSeg / 4;      // segments per wave
 constexpr int kZmPer = kZmSegW + 1;      // staged values per thread and plane (+ halo)
-static_assert(kZmSeg % 4 == 0 && 2 * kZmSeg <= kZmT, "staging layout");
+constexpr int kZmF = kZmH * kZmW;        // staged flags per plane (two per thread at most)
+static_assert(kZmSeg % 4 == 0 && 2 * kZmSeg <= kZmT && kZmF <= 2 * kZmT, "staging layout");
 
 // Site data of a node read ahead of its pull: the carried mask byte or ||F|| (as site_weight
 // reads it) and the node's flux (node_phi).  The z-marching pass issues these loads before
@@ -366,8 +368,9 @@ __device__ __forceinline__ M site_sink_ahead(const Phys<M>& P, double c, M phi, 
     return w * (phi * P.inv_sbar);
 }
 
-template <typename S, typename M>
+template <typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pull_record_zm(const float* __restrict__ rec,
+                                                         const uint8_t* __restrict__ flags,
                                                          const void* __restrict__ carry,
                                                          const void* __restrict__ phi_field,
                                                          float* __restrict__ rhoN,
@@ -378,6 +381,7 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     constexpr int Q = 19;
     using L = RecLayout<float>;
     __shared__ float ring[3 * kZmP];
+    __shared__ uint8_t fring[WALLS ? 3 * kZmF : 1];  // solid flags of the ring's planes
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kZmX * ty;
     // tiles in XCD-contiguous order: XCD k (blocks are dealt round-robin by id) takes a run of
     // consecutive tiles, x fastest, then y, then the z-chunk, so tiles that share halo rows and
@@ -413,25 +417,47 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
         segoff[tid] = (int)(((long long)wrapm(y0 - 1 + tid % kZmH, g.ny) * rlen +
                              (tid / kZmH) * L::W) * (long long)sizeof(float));
     __syncthreads();
-    auto load_plane = [&](int zp, float (&buf)[kZmPer]) {
+    // flags: positions tid and tid + kZmT of the (kZmH x kZmW) plane window, in-plane index
+    long long fo[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int pos = tid + kZmT * h;
+        if (WALLS && pos < kZmF)
+            fo[h] = wrapm(x0 - 1 + pos % kZmW, g.nx) +
+                    (long long)g.nx * wrapm(y0 - 1 + pos / kZmW, g.ny);
+    }
+    const long long fplane = (long long)g.nx * g.ny;
+    auto load_plane = [&](int zp, float (&buf)[kZmPer], uint8_t (&fb)[2]) {
         const float* base = rec + (long long)wrapc(zp, g.nz) * plane;
 #pragma unroll
         for (int m = 0; m < kZmSegW; ++m) buf[m] = ld_at(base, (uint32_t)segoff[wave + 4 * m] + xin);
         if (halo) buf[kZmSegW] = ld_at(base, hoff);
+        if constexpr (WALLS) {
+            const uint8_t* fbase = flags + (long long)wrapc(zp, g.nz) * fplane;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (tid + kZmT * h < kZmF) fb[h] = fbase[fo[h]];
+        }
     };
-    auto store_plane = [&](int slot, const float (&buf)[kZmPer]) {
+    auto store_plane = [&](int slot, const float (&buf)[kZmPer], const uint8_t (&fb)[2]) {
         float* r = ring + slot * kZmP;
 #pragma unroll
         for (int m = 0; m < kZmSegW; ++m) r[(wave + 4 * m) * kZmW + 1 + lane] = buf[m];
         if (halo) r[hlds] = buf[kZmSegW];
+        if constexpr (WALLS) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (tid + kZmT * h < kZmF) fring[slot * kZmF + tid + kZmT * h] = fb[h];
+        }
     };
     float buf[kZmPer];
-    load_plane(z0 - 1, buf);
-    store_plane(0, buf);
-    load_plane(z0, buf);
-    store_plane(1, buf);
-    load_plane(z0 + 1, buf);
-    store_plane(2, buf);
+    uint8_t fbuf[2] = {0, 0};
+    load_plane(z0 - 1, buf, fbuf);
+    store_plane(0, buf, fbuf);
+    load_plane(z0, buf, fbuf);
+    store_plane(1, buf, fbuf);
+    load_plane(z0 + 1, buf, fbuf);
+    store_plane(2, buf, fbuf);
     __syncthreads();
     const int x = x0 + tx, y = y0 + ty;
     const bool valid = x < g.nx && y < g.ny;
@@ -440,20 +466,29 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     for (int z = z0; z < z1; ++z) {
         const bool next = z + 1 < z1;
         const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+        // solid nodes hold no state and are skipped, as in k_pull_record
+        const bool fluid =
+            valid && !(WALLS && fring[sc * kZmF + (ty + 1) * kZmW + (tx + 1)]);
         double cpre = 0.0;
         M phin = M(0);
-        if (valid) site_ahead<S, M>(P, carry, phi_field, n, cpre, phin);
-        if (next) load_plane(z + 2, buf);
-        if (valid) {
+        if (fluid) site_ahead<S, M>(P, carry, phi_field, n, cpre, phin);
+        if (next) load_plane(z + 2, buf, fbuf);
+        if (fluid) {
             M j[3] = {M(0), M(0), M(0)}, drho = M(0), dsum = M(0), rn[3] = {M(0), M(0), M(0)};
             const int slot[3] = {sp, sc, sm};  // plane of x - c_i by c_z = -1, 0, +1
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
-                const float* src =
-                    ring + slot[1 + cz] * kZmP + (ty + 1 - cy) * kZmW + (tx + 1 - cx);
+                const int at = (ty + 1 - cy) * kZmW + (tx + 1 - cx);
+                const float* src = ring + slot[1 + cz] * kZmP + at;
+                float sgn = 1.0f;
+                // halfway bounce-back: from a solid x - c_i the node's own f_opp(i)*
+                if (WALLS && i != 0 && fring[slot[1 + cz] * kZmF + at]) {
+                    src = ring + sc * kZmP + (ty + 1) * kZmW + (tx + 1);
+                    sgn = -1.0f;
+                }
                 float ar, dr, rr;
-                record_dir<Q, float>(i, 1.0f, [&](int sl) { return src[sl * kZmH * kZmW]; }, ar,
+                record_dir<Q, float>(i, sgn, [&](int sl) { return src[sl * kZmH * kZmW]; }, ar,
                                      dr, rr);
                 const M a = static_cast<M>(ar);
                 drho += a;
@@ -480,7 +515,7 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
             mom[3 * g.N + n] = static_cast<float>(j[2]);
         }
         __syncthreads();  // every read of plane z - 1 is done
-        if (next) store_plane(sm, buf);
+        if (next) store_plane(sm, buf, fbuf);
         __syncthreads();
         const int t = sm;
         sm = sc;
@@ -603,9 +638,9 @@ static cge_status split_impl(cge_ctx* c, long long nsteps) {
 
 cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_impl, c, nsteps); }
 
-// The z-marching pass 1 serves D3Q19 without solid nodes with FP32 records (checked where
-// it is launched) when its blocks fit the per-block sink accumulators and a plane of
-// records is addressable with 32-bit offsets.
+// The z-marching pass 1 serves D3Q19 with FP32 records (checked where it is launched) when
+// its blocks fit the per-block sink accumulators and a plane of records is addressable with
+// 32-bit offsets.
 static bool zm_ok(const cge_ctx* c) {
     const dim3 gz = zm_grid(c->g);
     const long long blocks = (long long)gz.x * gz.y * gz.z;
@@ -632,11 +667,11 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
                            c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
     else {
         bool marched = false;
-        if constexpr (Q == 19 && !WALLS && std::is_same<MomT<S>, float>::value) {
+        if constexpr (Q == 19 && std::is_same<MomT<S>, float>::value) {
             if (zm_ok(c)) {
-                hipLaunchKernelGGL((k_pull_record_zm<S, M>), zm_grid(c->g), dim3(kZmX, kZmY, 1),
-                                   0, c->stream, rec, c->carry, c->phi_field, rhoN, mom,
-                                   c->acc_sink, c->acc_sites, c->g, P);
+                hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS>), zm_grid(c->g),
+                                   dim3(kZmX, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
+                                   c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
                 marched = true;
             }
         }

@@ -10,9 +10,9 @@ the rounding of the record and of the rebuilt populations:
     FP32 values and the FP32 rebuild of each pulled population, against the split form's
     FP32-stored populations), the same sites and sink total to 1e-9 (1e-7 with the soft
     site rule, whose logistic weights amplify rounding differences of ||F|| by 1 / kappa).
-Shapes cover the z-marching pull of D3Q19 without solid nodes (64 x 4 tiles, 32-plane
-chunks) with ragged tiles and chunks, one and two planes, and the general pull: D2Q9, solid
-nodes, the |rho^N| < Gamma and soft site rules."""
+Shapes cover the z-marching pull of D3Q19 at FP32 storage (64 x 4 tiles, 32-plane chunks)
+with ragged tiles and chunks, one and two planes and solid nodes, and the general pull: D2Q9,
+FP64, the |rho^N| < Gamma and soft site rules."""
 import numpy as np
 import pytest
 
@@ -69,9 +69,12 @@ SPLIT_CASES = {
     "zm_aligned": ("sphere3d", (33, 8, 64), dict(radius=3.5, phi=1e-3)),
     "zm_one_plane": ("sphere3d", (1, 24, 64), dict(radius=6.0, phi=1e-3)),
     "zm_two_planes": ("sphere3d", (2, 20, 66), dict(radius=6.0, phi=1e-3)),
+    # with solid nodes (the z-marching pull at FP32 storage, the general one in FP64): the
+    # cavity ring, and a hemisphere on a wall with a flux field, ragged in x and z
+    "walls": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
+    "walls_hemisphere": ("hemisphere3d", (40, 20, 70), dict(radius=8.0, phi=1e-3)),
     # general pull
     "d2q9": ("drop2d", (1, 40, 52), dict(radius=11.0, phi=1e-3)),
-    "walls": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
     "soft": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3, site_rule="soft",
                                             gamma=0.1, kappa=0.01)),
 }
