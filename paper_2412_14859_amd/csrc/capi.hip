@@ -167,7 +167,9 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     c->g = Geo{params->nx, params->ny, params->nz,
                (long long)params->nx * params->ny * params->nz};
     c->stream = static_cast<hipStream_t>(hip_stream);
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess) {
         delete c;
         return CGE_EDEVICE;
     }

@@ -18,6 +18,7 @@ struct cge_ctx {
     cge::Geo g{};
     hipStream_t stream = nullptr;
     int device = 0;
+    int cus = 0;  // compute units of the device (launch shapes that fill the chip)
     int kernel = CGE_KERNEL_TWOPASS;  // resolved step implementation
     // caller-owned buffers
     void* pop[2] = {nullptr, nullptr};

@@ -328,13 +328,13 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
 }
 
 // Pass 1 from records for D3Q19 with FP32 records: a block takes a 64 x 4 tile of nodes
-// through kZmZ consecutive planes.  The records of three planes (the tile and one node
+// through zc consecutive planes (zm_chunk).  The records of three planes (the tile and one node
 // around it) sit in an LDS ring, with their solid flags beside them when there are walls;
 // the next plane is loaded into registers while the current one is computed, then stored
 // over the plane that is no longer needed.  Each record value then passes through L1 about
-// (kZmZ + 2) / kZmZ x 66 x 6 / (64 x 4) times instead of once per pulling neighbour.  The
+// (zc + 2) / zc x 66 x 6 / (64 x 4) times instead of once per pulling neighbour.  The
 // arithmetic is k_pull_record's, bounce-back included.
-constexpr int kZmX = 64, kZmY = 4, kZmZ = 32;
+constexpr int kZmX = 64, kZmY = 4;
 constexpr int kZmW = kZmX + 2, kZmH = kZmY + 2;
 constexpr int kZmP = kRec * kZmH * kZmW;  // staged values per plane
 constexpr int kZmT = kZmX * kZmY;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
                                                          float* __restrict__ mom,
                                                          double* __restrict__ acc_sink,
                                                          long long* __restrict__ acc_sites,
-                                                         Geo g, Phys<M> P) {
+                                                         Geo g, Phys<M> P, int zc) {
     constexpr int Q = 19;
     using L = RecLayout<float>;
     __shared__ float ring[3 * kZmP];
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     const int by = __builtin_amdgcn_readfirstlane((int)((tile / gridDim.x) % gridDim.y));
     const int bz = __builtin_amdgcn_readfirstlane((int)(tile / (gridDim.x * gridDim.y)));
     const int x0 = bx * kZmX, y0 = by * kZmY;
-    const int z0 = bz * kZmZ, z1 = min(z0 + kZmZ, g.nz);
+    const int z0 = bz * zc, z1 = min(z0 + zc, g.nz);
     const long long rlen = L::row_len(g.nx);
     const long long plane = (long long)g.ny * rlen;
     // Staging of one plane: the tile's rows (value sl, row ry) are kZmSeg segments of 64
@@ -531,8 +531,32 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     }
 }
 
-static dim3 zm_grid(const Geo& g) {
-    return dim3((g.nx + kZmX - 1) / kZmX, (g.ny + kZmY - 1) / kZmY, (g.nz + kZmZ - 1) / kZmZ);
+// Planes per z-chunk.  A chunk's first three planes are loaded before any is computed, and
+// blocks run in rounds of two per CU (two fit a CU's LDS), so the pass takes about
+// rounds x (planes per chunk + 3) plane-times; the chunk count that minimises this is taken.
+// At 256^3 that is 2 chunks of 128 planes (measured per step: 32 planes 0.72 ms, 64 0.70,
+// 128 0.69); at 192^3 7 chunks of 28 (32 planes: 0.47 ms, 48 planes, whose 576 blocks leave
+// a second round nearly empty: 0.58 ms).
+static int zm_chunk(const cge_ctx* c) {
+    const Geo& g = c->g;
+    const long long tiles = (long long)((g.nx + kZmX - 1) / kZmX) * ((g.ny + kZmY - 1) / kZmY);
+    const long long slots = 2ll * (c->cus > 0 ? c->cus : 1);
+    long long best = -1, best_zc = g.nz;
+    for (long long chunks = 1; chunks <= g.nz && chunks <= 4096; ++chunks) {
+        const long long zc = (g.nz + chunks - 1) / chunks;
+        const long long used = (g.nz + zc - 1) / zc;  // chunks of zc planes that cover nz
+        const long long rounds = (tiles * used + slots - 1) / slots;
+        const long long cost = rounds * (zc + 3);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_zc = zc;
+        }
+    }
+    return (int)best_zc;
+}
+
+static dim3 zm_grid(const Geo& g, int zc) {
+    return dim3((g.nx + kZmX - 1) / kZmX, (g.ny + kZmY - 1) / kZmY, (g.nz + zc - 1) / zc);
 }
 
 // Pass 2 to records: gradient and moments as k_finish, then the node's record instead of its
@@ -642,7 +666,7 @@ cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_imp
 // its blocks fit the per-block sink accumulators and a plane of records is addressable with
 // 32-bit offsets.
 static bool zm_ok(const cge_ctx* c) {
-    const dim3 gz = zm_grid(c->g);
+    const dim3 gz = zm_grid(c->g, zm_chunk(c));
     const long long blocks = (long long)gz.x * gz.y * gz.z;
     const long long plane = (long long)c->g.ny * RecLayout<float>::row_len(c->g.nx) * 4;
     return blocks <= c->acc_len && plane < (1ll << 31);
@@ -669,9 +693,11 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
         bool marched = false;
         if constexpr (Q == 19 && std::is_same<MomT<S>, float>::value) {
             if (zm_ok(c)) {
-                hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS>), zm_grid(c->g),
+                const int zc = zm_chunk(c);
+                hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS>), zm_grid(c->g, zc),
                                    dim3(kZmX, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
-                                   c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
+                                   c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P,
+                                   zc);
                 marched = true;
             }
         }
