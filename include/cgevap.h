@@ -75,9 +75,11 @@ typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } 
  *            is populations as for every other form; a call of one step is SPLIT's step.
  *            Same support as SPLIT; needs 14 N values of library scratch (FP64 at FP64
  *            storage, FP32 otherwise; rows padded to 256 B), allocated at cge_create for
- *            RECORD, and for AUTO at FP64 and FP32 storage.
- *   AUTO:    at unit relaxation times RECORD (SPLIT at FP16 storage, whose state between
- *            steps then stays in half precision), else FUSED where supported, else TWOPASS.
+ *            RECORD, and for AUTO where AUTO selects it.
+ *   AUTO:    at unit relaxation times RECORD for D3Q19 at FP64 and FP32 storage, SPLIT for
+ *            D2Q9 (where the record pull has no LDS-staged form and is no faster) and at FP16
+ *            storage (whose state between steps then stays in half precision); otherwise
+ *            FUSED where supported, else TWOPASS.
  * All give the same results up to rounding. */
 typedef enum {
     CGE_KERNEL_AUTO = 0,

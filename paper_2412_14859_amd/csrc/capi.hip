@@ -185,10 +185,12 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     c->kernel = CGE_KERNEL_TWOPASS;  // resolved at cge_bind
     // the moment record also serves the checkpointed forward run of the adjoint at unit tau
     const bool need_mom = unit;
-    // records for the record form, which auto selects at unit tau with FP64 or FP32 storage
+    // records for the record form, which auto selects at unit tau for D3Q19 with FP64 or
+    // FP32 storage
     const bool need_rec =
         unit && (params->kernel == CGE_KERNEL_RECORD ||
-                 (params->kernel == CGE_KERNEL_AUTO && params->precision != CGE_FP16S));
+                 (params->kernel == CGE_KERNEL_AUTO && params->precision != CGE_FP16S &&
+                  c->Q == 19));
     const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type (the
                                                                    // widest use of rhoN)
     c->acc_len = twopass_blocks(c);

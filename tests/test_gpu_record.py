@@ -127,6 +127,11 @@ def test_automatic_choice_of_the_step_form():
     s = gpu_for(w, "fp16s", kernel="record")
     assert s.kernel_name() == "k_pull_record"
     s.close()
+    w9 = case("drop2d", (1, 40, 52), radius=11.0, phi=1e-3)
+    for precision in ("fp64", "fp32s"):  # D2Q9: the split step
+        s = gpu_for(w9, precision)
+        assert s.kernel_name() == "k_finish", precision
+        s.close()
     w2 = case("sphere3d", (8, 8, 64), radius=3.0, phi=1e-3, tau=(1.0, 0.8))
     s = gpu_for(w2, "fp32s")
     assert s.kernel_name() != "k_pull_record"
