@@ -138,3 +138,28 @@ def test_automatic_choice_of_the_step_form():
     s.close()
     with pytest.raises(cgevap.CgeError):
         gpu_for(w2, "fp32s", kernel="record")
+
+
+@pytest.mark.parametrize("name", ["zm_ragged", "walls_hemisphere", "d2q9"])
+def test_record_form_at_fp16_storage(name):
+    """Selected explicitly at FP16 storage, the record form keeps FP32 records between the
+    steps of a call, so it differs from the split step by the split step's FP16 rounding of
+    every stored population: within 2e-2 of the population scale as between the other step
+    forms at FP16 storage, with the same site count and the sink total within 1e-3."""
+    wl, shape, over = SPLIT_CASES[name]
+    w = case(wl, shape, **over)
+    Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
+    _flush(f"[record vs split] {name} fp16s shape={shape}")
+    a = gpu_for(w, "fp16s", kernel="record")
+    b = gpu_for(w, "fp16s", kernel="split")
+    a.step(9)
+    b.step(9)
+    e = e_pop(a.populations().cpu().numpy(), b.populations().cpu().numpy(), Q, rho_in,
+              w["solid"])
+    _flush(f"  e_pop(record, split) = {e:.3e}")
+    assert e < 2e-2, e
+    oa, ob = a.observables(), b.observables()
+    assert oa["site_steps"] == ob["site_steps"]
+    assert abs(oa["sink_total"] - ob["sink_total"]) <= 1e-3 * abs(ob["sink_total"])
+    a.close()
+    b.close()
