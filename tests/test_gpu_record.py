@@ -163,3 +163,26 @@ def test_record_form_at_fp16_storage(name):
     assert abs(oa["sink_total"] - ob["sink_total"]) <= 1e-3 * abs(ob["sink_total"])
     a.close()
     b.close()
+
+
+def test_z_marching_pull_against_the_oracle_fp32():
+    """The benchmark's kernel pair (the z-marching pull, FP32 records) against the FP64
+    oracle directly, in calls of several steps: with soft sites no site decision can flip
+    between precisions, so FP32 storage stays within the 1e-5 bar without imposing the
+    oracle's masks.  The shape spans ragged tiles in x and y and several planes."""
+    w = case("sphere3d", (14, 16, 70), radius=5.0, phi=1e-3, site_rule="soft", kappa=0.02)
+    Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
+    _flush("[record fp32s vs oracle] d3q19 soft 14x16x70")
+    ora = oracle_for(w)
+    sim = gpu_for(w, "fp32s", kernel="record")
+    worst = 0.0
+    for _ in range(3):
+        sim.step(5)
+        ora.step(5)
+        e = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in)
+        worst = max(worst, e)
+        assert e < 1e-5, e
+    _flush(f"  worst e_pop {worst:.3e}")
+    og, oo = sim.observables(), ora.observables()
+    assert abs(og["sink_total"] - oo["sink_total"]) <= 1e-5 * abs(oo["sink_total"])
+    sim.close()
