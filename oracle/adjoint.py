@@ -15,7 +15,10 @@ optionally with solid nodes):
   perturbation (Eq. perturb), recolouring (Eq. recolor)
   streaming (Eq. Stream)
 with the readings used throughout: t_i(a) = A_i + B_i a, C_0 = c_s^2 - (1 - W_0), C_i = W_i;
-cos(theta_i) faded out between |F| = 2e-5 and 1e-5; cos(theta_0) = 0.  Solid nodes (Sec. III,
+cos(theta_i) = F.c_i / (|F| |c_i|) and the perturbation taken as 0 where F.F <= 1e-24 (their
+limit at F = 0); cos(theta_0) = 0; the optional regularisation params['recolor_fade'] = w > 0
+(off by default, not the paper's model) multiplies cos(theta_i) by clamp(|F|/w - 1, 0, 1),
+as the C oracle does.  Solid nodes (Sec. III,
 walls) carry no populations: streaming bounces back halfway from them, and in the gradient
 stencil a solid node takes the W-weighted mean of rho^N over its fluid neighbours (neutral
 wetting); the sink acts at fluid nodes only.
@@ -135,11 +138,16 @@ def step(L, p, f, fprev, phi, weight, stored=None, solid=None):
     uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
     F = phase_gradient(L, wetted(L, rhoN, solid))
     F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2]
-    pos = F2 > 0
-    Fn = torch.where(pos, torch.sqrt(torch.where(pos, F2, torch.ones_like(F2))),
+    # ||F|| itself (carried to the next step's site weight) is exact; the perturbation and
+    # cos(theta) are 0/0 forms at F = 0 and are cut where F.F <= 1e-24
+    nz = F2 > 0
+    Fn = torch.where(nz, torch.sqrt(torch.where(nz, F2, torch.ones_like(F2))),
                      torch.zeros_like(F2))
+    pos = F2 > 1e-24
+    Fp = torch.where(pos, Fn, torch.zeros_like(Fn))
     invFn = torch.where(pos, 1.0 / torch.where(pos, Fn, torch.ones_like(Fn)), torch.zeros_like(Fn))
-    fade = torch.clamp(Fn / 1e-5 - 1.0, 0.0, 1.0)
+    w = p.get("recolor_fade", 0.0)
+    fade = torch.clamp(Fn / w - 1.0, 0.0, 1.0) if w > 0 else torch.ones_like(Fn)
     a_r, a_b = alphas(float(L["W"][0]), p["rho_in"])
     inv_tau = (rr / rho) / p["tau"][0] + (rb / rho) / p["tau"][1]
     abar = (rr / rho) * a_r + (rb / rho) * a_b
@@ -151,7 +159,7 @@ def step(L, p, f, fprev, phi, weight, stored=None, solid=None):
         feq = rho * (t_i + L["W"][i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu))
         f1 = fcb[i] - inv_tau * (fcb[i] - feq)
         Fc = ci[0] * F[0] + ci[1] * F[1] + ci[2] * F[2]
-        f1 = f1 + 2.25 * p["sigma"] * inv_tau * (L["W"][i] * Fc * Fc * invFn - L["C"][i] * Fn)
+        f1 = f1 + 2.25 * p["sigma"] * inv_tau * (L["W"][i] * Fc * Fc * invFn - L["C"][i] * Fp)
         cos = Fc * invFn * fade / L["clen"][i] if i != 0 else torch.zeros_like(Fc)
         sep = p["beta"] * rr * rb / (rho * rho) * cos * rho * t_i
         out_r.append(rr / rho * f1 + sep)

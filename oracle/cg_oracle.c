@@ -29,12 +29,15 @@
  *     C_i = W_i (i >= 1), C_0 = c_s^2 - (1 - W_0): sum C_i = c_s^2 and
  *     sum C_i c_ia c_ib = c_s^2 delta_ab, which fixes the interfacial stress to sigma.
  *   - D2Q9 is built with the same constructions (the paper uses D3Q19 only).
- *   - The angle theta_i between F and c_i is undefined at F = 0, and where F vanishes by
- *     symmetry inside a mixture its direction is rounding noise.  cos(theta_i) is multiplied
- *     by a fade g(||F||) = 0 for ||F|| <= 1e-5, ||F||/1e-5 - 1 up to 2e-5, and 1 above
- *     (continuous, so rounding near the cut moves the result only a little; real interfaces
- *     have ||F|| ~ 0.1).  cos(theta_0) = 0 for the rest direction.  The perturbation is
- *     continuous at F = 0 (it vanishes with ||F||) and is applied for F != 0.
+ *   - The angle theta_i between F and c_i is undefined at F = 0: cos(theta_i) =
+ *     F.c_i / (||F|| ||c_i||) (Eq. recolor) where F.F > 1e-24, and 0 otherwise; the
+ *     perturbation (Eq. perturb), which vanishes continuously with ||F||, is cut at the same
+ *     place.  cos(theta_0) = 0 for the rest direction.  An optional regularisation, off by
+ *     default (recolor_fade = 0) and not part of the paper's model, multiplies cos(theta_i)
+ *     by g(||F||) = clamp(||F|| / w - 1, 0, 1) for a width w = recolor_fade > 0: zero up to
+ *     ||F|| = w, one from 2w.  It exists for small periodic boxes, where F vanishes by
+ *     symmetry at mixed nodes between a drop and its images and its direction there is
+ *     rounding noise.
  *   - Step 0 uses the gradient of the initial phase field as the "previous" gradient.
  *   - Site criterion is strict (>).  An alternative local rule |rho^N_pre| < Gamma
  *     (site_rule = 1) uses the current pre-sink phase field.  A soft rule (site_rule = 2)
@@ -74,6 +77,7 @@ typedef struct {
     int site_rule; /* 0: ||F_prev|| > gamma (paper); 1: |rho^N_pre| < gamma;
                       2: soft weight 1 / (1 + exp(-(||F_prev|| - gamma) / kappa)) */
     double kappa;
+    double recolor_fade; /* 0: Eq. recolor as printed; w > 0: cos(theta) faded out below 2w */
 } ora_params;
 
 typedef struct {
@@ -516,8 +520,15 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
         colour_gradient(s, n, Fv);
         double F2 = Fv[0] * Fv[0] + Fv[1] * Fv[1] + Fv[2] * Fv[2];
         double Fn = sqrt(F2);
-        int has_grad = F2 > 0.0;
-        double fade = Fn >= 2e-5 ? 1.0 : (Fn > 1e-5 ? Fn / 1e-5 - 1.0 : 0.0);
+        /* cos(theta) and the perturbation are 0/0 forms at F = 0: both are taken as 0 where
+           F.F <= 1e-24 (their limit; the perturbation is O(||F||)) */
+        int has_grad = F2 > 1e-24;
+        double fade = 1.0; /* optional regularisation, off unless recolor_fade > 0 */
+        if (s->p.recolor_fade > 0.0) {
+            fade = Fn / s->p.recolor_fade - 1.0;
+            if (fade < 0.0) fade = 0.0;
+            if (fade > 1.0) fade = 1.0;
+        }
 
         for (int i = 0; i < Q; ++i) {
             double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];

@@ -21,7 +21,8 @@ class OraParams(C.Structure):
     _fields_ = [("Q", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("rho_in", C.c_double * 2), ("tau", C.c_double * 2), ("sigma", C.c_double),
                 ("beta", C.c_double), ("phi", C.c_double), ("sbar", C.c_double),
-                ("gamma", C.c_double), ("site_rule", C.c_int), ("kappa", C.c_double)]
+                ("gamma", C.c_double), ("site_rule", C.c_int), ("kappa", C.c_double),
+                ("recolor_fade", C.c_double)]
 
 
 class OraObs(C.Structure):
@@ -94,7 +95,8 @@ def tables(Q):
 
 class Oracle:
     """One oracle simulation.  `params` keys: Q, shape (nz, ny, nx), rho_in, tau, sigma,
-    beta, phi, sbar, gamma, site_rule ('grad', 'phase' or 'soft'), kappa (soft rule width)."""
+    beta, phi, sbar, gamma, site_rule ('grad', 'phase' or 'soft'), kappa (soft rule width),
+    recolor_fade (optional regularisation width of cos(theta); 0, the default, is Eq. recolor)."""
 
     def __init__(self, params, solid=None, phi_field=None):
         Q = int(params["Q"])
@@ -110,6 +112,7 @@ class Oracle:
         p.gamma = params["gamma"]
         p.site_rule = {"grad": 0, "phase": 1, "soft": 2}[params.get("site_rule", "grad")]
         p.kappa = params.get("kappa", 0.01)
+        p.recolor_fade = params.get("recolor_fade", 0.0)
         self.Q, self.shape, self.N = Q, (nz, ny, nx), nx * ny * nz
         self.D = 2 if Q == 9 else 3
         self._solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)

@@ -126,9 +126,13 @@ def _base(Q, shape, **kw):
     return p
 
 
-def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
+def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None, offset=None):
     """Workload dict: params (lattice + physics), rho_r, rho_b, solid (or None),
-    phi_field (or None), steps.  shape/radius downscale a workload; phi overrides the flux.
+    phi_field (or None), steps.  shape/radius downscale a workload; phi overrides the flux;
+    offset = (ox, oy, oz) moves the drop centre of the drop workloads off the box centre (a
+    centre on a node puts the saddles of the phase field between the drop and its periodic
+    images on nodes, where the gradient vanishes inside a mixture and its direction, and so the
+    recolouring angle, is rounding noise; half a node moves every such saddle between nodes).
 
     Names: 'drop2d' (D2Q9 128^2 drop R 32, |rho^N| < 0.5 site rule), 'flat2d' (D2Q9 1024^2
     flat interface between walls), 'ellipse2d' (D2Q9 1024^2 ellipse 200 x 120),
@@ -140,11 +144,12 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
     'contrast_flat3d' (D3Q19 160^3 film of height 80 on a wall at z = 0, 1, blue outlet on
     the top plane), 'cap3d' (D3Q19 192^3 cap pinned on a cylindrical cavity, ring radii
     50 / 53, height 8)."""
+    ox, oy, oz = offset or (0.0, 0.0, 0.0)
     if name == "drop2d":
         shape = shape or (1, 128, 128)
         R = radius or 32.0 * shape[2] / 128.0
         p = _base(9, shape, site_rule="phase", gamma=0.5)
-        d = sphere_distance(shape, (shape[2] / 2, shape[1] / 2, 0.0), R)
+        d = sphere_distance(shape, (shape[2] / 2 + ox, shape[1] / 2 + oy, 0.0), R)
         rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
         w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": None, "phi_field": None,
              "steps": 2000, "radius": R}
@@ -171,7 +176,7 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
         shape = shape or (256, 256, 256)
         R = radius or 64.0 * shape[2] / 256.0
         p = _base(19, shape, sigma=4.0 * 5e-4 / 9.0)
-        d = sphere_distance(shape, (shape[2] / 2, shape[1] / 2, shape[0] / 2), R)
+        d = sphere_distance(shape, (shape[2] / 2 + ox, shape[1] / 2 + oy, shape[0] / 2 + oz), R)
         rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
         w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": None, "phi_field": None,
              "steps": 10000, "radius": R}
@@ -180,13 +185,13 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
         nz, ny, nx = shape
         R = radius or 96.0 * nx / 384.0
         p = _base(19, shape, sigma=4.0 * 5e-4 / 9.0, rho_in=(1.0, 0.1), tau=(1.0, 0.6))
-        d = sphere_distance(shape, (nx / 2, ny / 2, 0.5), R)
+        d = sphere_distance(shape, (nx / 2 + ox, ny / 2 + oy, 0.5), R)
         rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
         solid = wall_layers(shape, 0, [0, nz - 1])
         rr = np.where(solid == 1, 0.0, rr)
         rb = np.where(solid == 1, 0.0, rb)
         _, y, x = grid(shape)
-        rxy = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2)
+        rxy = np.sqrt((x - nx / 2 - ox) ** 2 + (y - ny / 2 - oy) ** 2)
         ph = 1e-5 * (1.0 + 0.2 * rxy / R) + uniform_noise(shape, -1e-7, 1e-7,
                                                             1001 if seed is None else seed)
         w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": solid, "phi_field": ph,
@@ -196,7 +201,7 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
         s = shape[2] / 512.0
         R = radius or 96.0 * s
         p = _base(9, shape)
-        c = (shape[2] / 2, shape[1] / 2, 0.0)
+        c = (shape[2] / 2 + ox, shape[1] / 2 + oy, 0.0)
         d = sphere_distance(shape, c, R)
         rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
         ph = 1e-5 * uniform_noise(shape, 0.9, 1.1, 1002 if seed is None else seed)
@@ -226,7 +231,7 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
         nz, ny, nx = shape
         R = radius or (66.0 * nx / 192.0 if three else 66.0 * nx / 384.0)
         p = _base(19 if three else 9, shape, sigma=0.1, beta=0.99)
-        centre = (nx / 2, ny / 2, 0.5) if three else (nx / 2, 0.5, 0.0)
+        centre = (nx / 2 + ox, ny / 2 + oy, 0.5) if three else (nx / 2 + ox, 0.5, 0.0)
         d = sphere_distance(shape, centre, R)
         rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
         # walls at both ends of the substrate axis: with one wall layer and periodic wrap,
@@ -266,7 +271,7 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
                  "height": h0, "outlet": (False, True)}
         else:
             R = radius or 44.0 * nx / 192.0
-            d = sphere_distance(shape, (nx / 2, ny / 2, nz / 2), R)
+            d = sphere_distance(shape, (nx / 2 + ox, ny / 2 + oy, nz / 2 + oz), R)
             rr, rb = densities_from_distance(d, 2.0, p["rho_in"])
             w = {"params": p, "rho_r": rr, "rho_b": rb, "solid": None, "phi_field": None,
                  "radius": R, "outlet": (True, True)}
@@ -290,7 +295,7 @@ def workload(name, shape=None, radius=None, phi=None, seed=None, ratio=None):
         zc = top + hc - Rs
         p = _base(19, shape, sigma=0.1, beta=0.99)
         z, y, x = grid(shape)
-        r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2)
+        r = np.sqrt((x - nx / 2 - ox) ** 2 + (y - ny / 2 - oy) ** 2)
         dsph = Rs - np.sqrt(r * r + (z - zc) ** 2)
         d = np.where(z > top, dsph, np.where(r < r_in, np.maximum(dsph, r_in - r),
                                              np.minimum(dsph, r_out - r)))

@@ -59,9 +59,10 @@ def test_gradient_wrt_flux_matches_central_differences():
     _, masks = A.run(p, w["rho_r"], w["rho_b"], phi, n, return_masks=True)
     g = A.gradients(p, w["rho_r"], w["rho_b"], phi, n, target, masks=masks)["grad_phi"]
     assert float(g.abs().max()) > 0
-    # central differences carry an O(eps^2) truncation error (relative ~1e-4 .. 1e-3 at
-    # eps = 1e-3 on this instance); a wrong gradient would leave a floor that does not shrink,
-    # so the error must also fall ~100x when eps falls 10x
+    # central differences carry an O(eps^2) truncation error; a wrong gradient would leave a
+    # floor that does not shrink, so the error must also fall ~100x when eps falls 10x, unless
+    # both are already at the rounding floor (below 1e-7: the loss is linear in phi to ~1e-10
+    # over +-1e-3 relative on this instance), far below any wrong gradient's floor
     for trial in range(3):
         v = torch.as_tensor(rng.standard_normal(phi.shape), dtype=DT) * phi
         ad = float((g * v).sum())
@@ -72,7 +73,8 @@ def test_gradient_wrt_flux_matches_central_differences():
             lm = A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], phi - eps * v, n, masks=masks),
                              target)
             err.append(abs(float(lp - lm) / (2 * eps) - ad) / abs(ad))
-        assert err[0] < 2e-3 and err[1] < 2e-5 and err[1] < err[0] / 30, (trial, err)
+        assert err[0] < 2e-3 and err[1] < 2e-5, (trial, err)
+        assert err[1] < err[0] / 30 or max(err) < 1e-7, (trial, err)
 
 
 def test_gradient_wrt_gamma_matches_central_differences_soft_sites():
@@ -88,7 +90,8 @@ def test_gradient_wrt_gamma_matches_central_differences_soft_sites():
         lm = A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], phi, n,
                                gamma=torch.tensor(p["gamma"] - eps, dtype=DT)), target)
         err.append(abs(float(lp - lm) / (2 * eps) - res["grad_gamma"]) / abs(res["grad_gamma"]))
-    assert err[0] < 2e-3 and err[1] < 2e-5 and err[1] < err[0] / 30, err
+    assert err[0] < 2e-3 and err[1] < 2e-5, err
+    assert err[1] < err[0] / 30 or max(err) < 1e-7, err
 
 
 def test_red_mass_sensitivity_is_minus_mask_over_sbar():
