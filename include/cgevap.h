@@ -73,9 +73,11 @@ typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } 
  *            recolouring (Eq. recolor)) instead of its 2Q populations.  The first step of
  *            a call pulls populations and the last writes them, so between calls the state
  *            is populations as for every other form; a call of one step is SPLIT's step.
- *            Same support as SPLIT; needs 14 N values of library scratch (FP64 at FP64
- *            storage, FP32 otherwise; rows padded to 256 B), allocated at cge_create for
- *            RECORD, and for AUTO where AUTO selects it.
+ *            Same support as SPLIT, except FP16S (CGE_EUNSUPPORTED at cge_create: its FP32
+ *            records would keep the state between steps at FP32, not half precision); needs
+ *            14 N values of library scratch (FP64 at FP64 storage, FP32 otherwise; rows
+ *            padded to 256 B), allocated at cge_create for RECORD, and for AUTO where AUTO
+ *            selects it.
  *   AUTO:    at unit relaxation times RECORD for D3Q19 at FP64 and FP32 storage, SPLIT for
  *            D2Q9 (where the record pull has no LDS-staged form and is no faster) and at FP16
  *            storage (whose state between steps then stays in half precision); otherwise
@@ -104,6 +106,12 @@ typedef struct {
     int site_rule;          /* cge_site_rule                                              */
     int kernel;             /* cge_kernel                                                 */
     unsigned long long seed; /* stochastic-rounding stream (FP16S only)                   */
+    double recolor_fade;    /* 0 (default): cos(theta_i) = F.c_i / (||F|| ||c_i||) as in     */
+                            /* Eq. recolor, taken as 0 where F.F <= 1e-24 (with the         */
+                            /* perturbation).  w > 0: an optional regularisation, not the   */
+                            /* paper's model, multiplies cos(theta_i) by                    */
+                            /* clamp(||F||/w - 1, 0, 1) (for small periodic boxes where F   */
+                            /* vanishes by symmetry at mixed nodes).  Must be finite, >= 0. */
 } cge_params;
 
 /* Observables of the current state (post-streaming, pre-sink), reduced in FP64 in a fixed
@@ -246,6 +254,13 @@ cge_status cge_set_height_flux(cge_ctx* ctx, double phi_s, double K, double h_sc
  * CGE_EINVAL for rho_out <= 0 or not finite, or fewer than 3 planes along the axis.  The
  * adjoint returns CGE_EUNSUPPORTED while outlets are on. */
 cge_status cge_set_outlet(cge_ctx* ctx, int lo, int hi, double rho_out);
+
+/* Launch shape of the record form's z-marching pull (D3Q19, FP32 records): planes per
+ * z-chunk of a block's march.  0 (the default) chooses it from the grid and the device's
+ * compute-unit count; planes > 0 takes that many (at most nz).  Results do not depend on it
+ * beyond the grouping of the FP64 sink partials (1e-15 relative).  For tuning, and for tests
+ * of chunked marches on small grids.  CGE_EINVAL for planes < 0. */
+cge_status cge_set_zchunk(cge_ctx* ctx, int planes);
 
 /* Restore the step counter and the FP64 sink bookkeeping (checkpoint resume). */
 cge_status cge_set_counters(cge_ctx* ctx, long long step, long long site_steps,

@@ -23,7 +23,7 @@ EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibri
            "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
            "cge_load_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
            "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_outlet",
-           "cge_set_counters",
+           "cge_set_counters", "cge_set_zchunk",
            "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
@@ -35,7 +35,8 @@ class CgeParams(C.Structure):
                 ("sigma", C.c_double), ("beta", C.c_double), ("phi", C.c_double),
                 ("sbar", C.c_double), ("gamma", C.c_double), ("kappa", C.c_double),
                 ("site_rule", C.c_int),
-                ("kernel", C.c_int), ("seed", C.c_ulonglong)]
+                ("kernel", C.c_int), ("seed", C.c_ulonglong),
+                ("recolor_fade", C.c_double)]
 
 
 class CgeObs(C.Structure):
@@ -90,6 +91,7 @@ def lib():
         L.cge_set_height_flux.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_longlong]
         L.cge_set_outlet.argtypes = [vp, C.c_int, C.c_int, C.c_double]
         L.cge_set_counters.argtypes = [vp, C.c_longlong, C.c_longlong, C.c_double]
+        L.cge_set_zchunk.argtypes = [vp, C.c_int]
         L.cge_step.argtypes = [vp, C.c_longlong]
         L.cge_observables.argtypes = [vp, P(CgeObs)]
         L.cge_fields.argtypes = [vp, vp, vp, vp, vp]
@@ -127,6 +129,7 @@ def make_params(params, precision="fp64", kernel="auto", seed=0):
     p.site_rule = SITE_RULES[params.get("site_rule", "grad")]
     p.kernel = KERNELS[kernel]
     p.seed = seed
+    p.recolor_fade = params.get("recolor_fade", 0.0)
     return p
 
 
@@ -310,6 +313,10 @@ class Simulation:
                                        _ptr(g), _ptr(gr), _ptr(gphi), _ptr(gpt), C.byref(gg)))
         return {"grad_phi": gphi, "grad_phi_t": gpt, "grad_gamma": gg.value}
 
+    def set_zchunk(self, planes):
+        """Planes per z-chunk of the record form's z-marching pull (0: automatic)."""
+        self._check(lib().cge_set_zchunk(self._ctx, int(planes)))
+
     def set_counters(self, step=0, site_steps=0, sink_total=0.0):
         self._check(lib().cge_set_counters(self._ctx, step, site_steps, sink_total))
 
@@ -346,7 +353,10 @@ def _autograd_function():
         """rho^N after nsteps from a fixed start state, differentiable in the flux field phi(x)
         and the site threshold Gamma (hard sites held at the forward run's, or soft sites).
         The forward keeps a checkpoint every K steps; the backward recomputes each segment
-        and runs the library's reverse steps."""
+        and runs the library's reverse steps.  The segments are recomputed under the flux
+        field, Gamma and kappa of this forward, which the backward puts back into the
+        simulation first: another run on the same simulation between forward and backward
+        does not change the gradient."""
 
         @staticmethod
         def forward(ctx, phi_field, gamma, sim, start, nsteps, K):
@@ -359,11 +369,16 @@ def _autograd_function():
             ckpt = sim.forward_ckpt(nsteps, K)
             ctx.sim, ctx.ckpt, ctx.nsteps, ctx.K = sim, ckpt, nsteps, K
             ctx.phi_dtype, ctx.gamma_like = phi_field.dtype, gamma
+            ctx.phi_used = sim.phi_field.clone()
+            ctx.gamma_used = float(sim.params["gamma"])
+            ctx.kappa_used = float(sim.params.get("kappa", 0.01))
             return sim.fields()["rhoN"]
 
         @staticmethod
         def backward(ctx, grad_rhoN):
             sim = ctx.sim
+            sim.phi_field.copy_(ctx.phi_used)
+            sim.set_site_threshold(ctx.gamma_used, ctx.kappa_used)
             r = sim.backward(ctx.ckpt, ctx.nsteps, ctx.K, grad_rhoN.contiguous())
             gphi = r["grad_phi"].to(ctx.phi_dtype)
             gg = torch.as_tensor(r["grad_gamma"], dtype=ctx.gamma_like.dtype,

@@ -140,11 +140,14 @@ __device__ __forceinline__ void adj_node(const Phys<double>& P, double rho, doub
     const double om = UNIT ? 1.0 : pr * P.omega_r + pb * P.omega_b;
     const double abar = pr * P.alpha_r + pb * P.alpha_b;
     const double F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-    const bool hg = F2 > 0.0;
-    const double Fn = hg ? sqrt(F2) : 0.0;
-    const double iF = hg ? 1.0 / Fn : 0.0;
-    const double fade = Fn >= 2e-5 ? 1.0 : (Fn > 1e-5 ? Fn * 1e5 - 1.0 : 0.0);
-    const double dfade = (Fn > 1e-5 && Fn < 2e-5) ? 1e5 : 0.0;
+    const double Fn = F2 > 0.0 ? sqrt(F2) : 0.0;
+    const double iFc = F2 > 0.0 ? 1.0 / Fn : 0.0;  // d||F||/dF = F iFc (the carried ||F||)
+    // cos(theta) and the perturbation are cut where F.F <= kF2Cut (as in the forward step)
+    const bool hg = F2 > kF2Cut;
+    const double Fp = hg ? Fn : 0.0;
+    const double iF = hg ? iFc : 0.0;
+    const double fade = recolor_fade(Fn, P.inv_fade);
+    const double dfade = recolor_fade_slope(Fn, P.inv_fade);
     const double kp = 2.25 * P.sigma * om;
     const double sep = 0.5 * P.beta * (1.0 - rN * rN) * rho;
 
@@ -158,7 +161,7 @@ __device__ __forceinline__ void adj_node(const Phys<double>& P, double rho, doub
         const double Fc = cx * F[0] + cy * F[1] + cz * F[2];
         const double t = A + B * abar;
         const double feq = rho * (t + W * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        const double Pq = W * Fc * Fc * iF - pertC<Q>(i) * Fn;
+        const double Pq = W * Fc * Fc * iF - pertC<Q>(i) * Fp;
         double f2, f = 0.0;
         if constexpr (UNIT) {
             f2 = feq + kp * Pq;
@@ -218,7 +221,7 @@ __device__ __forceinline__ void adj_node(const Phys<double>& P, double rho, doub
     drN_o = drN;
     drho_o = drho_p;
     // the carried ||F_n|| feeds the next step's soft site weight
-    const double aFn = aF1n * iF;
+    const double aFn = aF1n * iFc;
     lamF_o[0] = dF[0] + (sF + aFn) * F[0];
     lamF_o[1] = dF[1] + (sF + aFn) * F[1];
     lamF_o[2] = dF[2] + (sF + aFn) * F[2];
@@ -241,11 +244,13 @@ __device__ __forceinline__ void adj_node_unit(const Phys<double>& P, double rho,
     const double pr = 0.5 * (1.0 + rN), pb = 0.5 * (1.0 - rN);
     const double abar = pr * P.alpha_r + pb * P.alpha_b;
     const double F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-    const bool hg = F2 > 0.0;
-    const double Fn = hg ? sqrt(F2) : 0.0;
-    const double iF = hg ? 1.0 / Fn : 0.0;
-    const double fade = Fn >= 2e-5 ? 1.0 : (Fn > 1e-5 ? Fn * 1e5 - 1.0 : 0.0);
-    const double dfade = (Fn > 1e-5 && Fn < 2e-5) ? 1e5 : 0.0;
+    const double Fn = F2 > 0.0 ? sqrt(F2) : 0.0;
+    const double iFc = F2 > 0.0 ? 1.0 / Fn : 0.0;
+    const bool hg = F2 > kF2Cut;
+    const double Fp = hg ? Fn : 0.0;
+    const double iF = hg ? iFc : 0.0;
+    const double fade = recolor_fade(Fn, P.inv_fade);
+    const double dfade = recolor_fade_slope(Fn, P.inv_fade);
     const double kp = 2.25 * P.sigma;
     const double sep = 0.5 * P.beta * (1.0 - rN * rN) * rho;
     // class constants: k = 0 rest, 1 axis, 2 diagonal
@@ -259,7 +264,7 @@ __device__ __forceinline__ void adj_node_unit(const Phys<double>& P, double rho,
         wr[k] = rho * W;
         base[k] = rho * t[k] - 1.5 * wr[k] * uu;
         pf[k] = kp * W * iF;
-        kc[k] = kp * pertC<Q>(i) * Fn;
+        kc[k] = kp * pertC<Q>(i) * Fp;
     }
     double drN = 0.0, Sxf = 0.0;
     double X0[3] = {0.0, 0.0, 0.0}, E1[3] = {0.0, 0.0, 0.0}, X2[3] = {0.0, 0.0, 0.0};
@@ -327,7 +332,7 @@ __device__ __forceinline__ void adj_node_unit(const Phys<double>& P, double rho,
     drho_p -= (du[0] * u[0] + du[1] * u[1] + du[2] * u[2]) / rho;
     drN_o = drN;
     drho_o = drho_p;
-    const double aFn = aF1n * iF;
+    const double aFn = aF1n * iFc;
     lamF_o[0] = dF[0] + (sF + aFn) * F[0];
     lamF_o[1] = dF[1] + (sF + aFn) * F[1];
     lamF_o[2] = dF[2] + (sF + aFn) * F[2];

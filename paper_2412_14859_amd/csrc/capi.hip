@@ -49,6 +49,7 @@ Phys<M> phys(const cge_ctx* c) {
     P.phi = M(c->p.phi);
     P.inv_sbar = M(1.0 / c->p.sbar);
     P.inv_kappa = M(c->p.site_rule == CGE_SITE_SOFT ? 1.0 / c->p.kappa : 0.0);
+    P.inv_fade = M(c->p.recolor_fade > 0.0 ? 1.0 / c->p.recolor_fade : 0.0);
     P.site_rule = c->p.site_rule;
     return P;
 }
@@ -143,6 +144,8 @@ static const char* validate(const cge_params* p) {
     if (p->site_rule == CGE_SITE_SOFT && !(is_fin(p->kappa) && p->kappa > 0.0))
         return "kappa must be > 0 for the soft site rule";
     if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_RECORD) return "unknown kernel";
+    if (!(is_fin(p->recolor_fade) && p->recolor_fade >= 0.0))
+        return "recolor_fade must be finite and >= 0";
     return nullptr;
 }
 
@@ -177,8 +180,11 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     // split step needs unit relaxation times
     const bool unit = split_supported(c);
     const bool soft = params->site_rule == CGE_SITE_SOFT;
+    // the record form keeps FP32 records between the steps of a call, so at FP16 storage
+    // only a call's last step would store half precision: refused rather than mislabelled
     if ((params->kernel == CGE_KERNEL_FUSED && (c->Q != 19 || soft)) ||
-        ((params->kernel == CGE_KERNEL_SPLIT || params->kernel == CGE_KERNEL_RECORD) && !unit)) {
+        ((params->kernel == CGE_KERNEL_SPLIT || params->kernel == CGE_KERNEL_RECORD) && !unit) ||
+        (params->kernel == CGE_KERNEL_RECORD && params->precision == CGE_FP16S)) {
         delete c;
         return CGE_EUNSUPPORTED;
     }
@@ -367,6 +373,13 @@ cge_status cge_set_site_threshold(cge_ctx* c, double gamma, double kappa) {
         return fail(c, CGE_EINVAL, "site threshold must be finite");
     c->p.gamma = gamma;
     if (kappa > 0.0) c->p.kappa = kappa;
+    return CGE_OK;
+}
+
+cge_status cge_set_zchunk(cge_ctx* c, int planes) {
+    if (!c) return CGE_EINVAL;
+    if (planes < 0) return fail(c, CGE_EINVAL, "planes must be >= 0");
+    c->zchunk = planes;
     return CGE_OK;
 }
 

@@ -20,6 +20,7 @@ struct cge_ctx {
     int device = 0;
     int cus = 0;  // compute units of the device (launch shapes that fill the chip)
     int kernel = CGE_KERNEL_TWOPASS;  // resolved step implementation
+    int zchunk = 0;                   // planes per chunk of the z-marching pull (0: automatic)
     // caller-owned buffers
     void* pop[2] = {nullptr, nullptr};
     int cur = 0;  // pop[cur] holds the current state

@@ -78,8 +78,29 @@ struct Phys {
     M phi;            // uniform flux
     M inv_sbar;
     M inv_kappa;      // soft site rule width
+    M inv_fade;       // 1 / recolor_fade, or 0 when the optional cos(theta) fade is off
     int site_rule;    // 0 grad, 1 phase, 2 soft
 };
+
+// cos(theta_i) and the perturbation are 0/0 forms at F = 0 (Eqs. perturb, recolor): both are
+// taken as 0 where F.F is at most this (their limit; the perturbation is O(||F||)).
+constexpr double kF2Cut = 1e-24;
+
+// Optional regularisation of the recolouring angle (off when inv_fade == 0): cos(theta_i) is
+// multiplied by clamp(||F|| / w - 1, 0, 1) for the width w = 1 / inv_fade.
+template <typename M>
+__host__ __device__ __forceinline__ M recolor_fade(M Fn, M inv_fade) {
+    if (!(inv_fade > M(0))) return M(1);
+    const M g = Fn * inv_fade - M(1);
+    return g < M(0) ? M(0) : (g > M(1) ? M(1) : g);
+}
+// its derivative with respect to ||F||
+template <typename M>
+__host__ __device__ __forceinline__ M recolor_fade_slope(M Fn, M inv_fade) {
+    if (!(inv_fade > M(0))) return M(0);
+    const M g = Fn * inv_fade - M(1);
+    return (g > M(0) && g < M(1)) ? inv_fade : M(0);
+}
 
 struct Geo {
     int nx, ny, nz;

@@ -351,7 +351,9 @@ __device__ __forceinline__ void gradient(const R* __restrict__ rhoN, const Geo& 
 // diagonal) is formed once per node:
 //   feq_i = base_k + W_k rho (c_i.u) (3 + 4.5 c_i.u),   base_k = A_k drho + B_k dB - 1.5 W_k rho u.u
 //   pert_i = (9/4)(sigma/tau) [W_k (F.c_i)^2 / |F| - C_k |F|]
-//   dd_i = rho^N full_i + [2 beta (rho_r rho_b / rho) fade / (|F| |c_i|) t_k(abar)] (F.c_i)
+//   dd_i = rho^N full_i + [2 beta (rho_r rho_b / rho) / (|F| |c_i|) t_k(abar)] (F.c_i)
+// (cos(theta) and the perturbation taken as 0 where F.F <= kF2Cut; the optional fade of
+// cos(theta) multiplies the bracket)
 template <int Q, typename M, bool UNIT = false, typename Load, typename Store>
 __device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M (&u)[3],
                                      const M (&F)[3], const Phys<M>& P, Store&& store) {
@@ -363,15 +365,14 @@ __device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M
     const M dB = rho * (abar - P.alpha_ref) + drho * P.alpha_ref;
     const M uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const M F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-    const bool hg = F2 > M(0);
-    const M Fn = hg ? sqrt(F2) : M(0);
+    const M Fn = F2 > M(0) ? sqrt(F2) : M(0);  // carried to the next step's site decision
+    const bool hg = F2 > M(kF2Cut);
+    const M Fp = hg ? Fn : M(0);               // ||F|| in the perturbation
     const M invFn = hg ? M(1) / Fn : M(0);
     const M kp = M(2.25) * P.sigma * omega;                         // (9/4) sigma / tau
     const M sep = M(0.5) * P.beta * (M(1) - rhoN * rhoN) * rho;      // 2 beta rho_r rho_b / rho
-    // cos(theta_i) = F.c_i / (|F| |c_i|) fades out linearly between |F| = 2e-5 and 1e-5: where
-    // F vanishes by symmetry inside a mixture its direction is rounding noise
-    const M fade = Fn >= M(2e-5) ? M(1) : (Fn > M(1e-5) ? Fn * M(1e5) - M(1) : M(0));
-    const M cosw = invFn * fade;
+    // cos(theta_i) = F.c_i / (|F| |c_i|) (Eq. recolor), times the optional fade
+    const M cosw = invFn * recolor_fade(Fn, P.inv_fade);
     // per weight class k: 0 rest, 1 axis (|c| = 1), 2 diagonal (|c| = sqrt 2)
     constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;  // first direction of classes 1 and 2
     M base[3], wr[3], pf[3], kc[3], tref[3], gs[3];
@@ -382,7 +383,7 @@ __device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M
         wr[k] = W * rho;
         base[k] = A * drho + B * dB - M(1.5) * wr[k] * uu;
         pf[k] = kp * W * invFn;
-        kc[k] = kp * M(pertC<Q>(i)) * Fn;
+        kc[k] = kp * M(pertC<Q>(i)) * Fp;
         tref[k] = P.rho_ref * (A + B * P.alpha_ref);
         gs[k] = sep * cosw * M(inv_len<Q>(i)) * (A + B * abar);
     }
@@ -411,7 +412,8 @@ __device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M
 // weight class k and direction i of that class (h_k = W_k / W_1),
 //   ft_i* = b_k + h_k A (c_i.u)(1 + 1.5 c_i.u) + h_k P (F.c_i)^2
 //   dd_i* = rho^N (ft_i* + t_ref,k) + g_k (F.c_i)
-// with A = 3 W_1 rho, P = W_1 kp / |F|, b_k = base_k - kc_k and g_k = gs_k formed as in
+// with A = 3 W_1 rho, P = W_1 kp / |F| (0 where F.F <= kF2Cut), b_k = base_k - kc_k and
+// g_k = gs_k formed as in
 // collide (t_ref,k = rho_ref t_k(alpha_ref)).  The record is b_0, b_1, b_2, A, P, u, F,
 // rho^N, g_1, g_2: 14 values instead of 2Q populations.  Returns ||F||.
 constexpr int kRec = 14;
@@ -427,20 +429,20 @@ __device__ __forceinline__ M record_values(M drho, M rho, M rhoN, const M (&u)[3
     const M dB = rho * (abar - P.alpha_ref) + drho * P.alpha_ref;
     const M uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const M F2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-    const bool hg = F2 > M(0);
-    const M Fn = hg ? sqrt(F2) : M(0);
+    const M Fn = F2 > M(0) ? sqrt(F2) : M(0);
+    const bool hg = F2 > M(kF2Cut);
+    const M Fp = hg ? Fn : M(0);
     const M invFn = hg ? M(1) / Fn : M(0);
     const M kp = M(2.25) * P.sigma * omega;
     const M sep = M(0.5) * P.beta * (M(1) - rhoN * rhoN) * rho;
-    const M fade = Fn >= M(2e-5) ? M(1) : (Fn > M(1e-5) ? Fn * M(1e5) - M(1) : M(0));
-    const M cosw = invFn * fade;
+    const M cosw = invFn * recolor_fade(Fn, P.inv_fade);
     constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int i = k == 0 ? 0 : (k == 1 ? i1 : i2);
         const M A = M(restA<Q>(i)), B = M(restB<Q>(i)), W = M(weight<Q>(i));
         const M base = A * drho + B * dB - M(1.5) * (W * rho) * uu;
-        r[kB0 + k] = base - kp * M(pertC<Q>(i)) * Fn;
+        r[kB0 + k] = base - kp * M(pertC<Q>(i)) * Fp;
         if (k > 0) r[kG1 + k - 1] = sep * cosw * M(inv_len<Q>(i)) * (A + B * abar);
     }
     const M W1 = M(weight<Q>(i1));

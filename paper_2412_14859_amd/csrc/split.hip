@@ -539,6 +539,7 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
 // a second round nearly empty: 0.58 ms).
 static int zm_chunk(const cge_ctx* c) {
     const Geo& g = c->g;
+    if (c->zchunk > 0) return c->zchunk < g.nz ? c->zchunk : g.nz;
     const long long tiles = (long long)((g.nx + kZmX - 1) / kZmX) * ((g.ny + kZmY - 1) / kZmY);
     const long long slots = 2ll * (c->cus > 0 ? c->cus : 1);
     long long best = -1, best_zc = g.nz;

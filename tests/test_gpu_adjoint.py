@@ -279,6 +279,40 @@ def test_autograd_function_wrapper():
     sim.close()
 
 
+def test_autograd_function_interleaved_runs():
+    """Two differentiable runs on one simulation, both forwards before either backward, with
+    different flux fields and thresholds: each backward gives the gradient of its own run, the
+    one the same run gives when its backward follows its forward directly."""
+    import torch
+    from paper_2412_14859_amd import cgevap
+    w, target = _setup("d2q9_soft")
+    _flush("[adjoint] interleaved evaporate calls")
+    sim = gpu_for(w, "fp64")
+    start = sim.save_state().clone()
+    dev = sim.device
+    tgt = torch.as_tensor(target, device=dev)
+    base = torch.as_tensor(w["phi_field"], device=dev)
+    runs = [(base, w["params"]["gamma"]), (base * 1.3, w["params"]["gamma"] + 0.01)]
+
+    def leaves(ph, g):
+        return (ph.clone().requires_grad_(True),
+                torch.tensor(g, dtype=torch.float64, device=dev, requires_grad=True))
+
+    seq = []
+    for ph, g in runs:  # each backward right after its forward
+        phi, gamma = leaves(ph, g)
+        ((cgevap.evaporate(sim, phi, gamma, 25, 7, start) - tgt) ** 2).sum().backward()
+        seq.append((phi.grad.clone(), float(gamma.grad)))
+    ins = [leaves(ph, g) for ph, g in runs]
+    losses = [((cgevap.evaporate(sim, phi, gamma, 25, 7, start) - tgt) ** 2).sum()
+              for phi, gamma in ins]
+    for k in (1, 0):  # the later run's backward first, then the earlier one's
+        losses[k].backward()
+        assert torch.equal(ins[k][0].grad, seq[k][0]), k
+        assert float(ins[k][1].grad) == seq[k][1], k
+    sim.close()
+
+
 @pytest.mark.parametrize("name", ["d2q9_soft", "d2q9_soft_ratio"])
 def test_backward_is_repeatable_and_restores_the_state(name):
     """The backward seeds from the final checkpoint and leaves the context at the final state

@@ -14,11 +14,11 @@ def _flush(msg):
     print(msg, flush=True)
 
 
-def _evaporate(name, shape, phi, equil, flat):
+def _evaporate(name, shape, phi, equil, flat, precision="fp32s", fade=0.0):
     w = inputs.workload(name, shape=shape, ratio=2.0)
-    p = dict(w["params"], phi=0.0)
+    p = dict(w["params"], phi=0.0, recolor_fade=fade)
     sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
-                            phi_field=np.zeros(p["shape"]), precision="fp32s")
+                            phi_field=np.zeros(p["shape"]), precision=precision)
 
     def position():
         rr = sim.fields()["rho_r"]
@@ -68,12 +68,19 @@ def test_drop_at_density_ratio_two_follows_the_radius_law():
     assert float(rb.max()) < 1.01
 
 
-def test_film_at_density_ratio_two_follows_the_height_law():
+@pytest.mark.parametrize("precision,fade", [("fp64", 0.0), ("fp32s", 1e-5)])
+def test_film_at_density_ratio_two_follows_the_height_law(precision, fade):
     """Film 80 x 16 x 16 (h0 = 40, wall z = 0, 1, outlet at the top), phi = 3e-3, Gamma =
-    0.312 (matched to the mass-loss rate): within 3 % of h0 - phi t / rho0 up to t* = 0.85."""
-    _flush("[contrast] film 80x16x16 h0=40 ratio 2 phi 3e-3")
+    0.312 (matched to the mass-loss rate): within 3 % of h0 - phi t / rho0 up to t* = 0.85.
+    In FP64 with Eq. recolor as printed; at FP32 storage with the optional recolouring fade:
+    there the deterministic rounding of the stored colour differences leaves a red residue of
+    ~3e-7 in the blue above the film, whose gradient is rounding noise, and the recolouring
+    (a flux of fixed size along the unit gradient, whatever the gradient's magnitude)
+    gathers it into a red droplet from t* ~ 0.35 on (red fraction 0.05 there by t* = 0.55);
+    the fade switches the recolouring off where ||F|| < 2e-5, far below any interface."""
+    _flush(f"[contrast] film 80x16x16 h0=40 ratio 2 phi 3e-3 {precision} fade={fade}")
     x0, rho0, tstar, xs, ref, obs, rb = _evaporate("contrast_flat3d", (80, 16, 16), 3e-3, 2000,
-                                                   True)
+                                                   True, precision, fade)
     err = np.abs(xs - ref) / ref
     _flush(f"  h0 {x0:.3f} rho0 {rho0:.4f}; error by t*: " +
            " ".join(f"{a:.2f}:{e:.4f}" for a, e in zip(tstar[::4], err[::4])) +

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_2412_14859_amd import inputs
-from tests.helpers import e_pop, gpu_for, oracle_for
+from tests.helpers import HALF_NODE, e_pop, gpu_for, oracle_for
 
 pytestmark = pytest.mark.gpu
 
@@ -15,9 +15,13 @@ def _flush(msg):
 
 def _drop(Q, shape, R, ratio=2.0, wall=False, phi=1e-3):
     """A drop (density ratio `ratio`) in the middle of the last axis, blue at 1.03 so that
-    the outlets (rho_b = 1) draw an outflow; optionally a wall plane at index 0."""
+    the outlets (rho_b = 1) draw an outflow; optionally a wall plane at index 0.  The centre
+    sits half a node off the box centre (tests/helpers.HALF_NODE): no saddle of the phase
+    field between the drop and its periodic images falls on a node."""
     nz, ny, nx = shape
-    centre = (nx / 2, ny / 2, nz / 2) if Q == 19 else (nx / 2, ny / 2, 0.0)
+    ox, oy, oz = HALF_NODE
+    centre = (nx / 2 + ox, ny / 2 + oy, nz / 2 + oz) if Q == 19 else \
+        (nx / 2 + ox, ny / 2 + oy, 0.0)
     d = inputs.sphere_distance(shape, centre, R)
     rr, rb = inputs.densities_from_distance(d, 2.0, (ratio, 1.03))
     p = inputs._base(Q, shape, rho_in=(ratio, 1.0), phi=phi)
@@ -42,11 +46,10 @@ def test_outlet_matches_the_oracle(name, kernel):
     """FP64 step parity: every step, the oracle restarted from the GPU's state agrees with the
     GPU's next state within 1e-12, or within 10x the spread of a second restarted oracle whose
     input is perturbed by 2e-16 relative where that is larger; the free-running trajectories
-    are compared the same way against a perturbed oracle run.  The gauge matters where a node
-    crosses the fade window of cos(theta) (slope 1e5 in ||F||) while it holds both colours:
-    here the outlet flow takes the saddle between the drop and its periodic image (||F|| ~
-    1e-5 one interface width outside the drop) through it around step 11, and an ulp of
-    summation order in F becomes ~1e-12 in one step there, in the oracle against itself too."""
+    are compared the same way against a perturbed oracle run.  The gauge covers a node whose
+    recolouring angle is ill-conditioned (a mixed node where F nearly vanishes, so that an ulp
+    of summation order in F turns its direction); the drop is placed so that none is expected,
+    and the test reports how many steps needed the gauge."""
     Q, shape, R, wall = CASES[name]
     w = _drop(Q, shape, R, wall=wall)
     lo, hi = (not wall), True

@@ -25,13 +25,18 @@ CASES = {
     "d3q19_chunks": ("sphere3d", (40, 10, 70), dict(radius=4.5, phi=1e-3)),
     # relaxation times other than 1 (the general collision path of the fused step)
     "d3q19_tau": ("sphere3d", (20, 12, 70), dict(radius=4.0, phi=1e-3, tau=(1.0, 0.8))),
-    # logistic (soft) site weights of the gradient magnitude; Gamma / kappa = 10 keeps the
-    # bulk weight near 5e-5 (a weight of order 0.1 in the bulk drains the lighter colour below
-    # zero, where recolouring amplifies rounding differences step by step)
+    # logistic (soft) site weights of the gradient magnitude; Gamma / kappa = 30 keeps the
+    # bulk weight near 6e-14 (a weight of 1e-7 or more in the bulk drains the lighter colour
+    # below zero far from the drop within the run, where recolouring turns anti-diffusive and
+    # amplifies rounding differences step by step)
     "d2q9_soft": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3, site_rule="soft",
-                                                 gamma=0.1, kappa=0.01)),
+                                                 gamma=0.305, kappa=0.01)),
     "d3q19_soft": ("sphere3d", (14, 16, 70), dict(radius=5.0, phi=1e-3, site_rule="soft",
-                                                  kappa=0.02)),
+                                                  kappa=0.01)),
+    # the optional recolouring fade (not the paper's model; off by default) against the
+    # oracle's same option, on a drop centred on a node with its images close by
+    "d3q19_fade": ("sphere3d", (14, 16, 70), dict(radius=5.0, phi=1e-3, recolor_fade=1e-5,
+                                                  offset=(0.0, 0.0, 0.0))),
 }
 
 # step implementations to check per case: the two-pass step covers everything, the fused
