@@ -38,7 +38,9 @@ typedef enum {
     CGE_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed           */
     CGE_ESTATE = -4,       /* call out of order (e.g. step before cge_bind)        */
     CGE_EUNSUPPORTED = -5, /* valid but not supported combination                  */
-    CGE_ENUMERIC = -6      /* non-finite values found in the state                 */
+    CGE_ENUMERIC = -6,     /* non-finite values found in the state                 */
+    CGE_ECHECKPOINT = -7,  /* a saved state failed its integrity check             */
+    CGE_ESCRATCH = -8      /* the grid needs more than the static scratch holds    */
 } cge_status;
 
 typedef enum { CGE_D2Q9 = 9, CGE_D3Q19 = 19 } cge_lattice;
@@ -272,6 +274,30 @@ cge_status cge_step(cge_ctx* ctx, long long nsteps);
 
 /* Reduce the observables of the current state into *out (host).  Synchronises the stream. */
 cge_status cge_observables(cge_ctx* ctx, cge_obs* out);
+
+/* The observables of cge_observables for a state given by buffers instead of a context, for
+ * callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation).  It allocates nothing: its scratch (per-block FP64
+ * partials and an FP64 phase field) is a static 64 MiB device array of the library, which each
+ * GPU it runs on holds until the process ends; a grid qualifies when
+ *     8 (12 B + N) + 256 <= 64 MiB,   N = nx ny nz,  B = ceil(nx / min(256, 64 ceil(nx/64))) ny nz
+ * (D3Q19 up to 199^3, D2Q9 up to about 2800^2), else CGE_ESCRATCH before any device work.
+ *   params : the state's lattice, grid, precision and physics (validated as by cge_create)
+ *   pop    : device, one population buffer in the library's encoding (cge_bind), e.g. the
+ *            first cge_population_bytes() bytes of a cge_save_state snapshot
+ *   carry  : device, the carried site data of that state (the snapshot's carry part)
+ *   flags  : device, nullable, solid nodes as for cge_bind
+ *   out    : device, one cge_obs written by the last kernel; step, site_steps and sink_total
+ *            (context bookkeeping) are written as 0.  Copy it to the host after the stream.
+ * All work is enqueued on hip_stream (NULL = default stream); nothing synchronises.  Every call
+ * on one GPU shares that GPU's scratch, and a call overwrites all of it that it reads, so
+ * consecutive calls need no clearing, but calls that overlap on one GPU (different streams or
+ * host threads) race and must be serialised by the caller.  The first call on a device looks
+ * up the scratch address there (hipGetSymbolAddress).  Errors: CGE_EINVAL (bad parameters or a
+ * NULL pop, carry or out), CGE_ESCRATCH, CGE_EDEVICE. */
+cge_status cge_observables_noalloc(const cge_params* params, const void* pop,
+                                   const unsigned char* carry, const unsigned char* flags,
+                                   void* hip_stream, cge_obs* out);
 
 /* Per-node FP64 fields of the current state into device arrays (each nullable):
  * rho_r, rho_b, rhoN ([N]) and u ([D][N]).  Solid nodes get 0 (rhoN: wetting value). */

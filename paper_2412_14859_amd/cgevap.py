@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcgevap.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
+ECHECKPOINT, ESCRATCH = -7, -8
 PRECISIONS = {"fp64": 0, "fp32s": 1, "fp16s": 2}
 KERNELS = {"auto": 0, "twopass": 1, "fused": 2, "split": 3, "record": 4}
 SITE_RULES = {"grad": 0, "phase": 1, "soft": 2}
@@ -24,7 +25,7 @@ EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibri
            "cge_load_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
            "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_outlet",
            "cge_set_counters", "cge_set_zchunk",
-           "cge_step", "cge_observables", "cge_fields", "cge_set_timing", "cge_timing",
+           "cge_step", "cge_observables", "cge_observables_noalloc", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
 
@@ -94,6 +95,7 @@ def lib():
         L.cge_set_zchunk.argtypes = [vp, C.c_int]
         L.cge_step.argtypes = [vp, C.c_longlong]
         L.cge_observables.argtypes = [vp, P(CgeObs)]
+        L.cge_observables_noalloc.argtypes = [P(CgeParams), vp, vp, vp, vp, vp]
         L.cge_fields.argtypes = [vp, vp, vp, vp, vp]
         L.cge_set_timing.argtypes = [vp, C.c_int]
         L.cge_timing.argtypes = [vp, dp, P(C.c_longlong)]
@@ -344,6 +346,29 @@ def copy_probe(dst, src, nbytes, stream):
     st = lib().cge_copy_probe(_ptr(dst), _ptr(src), int(nbytes), C.c_void_p(stream.cuda_stream))
     if st != OK:
         raise CgeError(st, "copy probe failed")
+
+
+def observables_noalloc(params, precision, pop, carry, flags=None, stream=None, out=None):
+    """cge_observables_noalloc on device buffers (torch tensors): the observables of the state
+    in `pop` (encoded populations) and `carry`, with the library's static scratch.  Returns the
+    device tensor of one cge_obs (`out` if given, else a new one) without synchronising; decode
+    it with obs_from_device."""
+    import torch
+    if out is None:
+        out = torch.empty(C.sizeof(CgeObs), dtype=torch.uint8, device=pop.device)
+    cp = make_params(params, precision)
+    st = lib().cge_observables_noalloc(C.byref(cp), _ptr(pop), _ptr(carry), _ptr(flags),
+                                       C.c_void_p(stream.cuda_stream if stream is not None else 0),
+                                       _ptr(out))
+    if st != OK:
+        raise CgeError(st, "cge_observables_noalloc failed")
+    return out
+
+
+def obs_from_device(t):
+    """A cge_obs device tensor (bytes) as a dict."""
+    raw = bytes(t.cpu().numpy().tobytes())
+    return CgeObs.from_buffer_copy(raw).as_dict()
 
 
 def _autograd_function():

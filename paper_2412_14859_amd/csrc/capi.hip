@@ -460,6 +460,12 @@ cge_status cge_observables(cge_ctx* c, cge_obs* out) {
     return CGE_OK;
 }
 
+cge_status cge_observables_noalloc(const cge_params* p, const void* pop, const unsigned char* carry,
+                                   const unsigned char* flags, void* hip_stream, cge_obs* out) {
+    if (validate(p) || !pop || !carry || !out) return CGE_EINVAL;
+    return observables_noalloc(p, pop, carry, flags, hip_stream, out);
+}
+
 cge_status cge_fields(cge_ctx* c, double* rho_r, double* rho_b, double* u, double* rhoN) {
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");

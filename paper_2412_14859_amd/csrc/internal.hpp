@@ -110,6 +110,9 @@ size_t adjoint_bytes(const cge_params* p);
 
 // observables into c->obs_res (device), then copied to host by the caller
 cge_status observables(cge_ctx* c);
+// the same on explicit buffers, with the scratch in the library's static device array
+cge_status observables_noalloc(const cge_params* p, const void* pop, const unsigned char* carry,
+                               const unsigned char* flags, void* hip_stream, cge_obs* out);
 
 cge_status copy_probe(void* dst, const void* src, size_t nbytes, hipStream_t s);
 

@@ -5,6 +5,8 @@
 //   pass B (per node): (1/2)||grad rho^N|| (interface measure), after max rho_r is known:
 //          count of rho_r > max/2 (interface position rule of Sec. III)
 //   final: one block sums the per-block partials and the per-block sink accumulators.
+#include <mutex>
+
 #include "internal.hpp"
 #include "node.hpp"
 
@@ -172,27 +174,154 @@ __global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ pa
     }
 }
 
+// Scratch of one reduction: CGE_NOBS per-block partials, then the FP64 phase field (N values).
+static long long obs_blocks_of(const Geo& g) {
+    const dim3 gr = node_grid(g);
+    return (long long)gr.x * gr.y * gr.z;
+}
+static size_t obs_scratch_bytes(const Geo& g) {
+    return ((size_t)CGE_NOBS * obs_blocks_of(g) + (size_t)g.N) * sizeof(double);
+}
+
+// The reduction's launches on explicit buffers: part (obs_scratch_bytes), res (CGE_NOBS + 2
+// doubles; the last two take the sink accumulators when acc_sink is given).
+template <int Q, typename S, bool WALLS>
+static hipError_t obs_launch(const S* pop, const uint8_t* flags, const void* carry, double* part,
+                             double* res, const double* acc_sink, const long long* acc_sites,
+                             long long nacc, const Geo& g, const Phys<double>& P,
+                             hipStream_t stream) {
+    const dim3 gr = node_grid(g), bl = node_block(g);
+    const long long nblk = obs_blocks_of(g);
+    double* rhoN = part + (long long)CGE_NOBS * nblk;  // N doubles after the partials
+    hipLaunchKernelGGL((k_obs_a<Q, S, WALLS>), gr, bl, 0, stream, pop, flags, carry, rhoN, part,
+                       nblk, g, P, Lat<Q>::zeta);
+    if (WALLS)  // neutral wetting of the solid nodes, for the gradient of pass B
+        hipLaunchKernelGGL((k_wet<Q, double>), gr, bl, 0, stream, flags, rhoN, g);
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, stream, part, nblk, 0, 10,
+                       (const double*)nullptr, (const long long*)nullptr, 0LL, res);
+    hipLaunchKernelGGL((k_obs_b<Q, S, WALLS>), gr, bl, 0, stream, pop, flags, rhoN, res, part,
+                       nblk, g, P);
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, stream, part, nblk, O_PERIM, CGE_NOBS,
+                       acc_sink, acc_sites, nacc, res);
+    return hipGetLastError();
+}
+
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status obs_impl(cge_ctx* c) {
-    const Phys<double> P = phys<double>(c);
-    const dim3 gr = node_grid(c->g), bl = node_block(c->g);
-    const long long nblk = (long long)gr.x * gr.y * gr.z;
-    double* rhoN = c->obs_part + (long long)CGE_NOBS * nblk;  // N doubles after the partials
-    hipLaunchKernelGGL((k_obs_a<Q, S, WALLS>), gr, bl, 0, c->stream,
-                       static_cast<const S*>(c->pop[c->cur]), c->flags, c->carry, rhoN, c->obs_part,
-                       nblk, c->g, P, Lat<Q>::zeta);
-    if (WALLS)
-        if (cge_status s = wet_field<double>(c, rhoN)) return s;
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, c->stream, c->obs_part, nblk, 0, 10,
-                       (const double*)nullptr, (const long long*)nullptr, 0LL, c->obs_res);
-    hipLaunchKernelGGL((k_obs_b<Q, S, WALLS>), gr, bl, 0, c->stream,
-                       static_cast<const S*>(c->pop[c->cur]), c->flags, rhoN, c->obs_res,
-                       c->obs_part, nblk, c->g, P);
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, c->stream, c->obs_part, nblk, O_PERIM,
-                       CGE_NOBS, c->acc_sink, c->acc_sites, c->acc_len, c->obs_res);
-    return check(c, hipGetLastError(), "observable kernels");
+    return check(c,
+                 obs_launch<Q, S, WALLS>(static_cast<const S*>(c->pop[c->cur]), c->flags,
+                                         c->carry, c->obs_part, c->obs_res, c->acc_sink,
+                                         c->acc_sites, c->acc_len, c->g, phys<double>(c),
+                                         c->stream),
+                 "observable kernels");
 }
 
 cge_status observables(cge_ctx* c) { CGE_DISPATCH(c, obs_impl, c); }
+
+// ------------------------------------------------------------ allocation-free observables
+//
+// cge_observables_noalloc keeps the reduction's scratch in this file-scope array instead of a
+// context's.  Each device holds its own copy from the moment the library's code is loaded on
+// it until the process ends.  Host code never passes the array's name to a kernel (that is a
+// host-side stand-in): the device address is looked up once per device and kept below.
+constexpr size_t kNoallocScratch = 64ull << 20;  // bytes
+constexpr size_t kNoallocRes = 256;             // bytes reserved for res and the result
+static __device__ __align__(256) unsigned char scratch[kNoallocScratch];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first call there)
+static hipError_t scratch_on_current_device(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// res (sums and counts of the reduction) -> the cge_obs fields a state determines
+__global__ void k_obs_noalloc_out(const double* __restrict__ r, double rho_in_r, double sbar,
+                                  cge_obs* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    cge_obs o;
+    o.step = 0;
+    o.site_steps = 0;
+    o.sink_total = 0.0;
+    o.mass_r = r[O_MASS_R];
+    o.mass_b = r[O_MASS_B];
+    o.n_negative = (long long)r[O_NNEG];
+    o.p_in = r[O_NIN] > 0 ? r[O_PIN] / r[O_NIN] : 0.0;
+    o.p_out = r[O_NOUT] > 0 ? r[O_POUT] / r[O_NOUT] : 0.0;
+    o.n_sites = (long long)r[O_NSITES];
+    o.max_u = r[O_MAXU];
+    o.max_rho_r = r[O_MAXRR];
+    o.perim_grad = r[O_PERIM];
+    o.v_half = (long long)r[O_VHALF];
+    o.v_mass = o.mass_r / rho_in_r;
+    o.perim_sites = (double)o.n_sites / sbar;
+    *out = o;
+}
+
+template <int Q, typename S, bool WALLS>
+static hipError_t noalloc_impl(const cge_params* p, const void* pop, const uint8_t* flags,
+                               const void* carry, unsigned char* base, hipStream_t stream,
+                               cge_obs* out) {
+    cge_ctx tmp;  // host-side constants only: phys() reads the parameters and lattice
+    tmp.p = *p;
+    tmp.Q = Q;
+    const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+    double* res = reinterpret_cast<double*>(base);
+    double* part = reinterpret_cast<double*>(base + kNoallocRes);
+    hipError_t e = obs_launch<Q, S, WALLS>(static_cast<const S*>(pop), flags, carry, part, res,
+                                           nullptr, nullptr, 0, g, phys<double>(&tmp), stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_obs_noalloc_out, dim3(1), dim3(64), 0, stream, res, p->rho_in[0],
+                       p->sbar, out);
+    return hipGetLastError();
+}
+
+size_t noalloc_limit_bytes() { return kNoallocScratch - kNoallocRes; }
+size_t noalloc_need_bytes(const cge_params* p) {
+    const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+    return obs_scratch_bytes(g);
+}
+
+cge_status observables_noalloc(const cge_params* p, const void* pop, const unsigned char* carry,
+                               const unsigned char* flags, void* hip_stream, cge_obs* out) {
+    if (noalloc_need_bytes(p) > noalloc_limit_bytes()) return CGE_ESCRATCH;
+    void* base = nullptr;
+    if (scratch_on_current_device(&base) != hipSuccess) return CGE_EDEVICE;
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    unsigned char* b = static_cast<unsigned char*>(base);
+    const int key = p->lattice * 10 + p->precision;
+    const bool w = flags != nullptr;
+    hipError_t e;
+    switch (key) {
+        case 90: e = w ? noalloc_impl<9, double, true>(p, pop, flags, carry, b, st, out)
+                       : noalloc_impl<9, double, false>(p, pop, flags, carry, b, st, out); break;
+        case 91: e = w ? noalloc_impl<9, float, true>(p, pop, flags, carry, b, st, out)
+                       : noalloc_impl<9, float, false>(p, pop, flags, carry, b, st, out); break;
+        case 92: e = w ? noalloc_impl<9, _Float16, true>(p, pop, flags, carry, b, st, out)
+                       : noalloc_impl<9, _Float16, false>(p, pop, flags, carry, b, st, out); break;
+        case 190: e = w ? noalloc_impl<19, double, true>(p, pop, flags, carry, b, st, out)
+                        : noalloc_impl<19, double, false>(p, pop, flags, carry, b, st, out); break;
+        case 191: e = w ? noalloc_impl<19, float, true>(p, pop, flags, carry, b, st, out)
+                        : noalloc_impl<19, float, false>(p, pop, flags, carry, b, st, out); break;
+        case 192: e = w ? noalloc_impl<19, _Float16, true>(p, pop, flags, carry, b, st, out)
+                        : noalloc_impl<19, _Float16, false>(p, pop, flags, carry, b, st, out); break;
+        default: return CGE_EUNSUPPORTED;
+    }
+    return e == hipSuccess ? CGE_OK : CGE_EDEVICE;
+}
 
 }  // namespace cge

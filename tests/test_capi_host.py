@@ -81,6 +81,26 @@ def test_null_arguments():
     L.cge_destroy(None)
 
 
+def test_noalloc_observables_reject_on_the_host():
+    """cge_observables_noalloc checks its parameters, pointers and the size of its static
+    scratch before any device work (the pointers here are never dereferenced)."""
+    L = cgevap.lib()
+    fake = C.c_void_p(256)
+    big = cgevap.make_params(inputs.workload("sphere3d", shape=(4, 4, 4))["params"], "fp32s")
+    big.nx = big.ny = big.nz = 200           # 8e6 nodes + partials: beyond the 64 MiB
+    assert L.cge_observables_noalloc(C.byref(big), fake, fake, None, None, fake) == \
+        cgevap.ESCRATCH
+    ok = cgevap.make_params(inputs.workload("sphere3d", shape=(4, 4, 4))["params"], "fp32s")
+    ok.nx = ok.ny = ok.nz = 199              # the largest cube that fits; NULL out: EINVAL
+    assert L.cge_observables_noalloc(C.byref(ok), fake, fake, None, None, None) == \
+        cgevap.EINVAL
+    assert L.cge_observables_noalloc(C.byref(ok), None, fake, None, None, fake) == \
+        cgevap.EINVAL
+    assert L.cge_observables_noalloc(C.byref(_params(tau=0.5)), fake, fake, None, None,
+                                     fake) == cgevap.EINVAL
+    assert L.cge_observables_noalloc(None, fake, fake, None, None, fake) == cgevap.EINVAL
+
+
 def test_population_bytes():
     L = cgevap.lib()
     for prec, b in (("fp64", 8), ("fp32s", 4), ("fp16s", 2)):
