@@ -8,9 +8,13 @@
  *     throws.  After an error, cge_last_error(ctx) holds a message (valid until the next
  *     call on that context).  Parameter errors are detected on the host before any device
  *     work, so they are testable without a GPU.
- *   - Large buffers are caller-owned DEVICE pointers (e.g. torch tensors on the GPU);
- *     the library allocates only its own scratch (phase-field work array, reduction
- *     partials) at cge_create and frees it at cge_destroy.
+ *   - Large buffers are caller-owned DEVICE pointers (e.g. torch tensors on the GPU).  A
+ *     context also needs scratch: per-block FP64 partials and small result buffers, which the
+ *     library allocates at context creation and frees at cge_destroy, and large per-node
+ *     scratch (the phase field, the moment and post-collision records of the split step and
+ *     the record form, the fused step's second mask, the observables' phase field, the height
+ *     flux's column sums; cge_scratch_bytes() in all), which cge_create allocates in one
+ *     block and cge_create_with_scratch takes from the caller.
  *   - All device work is enqueued on the HIP stream given at cge_create, in order.
  *     Entry points that return host data (cge_observables, cge_timing) synchronise that
  *     stream; all others are asynchronous.
@@ -139,8 +143,22 @@ typedef struct cge_ctx cge_ctx;
 
 /* Validate parameters, allocate the library scratch on the current HIP device, and attach
  * the HIP stream (hipStream_t passed as void*, NULL = default stream).
- * Errors: CGE_EINVAL (bad parameters; *out untouched), CGE_ENOMEM, CGE_EDEVICE. */
+ * Errors: CGE_EINVAL (bad parameters; *out untouched), CGE_EUNSUPPORTED (a step form that
+ * does not support the parameters), CGE_ENOMEM, CGE_EDEVICE. */
 cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out);
+
+/* Bytes of the large per-node scratch a context of these parameters uses (0 for invalid
+ * parameters): at D3Q19 256^3 about 8 (phase field) + 1 (mask) + 16 (moments) + 56 (records)
+ * + 8 (observables) + 1 (column sums) bytes per node at FP32 storage. */
+size_t cge_scratch_bytes(const cge_params* params);
+
+/* cge_create with the large scratch in a caller-owned device buffer of at least
+ * cge_scratch_bytes() bytes, 256-byte aligned, which must stay valid and unused by others
+ * until cge_destroy (the library never frees it); the library then allocates only its
+ * per-block partials and result buffers.  CGE_EINVAL for a NULL, smaller or misaligned
+ * buffer; otherwise as cge_create. */
+cge_status cge_create_with_scratch(const cge_params* params, void* hip_stream, void* scratch,
+                                   size_t scratch_bytes, cge_ctx** out);
 
 /* Bytes of one population buffer: 2*Q*nx*ny*nz elements of 8 (FP64), 4 (FP32S) or
  * 2 (FP16S) bytes.  Returns 0 for invalid parameters. */
@@ -176,14 +194,33 @@ cge_status cge_init_equilibrium(cge_ctx* ctx, const double* rho_r, const double*
 cge_status cge_set_populations(cge_ctx* ctx, const double* f);
 cge_status cge_get_populations(cge_ctx* ctx, double* f);
 
-/* Raw snapshot of the state in the library's own encoding (bitwise exact round trip): the
- * current population buffer, then the carried site data from the next 256-byte boundary;
- * cge_state_bytes() bytes of device memory at dst / src (256-byte aligned).  Counters are not
- * included (see cge_set_counters).  Used for checkpoint / resume and by the adjoint's
- * recomputation segments. */
+/* Snapshot of the state in the library's own encoding (bitwise exact round trip), for
+ * checkpoint / resume; cge_state_bytes() bytes of device memory at dst / src (256-byte
+ * aligned).  Layout:
+ *   [0, pb)            the current population buffer, pb = cge_population_bytes()
+ *   [coff, coff + cb)  the carried site data, coff = pb rounded up to 256, cb its size
+ *   [toff, toff + 32)  an integrity trailer, toff = coff + cb rounded up to 256: four
+ *                      little-endian uint64: magic 0x5441545356454743, a fingerprint of the
+ *                      parameters, pb + cb, and a checksum
+ * checksum = sum mod 2^64, over the 8-byte little-endian words w_i of the populations and then
+ * of the site data (each region zero-padded to a multiple of 8 bytes; i counts on from the
+ * first region into the second), of m(w_i XOR (i * 0xD6E8FEB86659FD93)), where m(z) is the
+ * splitmix64 step: z += 0x9E3779B97F4A7C15; z = (z ^ z>>30) * 0xBF58476D1CE4E5B9;
+ * z = (z ^ z>>27) * 0x94D049BB133111EB; m = z ^ z>>31.
+ * fingerprint = 64-bit FNV-1a over the bytes of int32 lattice, nx, ny, nz, precision,
+ * site_rule, then float64 rho_in[0], rho_in[1], then int32 1 (format version).
+ * cge_save_state writes all of it (asynchronously).  cge_load_state first recomputes the
+ * checksum of src on the device and compares the trailer (synchronising the stream), and
+ * returns CGE_ECHECKPOINT, leaving the state untouched, for a missing trailer, a trailer of
+ * other parameters or a checksum mismatch.  Counters are not included (see
+ * cge_set_counters). */
 size_t cge_state_bytes(const cge_params* params);
 cge_status cge_save_state(cge_ctx* ctx, void* dst);
 cge_status cge_load_state(cge_ctx* ctx, const void* src);
+
+/* The same integrity check on a snapshot copied to HOST memory (cge_state_bytes() bytes), with
+ * no device work: CGE_OK, CGE_ECHECKPOINT, or CGE_EINVAL for bad parameters or NULL. */
+cge_status cge_verify_state(const cge_params* params, const void* snapshot);
 
 /* Adjoint (reverse mode) of nsteps steps, for the site rules GRAD_GT (sites held at those of
  * the forward run) and SOFT, with or without solid nodes (the transposes of the halfway
@@ -213,7 +250,8 @@ cge_status cge_load_state(cge_ctx* ctx, const void* src);
  *                      the context holds the state after nsteps again, with its step counter
  *                      and sink bookkeeping.
  * Errors: CGE_EINVAL (missing buffers, nsteps or K < 1), CGE_EUNSUPPORTED (PHASE_LT rule,
- * height flux or outlets on), CGE_EDEVICE. */
+ * height flux or outlets on), CGE_ECHECKPOINT (a checkpoint fails the integrity check of
+ * cge_load_state; the context then holds an intermediate state: load one), CGE_EDEVICE. */
 size_t cge_adjoint_bytes(const cge_params* params);
 size_t cge_segment_bytes(const cge_params* params, int K);
 cge_status cge_forward_ckpt(cge_ctx* ctx, long long nsteps, int K, void* const* ckpt);
@@ -237,8 +275,7 @@ cge_status cge_set_site_threshold(cge_ctx* ctx, double gamma, double kappa);
  * column's fluid nodes of the red fraction (1 + rho^N)/2 of the current pre-sink state.  The
  * field depends on the current state only, so resumed runs take the same fluxes.  every <= 0
  * switches it off (the field keeps its last values).  Each refresh reads the whole state once.
- * The first call with every > 0 allocates a library-owned buffer of column sums (8 bytes per
- * 8 nodes of a column), freed by cge_destroy; CGE_ENOMEM if that fails.
+ * The column sums (8 bytes per 8 nodes of a column) live in the context's scratch.
  * Needs a bound flux field (CGE_ESTATE otherwise); CGE_EINVAL unless K > 0, h_scale > 0 and
  * phi_s is finite.  The adjoint does not differentiate through the heights: cge_forward_ckpt
  * and cge_backward return CGE_EUNSUPPORTED while it is on. */

@@ -20,9 +20,9 @@ SITE_RULES = {"grad": 0, "phase": 1, "soft": 2}
 ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
 
 # every symbol the header declares
-EXPORTS = ["cge_create", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
+EXPORTS = ["cge_create", "cge_scratch_bytes", "cge_create_with_scratch", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
            "cge_set_populations", "cge_get_populations", "cge_state_bytes", "cge_save_state",
-           "cge_load_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
+           "cge_load_state", "cge_verify_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
            "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_outlet",
            "cge_set_counters", "cge_set_zchunk",
            "cge_step", "cge_observables", "cge_observables_noalloc", "cge_fields", "cge_set_timing", "cge_timing",
@@ -71,6 +71,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, dp, P = C.c_void_p, C.POINTER(C.c_double), C.POINTER
         L.cge_create.argtypes = [P(CgeParams), vp, P(vp)]
+        L.cge_scratch_bytes.argtypes = [P(CgeParams)]
+        L.cge_scratch_bytes.restype = C.c_size_t
+        L.cge_create_with_scratch.argtypes = [P(CgeParams), vp, vp, C.c_size_t, P(vp)]
         L.cge_population_bytes.argtypes = [P(CgeParams)]
         L.cge_population_bytes.restype = C.c_size_t
         L.cge_bind.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -81,6 +84,7 @@ def lib():
         L.cge_state_bytes.restype = C.c_size_t
         L.cge_save_state.argtypes = [vp, vp]
         L.cge_load_state.argtypes = [vp, vp]
+        L.cge_verify_state.argtypes = [P(CgeParams), vp]
         L.cge_adjoint_bytes.argtypes = [P(CgeParams)]
         L.cge_adjoint_bytes.restype = C.c_size_t
         L.cge_segment_bytes.argtypes = [P(CgeParams), C.c_int]
@@ -177,7 +181,12 @@ class Simulation:
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
             ctx = C.c_void_p()
-            st = L.cge_create(C.byref(cp), C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+            # the context's large scratch is a torch allocation (caller-owned, so torch's
+            # caching allocator reuses it across simulations)
+            sb = L.cge_scratch_bytes(C.byref(cp))
+            self.scratch = torch.empty(sb, dtype=torch.uint8, device=self.device)
+            st = L.cge_create_with_scratch(C.byref(cp), C.c_void_p(self.stream.cuda_stream),
+                                           _ptr(self.scratch), C.c_size_t(sb), C.byref(ctx))
             if st != OK:
                 raise CgeError(st, "cge_create failed")
             self._ctx = ctx
@@ -255,6 +264,8 @@ class Simulation:
         return out
 
     def load_state(self, snap):
+        """Load a snapshot; CgeError with status ECHECKPOINT if its integrity trailer does not
+        match (the state is then unchanged)."""
         self._check(lib().cge_load_state(self._ctx, _ptr(snap)))
 
     def reset_sites(self):
@@ -339,6 +350,16 @@ class Simulation:
 
     def kernel_name(self):
         return lib().cge_kernel_name(self._ctx).decode()
+
+
+def verify_state(params, precision, snapshot):
+    """Integrity check of a snapshot held in host memory (bytes-like or a CPU uint8 tensor /
+    numpy array): returns the status (OK or ECHECKPOINT)."""
+    a = np.ascontiguousarray(np.frombuffer(bytes(snapshot), dtype=np.uint8)
+                             if isinstance(snapshot, (bytes, bytearray)) else
+                             np.asarray(snapshot, dtype=np.uint8))
+    cp = make_params(params, precision)
+    return lib().cge_verify_state(C.byref(cp), a.ctypes.data_as(C.c_void_p))
 
 
 def copy_probe(dst, src, nbytes, stream):

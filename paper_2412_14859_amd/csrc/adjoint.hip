@@ -683,6 +683,7 @@ size_t cge_segment_bytes(const cge_params* p, int K) {
 }
 
 cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ckpt) {
+    TraceRange trace_("cge_forward_ckpt");
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps < 1 || K < 1 || !ckpt) return fail(c, CGE_EINVAL, "nsteps >= 1, K >= 1, ckpt");
@@ -705,6 +706,7 @@ cge_status cge_forward_ckpt(cge_ctx* c, long long nsteps, int K, void* const* ck
 cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, void* seg,
                         void* work, const double* dL_drhoN, const double* dL_drho,
                         double* grad_phi, double* grad_phi_t, double* grad_gamma) {
+    TraceRange trace_("cge_backward");
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (nsteps < 1 || K < 1 || !ckpt || !seg || !work || (!dL_drhoN && !dL_drho) || !grad_phi)
@@ -749,6 +751,7 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
     for (long long j = nseg - 1; j >= 0; --j) {
         const long long n0 = j * K;
         const long long len = nsteps - n0 < K ? nsteps - n0 : K;
+        TraceRange seg_trace_("adjoint segment (recompute, reverse steps)");
         if (cge_status s = cge_load_state(c, ckpt[j])) return s;
         c->step = step0 - nsteps + n0;  // the recomputed steps draw the same rounding keys
         if (unit) {
@@ -767,7 +770,7 @@ cge_status cge_backward(cge_ctx* c, long long nsteps, int K, void* const* ckpt, 
             }
         } else {
             for (long long t = 0; t < len; ++t) {  // states n0 .. n0 + len - 1
-                if (cge_status s = cge_save_state(c, segb + t * sb)) return s;
+                if (cge_status s = save_state(c, segb + t * sb, false)) return s;
                 if (t + 1 < len)
                     if (cge_status s = cge_step(c, 1)) return s;
             }

@@ -56,7 +56,8 @@ Phys<M> phys(const cge_ctx* c) {
 template Phys<float> phys<float>(const cge_ctx*);
 template Phys<double> phys<double>(const cge_ctx*);
 
-void timing_begin(cge_ctx* c) {
+void timing_begin(cge_ctx* c, const char* step_name) {
+    roctxRangePushA(step_name);
     if (!c->timing) return;
     if (c->ev_used + 2 > c->ev.size()) {
         for (int k = 0; k < 2; ++k) {
@@ -79,6 +80,7 @@ static void timing_fold(cge_ctx* c) {
 }
 
 void timing_end(cge_ctx* c) {
+    roctxRangePop();
     if (!c->timing || c->ev_used + 2 > c->ev.size()) return;
     (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
     c->ev_used += 2;
@@ -160,9 +162,53 @@ size_t cge_population_bytes(const cge_params* p) {
     return 2ull * p->lattice * (size_t)p->nx * p->ny * p->nz * elem_bytes(p->precision);
 }
 
-cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out) {
+// Large scratch of a context, carved from one block in this order (each part 256-aligned):
+// the phase field (N values of the arithmetic type), the fused step's second mask (N bytes,
+// D3Q19), the split step's moment record (unit tau), the record form's post-collision records
+// (where the record form may run), the observables' partials and FP64 phase field, and the
+// height flux's column sums.
+struct ScratchPlan {
+    size_t rhoN = 0, carry2 = 0, mom = 0, rec = 0, obs = 0, hf = 0, total = 0;
+    bool has_rec = false;
+};
+
+static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static ScratchPlan scratch_plan(const cge_params* p) {
+    ScratchPlan s;
+    const int Q = p->lattice;
+    const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+    const bool unit = p->tau[0] == 1.0 && p->tau[1] == 1.0;
+    // records where the record form may run: selected, or chosen by AUTO (unit tau, D3Q19,
+    // FP64 or FP32 storage)
+    const bool rec = unit && (p->kernel == CGE_KERNEL_RECORD ||
+                              (p->kernel == CGE_KERNEL_AUTO && p->precision != CGE_FP16S && Q == 19));
+    const size_t mbytes = p->precision == CGE_FP16S ? 4 : 8;  // the widest use of the field
+    const dim3 gr = node_grid(g);
+    const size_t nblk = (size_t)gr.x * gr.y * gr.z;
+    size_t off = 0;
+    auto take = [&](size_t& at, size_t bytes) {
+        at = off;
+        off += up256(bytes);
+    };
+    take(s.rhoN, g.N * mbytes);
+    take(s.carry2, Q == 19 ? (size_t)g.N : 0);
+    take(s.mom, unit ? split_scratch_bytes(p) : 0);
+    take(s.rec, rec ? record_bytes(p) : 0);
+    s.has_rec = rec;
+    take(s.obs, (CGE_NOBS * nblk + (size_t)g.N) * sizeof(double));
+    take(s.hf, height_partial_bytes(g, Q));
+    s.total = off;
+    return s;
+}
+
+static cge_status create_ctx(const cge_params* params, void* hip_stream, void* scratch,
+                             size_t scratch_bytes, cge_ctx** out) {
     if (!out) return CGE_EINVAL;
     if (validate(params)) return CGE_EINVAL;
+    const ScratchPlan plan = scratch_plan(params);
+    if (scratch && scratch_bytes < plan.total) return CGE_EINVAL;
+    if (scratch && ((uintptr_t)scratch & 255)) return CGE_EINVAL;
     cge_ctx* c = new (std::nothrow) cge_ctx();
     if (!c) return CGE_ENOMEM;
     c->p = *params;
@@ -177,11 +223,11 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
         return CGE_EDEVICE;
     }
     // the fused step needs D3Q19 and no solid nodes (the latter is known at cge_bind); the
-    // split step needs unit relaxation times
+    // split step needs unit relaxation times; the record form keeps FP32 records between the
+    // steps of a call, so at FP16 storage only a call's last step would store half precision:
+    // refused rather than mislabelled
     const bool unit = split_supported(c);
     const bool soft = params->site_rule == CGE_SITE_SOFT;
-    // the record form keeps FP32 records between the steps of a call, so at FP16 storage
-    // only a call's last step would store half precision: refused rather than mislabelled
     if ((params->kernel == CGE_KERNEL_FUSED && (c->Q != 19 || soft)) ||
         ((params->kernel == CGE_KERNEL_SPLIT || params->kernel == CGE_KERNEL_RECORD) && !unit) ||
         (params->kernel == CGE_KERNEL_RECORD && params->precision == CGE_FP16S)) {
@@ -189,28 +235,32 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
         return CGE_EUNSUPPORTED;
     }
     c->kernel = CGE_KERNEL_TWOPASS;  // resolved at cge_bind
+    if (scratch) {
+        c->scratch = scratch;
+    } else {
+        if (hipMalloc(&c->scratch, plan.total) != hipSuccess) {
+            c->scratch = nullptr;
+            delete c;
+            return CGE_ENOMEM;
+        }
+        c->scratch_owned = true;
+    }
+    char* base = static_cast<char*>(c->scratch);
+    c->rhoN = base + plan.rhoN;
+    c->carry2 = c->Q == 19 ? reinterpret_cast<unsigned char*>(base + plan.carry2) : nullptr;
     // the moment record also serves the checkpointed forward run of the adjoint at unit tau
-    const bool need_mom = unit;
-    // records for the record form, which auto selects at unit tau for D3Q19 with FP64 or
-    // FP32 storage
-    const bool need_rec =
-        unit && (params->kernel == CGE_KERNEL_RECORD ||
-                 (params->kernel == CGE_KERNEL_AUTO && params->precision != CGE_FP16S &&
-                  c->Q == 19));
-    const size_t mbytes = params->precision == CGE_FP16S ? 4 : 8;  // arithmetic type (the
-                                                                   // widest use of rhoN)
+    c->mom = unit ? base + plan.mom : nullptr;
+    c->rec = plan.has_rec ? base + plan.rec : nullptr;
+    c->obs_part = reinterpret_cast<double*>(base + plan.obs);
+    c->hf_part = base + plan.hf;
     c->acc_len = twopass_blocks(c);
     if (c->Q == 19 && fused_blocks(c) > c->acc_len) c->acc_len = fused_blocks(c);
     c->obs_blocks = twopass_blocks(c);
-    bool ok = (c->Q != 19 || hipMalloc(&c->carry2, c->g.N) == hipSuccess) &&
-              (!need_mom || hipMalloc(&c->mom, split_scratch_bytes(params)) == hipSuccess) &&
-              (!need_rec || hipMalloc(&c->rec, record_bytes(params)) == hipSuccess) &&
-              hipMalloc(&c->rhoN, c->g.N * mbytes) == hipSuccess &&
-              hipMalloc(&c->acc_sink, c->acc_len * sizeof(double)) == hipSuccess &&
+    // small library-owned buffers: per-block sink partials, reduction results
+    bool ok = hipMalloc(&c->acc_sink, c->acc_len * sizeof(double)) == hipSuccess &&
               hipMalloc(&c->acc_sites, c->acc_len * sizeof(long long)) == hipSuccess &&
-              hipMalloc(&c->obs_part, (CGE_NOBS * c->obs_blocks + c->g.N) * sizeof(double)) ==
-                  hipSuccess &&
-              hipMalloc(&c->obs_res, (CGE_NOBS + 2) * sizeof(double)) == hipSuccess;
+              hipMalloc(&c->obs_res, (CGE_NOBS + 2) * sizeof(double)) == hipSuccess &&
+              hipMalloc(&c->ck, 32) == hipSuccess;
     if (!ok) {
         cge_destroy(c);
         return CGE_ENOMEM;
@@ -223,6 +273,18 @@ cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out)
     }
     *out = c;
     return CGE_OK;
+}
+
+size_t cge_scratch_bytes(const cge_params* p) { return validate(p) ? 0 : scratch_plan(p).total; }
+
+cge_status cge_create(const cge_params* params, void* hip_stream, cge_ctx** out) {
+    return create_ctx(params, hip_stream, nullptr, 0, out);
+}
+
+cge_status cge_create_with_scratch(const cge_params* params, void* hip_stream, void* scratch,
+                                   size_t scratch_bytes, cge_ctx** out) {
+    if (!scratch) return CGE_EINVAL;
+    return create_ctx(params, hip_stream, scratch, scratch_bytes, out);
 }
 
 cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
@@ -265,6 +327,7 @@ static cge_status zero_counters(cge_ctx* c) {
 
 cge_status cge_init_equilibrium(cge_ctx* c, const double* rho_r, const double* rho_b,
                                 const double* u) {
+    TraceRange trace_("cge_init_equilibrium");
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (!rho_r || !rho_b) return fail(c, CGE_EINVAL, "rho_r and rho_b required");
@@ -289,40 +352,27 @@ cge_status cge_get_populations(cge_ctx* c, double* f) {
     return get_populations(c, f);
 }
 
-// the carried site data starts at the first 256-byte boundary after the populations
-static size_t carry_offset(const cge_params* p) {
-    return (cge_population_bytes(p) + 255) & ~(size_t)255;
-}
-
-size_t cge_state_bytes(const cge_params* p) {
-    const size_t pb = cge_population_bytes(p);
-    return pb ? carry_offset(p) + carry_bytes(p) : 0;
-}
+size_t cge_state_bytes(const cge_params* p) { return validate(p) ? 0 : state_bytes(p); }
 
 cge_status cge_save_state(cge_ctx* c, void* dst) {
+    TraceRange trace_("cge_save_state");
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (!dst) return fail(c, CGE_EINVAL, "dst is NULL");
-    const size_t pb = cge_population_bytes(&c->p);
-    if (cge_status s = check(c, hipMemcpyAsync(dst, c->pop[c->cur], pb, hipMemcpyDeviceToDevice,
-                                               c->stream), "state save"))
-        return s;
-    return check(c, hipMemcpyAsync(static_cast<char*>(dst) + carry_offset(&c->p), c->carry,
-                                   carry_bytes(&c->p), hipMemcpyDeviceToDevice, c->stream),
-                 "state save");
+    return save_state(c, dst, true);
 }
 
 cge_status cge_load_state(cge_ctx* c, const void* src) {
+    TraceRange trace_("cge_load_state");
     if (!c) return CGE_EINVAL;
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
     if (!src) return fail(c, CGE_EINVAL, "src is NULL");
-    const size_t pb = cge_population_bytes(&c->p);
-    if (cge_status s = check(c, hipMemcpyAsync(c->pop[c->cur], src, pb, hipMemcpyDeviceToDevice,
-                                               c->stream), "state load"))
-        return s;
-    return check(c, hipMemcpyAsync(c->carry, static_cast<const char*>(src) + carry_offset(&c->p),
-                                   carry_bytes(&c->p), hipMemcpyDeviceToDevice, c->stream),
-                 "state load");
+    return load_state(c, src, true);
+}
+
+cge_status cge_verify_state(const cge_params* p, const void* snapshot) {
+    if (validate(p) || !snapshot) return CGE_EINVAL;
+    return verify_state_host(p, snapshot);
 }
 
 cge_status cge_reset_sites(cge_ctx* c) {
@@ -354,11 +404,6 @@ cge_status cge_set_height_flux(cge_ctx* c, double phi_s, double K, double h_scal
         if (!c->phi_field) return fail(c, CGE_ESTATE, "the height flux needs a bound flux field");
         if (!is_fin(phi_s) || !is_fin(K) || !(K > 0.0) || !is_fin(h_scale) || !(h_scale > 0.0))
             return fail(c, CGE_EINVAL, "height flux needs finite phi_s, K > 0, h_scale > 0");
-        if (!c->hf_part &&
-            hipMalloc(&c->hf_part, height_partial_bytes(c->g, c->Q)) != hipSuccess) {
-            c->hf_part = nullptr;
-            return fail(c, CGE_ENOMEM, "height flux scratch");
-        }
         c->hf_phi = phi_s;
         c->hf_K = K;
         c->hf_hs = h_scale;
@@ -404,6 +449,7 @@ static cge_status run_steps(cge_ctx* c, long long nsteps) {
 }
 
 cge_status cge_step(cge_ctx* c, long long nsteps) {
+    TraceRange trace_("cge_step");
     if (!c) return CGE_EINVAL;
     if (nsteps < 0) return fail(c, CGE_EINVAL, "nsteps must be >= 0");
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
@@ -430,6 +476,7 @@ cge_status cge_step(cge_ctx* c, long long nsteps) {
 }
 
 cge_status cge_observables(cge_ctx* c, cge_obs* out) {
+    TraceRange trace_("cge_observables");
     if (!c) return CGE_EINVAL;
     if (!out) return fail(c, CGE_EINVAL, "out is NULL");
     if (!c->bound) return fail(c, CGE_ESTATE, "cge_bind first");
@@ -462,6 +509,7 @@ cge_status cge_observables(cge_ctx* c, cge_obs* out) {
 
 cge_status cge_observables_noalloc(const cge_params* p, const void* pop, const unsigned char* carry,
                                    const unsigned char* flags, void* hip_stream, cge_obs* out) {
+    TraceRange trace_("cge_observables_noalloc");
     if (validate(p) || !pop || !carry || !out) return CGE_EINVAL;
     return observables_noalloc(p, pop, carry, flags, hip_stream, out);
 }
@@ -537,15 +585,11 @@ const char* cge_last_error(const cge_ctx* c) { return c ? c->err.c_str() : "NULL
 void cge_destroy(cge_ctx* c) {
     if (!c) return;
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-    (void)hipFree(c->rhoN);
-    (void)hipFree(c->hf_part);
-    (void)hipFree(c->carry2);
-    (void)hipFree(c->mom);
-    (void)hipFree(c->rec);
+    if (c->scratch_owned) (void)hipFree(c->scratch);
     (void)hipFree(c->acc_sink);
     (void)hipFree(c->acc_sites);
-    (void)hipFree(c->obs_part);
     (void)hipFree(c->obs_res);
+    (void)hipFree(c->ck);
     delete c;
 }
 

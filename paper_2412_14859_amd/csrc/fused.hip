@@ -342,7 +342,7 @@ static cge_status fused_impl(cge_ctx* c, long long nsteps) {
             const S* src = static_cast<const S*>(c->pop[c->cur]);
             S* dst = static_cast<S*>(c->pop[1 - c->cur]);
             const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
-            timing_begin(c);
+            timing_begin(c, "fused step");
             if (unit)
                 hipLaunchKernelGGL((k_fused<Q, S, M, true>), dim3((unsigned)fs.nb),
                                    dim3(kFTX * kFTY), 0, c->stream, src, dst, mask[m],

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
 #include <vector>
@@ -38,16 +39,19 @@ struct cge_ctx {
     double* acc_sink = nullptr;     // per-block cumulative sink (FP64)
     long long* acc_sites = nullptr; // per-block cumulative site count
     long long acc_len = 0;
-    double* obs_part = nullptr;     // [CGE_NOBS][obs_blocks]
+    double* obs_part = nullptr;     // [CGE_NOBS][obs_blocks], then the FP64 phase field (N)
     long long obs_blocks = 0;
     double* obs_res = nullptr;      // [CGE_NOBS + 2] final values (device)
+    unsigned char* ck = nullptr;    // 32 bytes: the checksum of a state being loaded
     // blue pressure outlets on the end planes of the last axis
     int out_lo = 0, out_hi = 0;
     double out_rho = 1.0;
     // height-dependent flux (active when hf_every > 0)
     long long hf_every = 0;
     double hf_phi = 0.0, hf_K = 1.0, hf_hs = 1.0;
-    void* hf_part = nullptr;  // per-chunk column sums of the refresh (library-owned)
+    void* hf_part = nullptr;  // per-chunk column sums of the refresh (in the scratch block)
+    void* scratch = nullptr;  // the block the large scratch buffers are carved from
+    bool scratch_owned = false;  // allocated by cge_create (else the caller's)
     // counters
     long long step = 0;
     long long sites_offset = 0;
@@ -93,6 +97,14 @@ cge_status reset_sites(cge_ctx* c);
 template <typename R>
 cge_status wet_field(cge_ctx* c, R* rhoN);
 
+// saved states (state.hip): layout, copy with or without the integrity trailer, checks
+size_t state_carry_offset(const cge_params* p);
+size_t state_trailer_offset(const cge_params* p);
+size_t state_bytes(const cge_params* p);
+cge_status save_state(cge_ctx* c, void* dst, bool seal);
+cge_status load_state(cge_ctx* c, const void* src, bool verify);
+cge_status verify_state_host(const cge_params* p, const void* snapshot);
+
 // state conversion
 cge_status init_equilibrium(cge_ctx* c, const double* rr, const double* rb, const double* u);
 cge_status set_populations(cge_ctx* c, const double* f);
@@ -116,9 +128,18 @@ cge_status observables_noalloc(const cge_params* p, const void* pop, const unsig
 
 cge_status copy_probe(void* dst, const void* src, size_t nbytes, hipStream_t s);
 
-// timing helpers around step-kernel launches
-void timing_begin(cge_ctx* c);
+// timing helpers around the kernel launches of one step; they also open and close a roctx range
+// named after the step form (rocprofv3 --marker-trace shows the steps and their kernels)
+void timing_begin(cge_ctx* c, const char* step_name);
 void timing_end(cge_ctx* c);
+
+// roctx range over a scope (an entry point, a segment of the adjoint)
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // launch shape of the one-thread-per-node kernels: (bx, 1, 1) blocks, bx a multiple of 64
 inline dim3 node_block(const Geo& g) {

@@ -631,7 +631,7 @@ static cge_status split_one(cge_ctx* c, const void* carry_in, void* carry_out, v
     const S* src = static_cast<const S*>(c->pop[c->cur]);
     S* dst = static_cast<S*>(c->pop[1 - c->cur]);
     const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
-    timing_begin(c);
+    timing_begin(c, "split step");
     hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
                        carry_in, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
     if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
@@ -686,7 +686,7 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
     const S* src = static_cast<const S*>(c->pop[c->cur]);
     S* dst = static_cast<S*>(c->pop[1 - c->cur]);
     const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
-    timing_begin(c);
+    timing_begin(c, first ? "record step (from populations)" : (last ? "record step (to populations)" : "record step"));
     if (first)
         hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
                            c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);

@@ -116,7 +116,7 @@ static cge_status twopass_impl(cge_ctx* c, long long nsteps) {
         const S* src = static_cast<const S*>(c->pop[c->cur]);
         S* dst = static_cast<S*>(c->pop[1 - c->cur]);
         const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
-        timing_begin(c);
+        timing_begin(c, "two-pass step");
         hipLaunchKernelGGL((k_phase<Q, S, M, WALLS, MomT<S>>), gr, bl, 0, c->stream, src,
                            c->flags, c->carry, c->phi_field, rhoN, c->g, P, 1);
         if (WALLS)

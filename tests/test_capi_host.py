@@ -101,6 +101,36 @@ def test_noalloc_observables_reject_on_the_host():
     assert L.cge_observables_noalloc(None, fake, fake, None, None, fake) == cgevap.EINVAL
 
 
+def test_scratch_plan_and_caller_scratch_checks():
+    """cge_scratch_bytes sizes the large per-node scratch (records only where the record form
+    may run); cge_create_with_scratch refuses a missing, small or misaligned buffer before any
+    device work."""
+    L = cgevap.lib()
+    w = inputs.workload("sphere3d", shape=(8, 8, 64))["params"]
+    n = 8 * 8 * 64
+    sizes = {}
+    for prec in ("fp64", "fp32s", "fp16s"):
+        for kernel in ("auto", "split", "twopass"):
+            cp = cgevap.make_params(w, prec, kernel)
+            sizes[prec, kernel] = L.cge_scratch_bytes(C.byref(cp))
+            assert sizes[prec, kernel] >= n * (4 + 8), (prec, kernel)
+    # the record form's 14 values per node (FP32 records, rows of 64 nodes: no padding here)
+    assert sizes["fp32s", "auto"] - sizes["fp32s", "split"] == 14 * 4 * n
+    assert sizes["fp64", "auto"] - sizes["fp64", "split"] == 14 * 8 * n
+    assert sizes["fp16s", "auto"] == sizes["fp16s", "split"]
+    assert L.cge_scratch_bytes(C.byref(_params(nx=0))) == 0
+    cp = cgevap.make_params(w, "fp32s")
+    need = L.cge_scratch_bytes(C.byref(cp))
+    ctx = C.c_void_p()
+    fake = C.c_void_p(1 << 20)
+    assert L.cge_create_with_scratch(C.byref(cp), None, None, need, C.byref(ctx)) == cgevap.EINVAL
+    assert L.cge_create_with_scratch(C.byref(cp), None, fake, need - 1, C.byref(ctx)) == \
+        cgevap.EINVAL
+    assert L.cge_create_with_scratch(C.byref(cp), None, C.c_void_p((1 << 20) + 8), need,
+                                     C.byref(ctx)) == cgevap.EINVAL
+    assert ctx.value is None
+
+
 def test_population_bytes():
     L = cgevap.lib()
     for prec, b in (("fp64", 8), ("fp32s", 4), ("fp16s", 2)):
