@@ -5,10 +5,12 @@ unit density ratio, tau = 1, sigma = 4A/9 with A = 5e-4, beta = 0.7, phi = 1e-5,
 Gamma = 0.305, Sbar = 3; populations in FP32 shifted storage.  A step is one full time
 step (sink, sites, moments, gradient, collision, perturbation, recolouring, streaming).
 
-Prints one JSON line: MLUPS (whole job), ms/step, the roofline of the step kernel
-(algorithmic bytes per launch / average launch time measured with HIP events on the
-stream the library launches on), FP64 and FP16S legs, and the FP64 CPU oracle timed on a
-bounded sample of the same workload (cpu_baseline).
+Prints one JSON line: MLUPS (whole job), ms/step, the roofline of the dominant kernel
+(its algorithmic bytes per launch / its average launch time, measured with HIP events on the
+stream the library launches on), FP64 and FP16S legs, and the FP64 CPU oracle timed on
+bounded samples (cpu_baseline).  Flags run the other configurations instead (C2: D2Q9 1024^2
+film and ellipse, FP64 against FP32 storage; C4: the D3Q19 384x384x192 sessile drop) and the
+validation benchmarks.
 """
 import argparse
 import json
@@ -29,47 +31,70 @@ def algorithmic_bytes_per_node(Q, precision, walls=False, phi_field=False):
     return 2 * Q * 2 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
 
 
-def record_bytes_per_node(precision, walls=False, phi_field=False):
-    """What the record form stores between steps: the 14-value post-collision record read
-    once and written once (FP64 at FP64 storage, FP32 otherwise), plus the site data, the
-    flux field and the solid flag as above."""
-    elem = 8 if precision == "fp64" else 4
-    return 2 * 14 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
-
-
 STEP_KERNELS = {"k_collide": ("k_phase+k_collide", "twopass"), "k_fused": ("k_fused", "fused"),
                 "k_finish": ("k_moments+k_finish", "split"),
                 "k_pull_record": ("k_pull_record+k_finish_record", "record")}
-# source file of each step form (the record form's kernels live beside the split form's)
-FORM_FILE = {"twopass": "twopass", "fused": "fused", "split": "split", "record": "split",
-             "adjoint": "adjoint"}
+# the pass kernels of each step form (timed one by one)
+PASS_KERNELS = ("k_moments", "k_finish", "k_finish_tile", "k_pull_record_zm", "k_pull_record",
+                "k_finish_record", "k_phase", "k_collide", "k_fused")
+# source files of each kernel's launch (the record form's kernels live beside the split form's)
+KERNEL_FILE = {"k_moments": "split", "k_finish": "split", "k_finish_tile": "split",
+               "k_pull_record_zm": "split", "k_pull_record": "split", "k_finish_record": "split",
+               "k_phase": "twopass", "k_collide": "twopass", "k_fused": "fused"}
 
 
-def kernel_sources(tag):
-    """The files a step form's kernels and launches are compiled from."""
+def kernel_sources(kernel):
+    """The files a kernel and its launch are compiled from."""
     csrc = os.path.join(ROOT, "paper_2412_14859_amd", "csrc")
-    return [os.path.join(csrc, f) for f in (f"{FORM_FILE[tag]}.hip", "node.hpp", "lattice.hpp",
-                                            "internal.hpp")] + \
+    return [os.path.join(csrc, f) for f in (f"{KERNEL_FILE[kernel]}.hip", "node.hpp",
+                                            "lattice.hpp", "internal.hpp")] + \
         [os.path.join(ROOT, "include", "cgevap.h")]
 
 
-def sources_sha(tag):
-    """Hash of a step form's sources, to tell whether a stored counter summary still
-    applies."""
+def sources_sha(kernel):
+    """Hash of a kernel's sources, to tell whether a stored counter summary still applies."""
     import hashlib
     h = hashlib.sha256()
-    for p in kernel_sources(tag):
+    for p in kernel_sources(kernel):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
+def pass_bytes_per_node(kernel, Q, precision, walls=False, phi_field=False):
+    """Algorithmic bytes per node of one launch of a pass kernel: every value it must read
+    and write once.  Pass 1 (k_moments from populations, k_pull_record[_zm] from records,
+    k_phase) reads the state (2 Q populations or the 14-value record), the carried site byte,
+    the flux field and the solid flag when present, and writes the phase field and the moments
+    (k_phase: the phase field only); pass 2 (k_finish, k_finish_tile, k_finish_record,
+    k_collide) reads those, writes the state and the next site byte (k_collide also reads
+    the populations again: its algorithmic bytes are a whole step's).  The phase field and
+    the moments are stored like the state (FP64 next to FP64, else FP32)."""
+    elem = {"fp64": 8, "fp32s": 4, "fp16s": 2}[precision]
+    mom_e = 8 if precision == "fp64" else 4
+    pops = 2 * Q * elem
+    rec = 14 * (8 if precision == "fp64" else 4)
+    extra = (4 if phi_field else 0) + (1 if walls else 0)
+    inter = 5 * mom_e  # rho^N + (drho, j)
+    table = {
+        "k_moments": pops + 1 + extra + inter,
+        "k_pull_record_zm": rec + 1 + extra + inter,
+        "k_pull_record": rec + 1 + extra + inter,
+        "k_finish": inter + pops + 1 + (1 if walls else 0),
+        "k_finish_tile": inter + pops + 1,
+        "k_finish_record": inter + rec + 1 + (1 if walls else 0),
+        "k_phase": pops + 1 + extra + mom_e,
+        "k_collide": pops + 1 + extra + mom_e + pops + 1,
+        "k_fused": pops + 1 + extra + pops + 1,
+    }
+    return table[kernel]
+
+
 def stored_traffic(kernel, n, precision):
-    """HBM bytes per step measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (copy-calibrated)
-    for this kernel and workload, if the summary under profiles/ was taken on the current
-    sources; else None."""
-    tag = STEP_KERNELS[kernel][1]
-    path = os.path.join(ROOT, "profiles", f"{tag}_d3q19_{n}cube_{precision}.txt")
+    """HBM bytes per launch of one kernel measured with rocprofv3 FETCH_SIZE and WRITE_SIZE
+    (each scaled by what it reads for a copy of known size), from the summary under profiles/
+    for this kernel and workload, if it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_d3q19_{n}cube_{precision}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -78,9 +103,9 @@ def stored_traffic(kernel, n, precision):
             if ": " in line and not line.startswith(" "):
                 k, v = line.split(": ", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("sources_sha256") != sources_sha(tag):
+    if kv.get("sources_sha256") != sources_sha(kernel) or "traffic_bytes_per_launch" not in kv:
         return None
-    return float(kv["step_traffic_bytes"])
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def run_leg(workload, precision, steps, warmup, kernel="auto"):
@@ -98,6 +123,11 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ker_ms, ker_steps = sim.timing()
+    passes = {}
+    for k in PASS_KERNELS:
+        ms, nl = sim.timing_kernel(k)
+        if nl:
+            passes[k] = {"launches": nl, "avg_ms": ms / nl}
     sim.set_timing(False)
     obs = sim.observables()
     site_mask = sim.carry.cpu().numpy().copy()
@@ -108,22 +138,28 @@ def run_leg(workload, precision, steps, warmup, kernel="auto"):
                                      w["phi_field"] is not None)
     per_launch_ms = ker_ms / max(ker_steps, 1)
     kname = sim.kernel_name()
+    walls, phif = w["solid"] is not None, w["phi_field"] is not None
+    for k, v in passes.items():
+        v["bytes_per_node"] = pass_bytes_per_node(k, p["Q"], precision, walls, phif)
+        v["achieved_gbs"] = v["bytes_per_node"] * N / (v["avg_ms"] * 1e-3) / 1e9
     res = {
         "precision": precision,
         "kernel": kname,
+        "passes": passes,
         "mlups": N * steps / wall / 1e6,
         "ms_per_step": wall * 1e3 / steps,
         "kernel_ms_per_step": per_launch_ms,
-        "bytes_per_node": bpn,
-        "achieved_gbs": bpn * N / (per_launch_ms * 1e-3) / 1e9,
-        "stored_state_bytes_per_node": (record_bytes_per_node(
-            precision, w["solid"] is not None, w["phi_field"] is not None)
-            if kname == "k_pull_record" else bpn),
+        "population_equivalent_bytes_per_node": bpn,
+        "population_equivalent_gbs": bpn * N / (per_launch_ms * 1e-3) / 1e9,
         "v_mass": obs["v_mass"],
         "site_steps": obs["site_steps"],
         "n_negative": obs["n_negative"],
         "_site_mask": site_mask,
     }
+    # kernel time per step of the passes (the first and last step of a record-form call run
+    # the population passes), and the algorithmic bytes those passes move per step
+    res["step_bytes_per_node"] = sum(v["bytes_per_node"] * v["launches"] for v in passes.values()) \
+        / max(ker_steps, 1)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -499,6 +535,154 @@ def feature_costs(steps=200, precision="fp32s"):
     return {"workload": f"ms per step, 192^3, {precision}, {steps} steps", "costs": out}
 
 
+def c2_benchmark(steps=20000, phis=(1e-6, 1e-5, 1e-4), every=1000, oracle_steps=200):
+    """D2Q9 1024^2: a flat film at y = 512 between walls at y = 0 and 1023, and an ellipse
+    200 x 120, each at phi = 1e-6, 1e-5, 1e-4, 20000 steps, in FP64 and in FP32 storage.  The
+    FP32 run is compared with the FP64 run (film height and drop volume, site count); the FP64
+    run is checked against the FP64 oracle over its first 200 steps (all cores).  Both
+    population buffers fit in the 256 MB last-level cache (FP32: 75 MB each, FP64: 151 MB), so
+    the MLUPS are cache-resident, not an HBM roofline."""
+    import numpy as np
+    import torch
+    from oracle.oracle import Oracle  # the FP64 check of the GPU's FP64 run
+    from paper_2412_14859_amd import analytic, cgevap, inputs
+    cores = len(os.sched_getaffinity(0))
+    out = []
+    for name in ("flat2d", "ellipse2d"):
+        for phi in phis:
+            w = inputs.workload(name, phi=phi)
+            p = w["params"]
+            runs = {}
+            for prec in ("fp64", "fp32s"):
+                sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                                        phi_field=w["phi_field"], precision=prec)
+                if prec == "fp64":
+                    ora = Oracle(p, solid=w["solid"])
+                    ora.set_threads(cores)
+                    ora.init_equilibrium(w["rho_r"], w["rho_b"])
+                    ora.step(oracle_steps)
+                    sim.step(oracle_steps)
+                    f_o = ora.populations()
+                    f_g = sim.populations().cpu().numpy()
+                    fl = w["solid"] == 0 if w["solid"] is not None else None
+                    d = np.abs(f_g - f_o)
+                    e_or = float((d[:, :, fl] if fl is not None else d).max())
+                    same_sites = ora.observables()["site_steps"] == sim.observables()["site_steps"]
+                    del ora, f_o, f_g, d
+                    done = oracle_steps
+                else:
+                    done = 0
+                hist = []
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                while done < steps:
+                    k = min(every - done % every, steps - done)
+                    sim.step(k)
+                    done += k
+                    rr = sim.fields()["rho_r"]
+                    ob = sim.observables()
+                    x = analytic.film_height(rr[0], axis=0, solid_layers=1) \
+                        if name == "flat2d" else None
+                    hist.append((done, ob["v_mass"], x, ob["site_steps"]))
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                runs[prec] = {"hist": hist, "mlups": round(p["shape"][1] * p["shape"][2]
+                                                            * (steps - (oracle_steps if prec == "fp64" else 0))
+                                                            / wall / 1e6, 1)}
+                sim.close()
+            h64, h32 = runs["fp64"]["hist"], runs["fp32s"]["hist"]
+            v_err = max(abs(a[1] - b[1]) / a[1] for a, b in zip(h64, h32))
+            rec = {"case": name, "phi": phi, "steps": steps,
+                   "fp64_vs_oracle_200_steps": {"max_abs_population_diff": e_or,
+                                                "site_steps_equal": bool(same_sites)},
+                   "v_mass_fp64_end": h64[-1][1], "v_mass_fp32s_end": h32[-1][1],
+                   "volume_lost_fp64": h64[0][1] - h64[-1][1] if h64 else None,
+                   "max_rel_volume_diff_fp32s_vs_fp64": v_err,
+                   "rel_diff_of_volume_lost": abs((h32[0][1] - h32[-1][1]) - (h64[0][1] - h64[-1][1]))
+                                              / max(abs(h64[0][1] - h64[-1][1]), 1e-300),
+                   "site_steps_fp64": h64[-1][3], "site_steps_fp32s": h32[-1][3],
+                   "mlups_fp64": runs["fp64"]["mlups"], "mlups_fp32s": runs["fp32s"]["mlups"]}
+            if name == "flat2d":
+                rec["height_fp64_end"] = h64[-1][2]
+                rec["height_fp32s_end"] = h32[-1][2]
+                rec["max_abs_height_diff"] = max(abs(a[2] - b[2]) for a, b in zip(h64, h32))
+                rec["height_drop_fp64"] = h64[0][2] - h64[-1][2]
+            print(f"c2 {rec}", file=sys.stderr, flush=True)
+            out.append(rec)
+    return {"workload": "D2Q9 1024^2 flat film (walls y=0,1023) and ellipse 200x120, sigma 4.44e-4, "
+                        "beta 0.7, Gamma 0.305, Sbar 3, tau 1; FP32 storage against FP64; "
+                        "cache-resident", "cases": out}
+
+
+def c4_benchmark(steps=20000, every=2000, precision="fp32s"):
+    """D3Q19 384 x 384 x 192 sessile drop: a hemispherical cap R = 96 on the wall z = 0 (lid at
+    z = 191), density ratio 10 (liquid 1.0, vapour 0.1), tau 1.0 / 0.6, flux
+    1e-5 (1 + 0.2 r / 96) with seeded noise 1e-7, 20000 steps at FP32 storage: MLUPS, the
+    kernels' rooflines and the vapour density (closed box, no outlet: the evaporated mass stays
+    in the vapour, whose density drifts up)."""
+    import numpy as np
+    import torch
+    from paper_2412_14859_amd import cgevap, inputs
+    w = inputs.workload("sessile3d")
+    p = w["params"]
+    nz, ny, nx = p["shape"]
+    N = nx * ny * nz
+    sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
+                            phi_field=w["phi_field"], precision=precision)
+    fluid = torch.as_tensor(w["solid"] == 0, device=sim.device)
+
+    def vapour():
+        fl = sim.fields()
+        vap = (fl["rhoN"] < -0.99) & fluid
+        rb = fl["rho_b"][vap]
+        return float(rb.mean()), float(rb.max()), int(vap.sum())
+
+    hist = [(0, sim.observables()["v_mass"]) + vapour()]
+    sim.set_timing(True)
+    wall = 0.0
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(k)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        done += k
+        ob = sim.observables()
+        hist.append((done, ob["v_mass"]) + vapour())
+        print(f"c4 step {done} v_mass {ob['v_mass']:.2f} vapour {hist[-1][2:]}", file=sys.stderr,
+              flush=True)
+    passes = {}
+    for kname in PASS_KERNELS:
+        ms, nl = sim.timing_kernel(kname)
+        if nl:
+            bpn = pass_bytes_per_node(kname, 19, precision, True, True)
+            gbs = bpn * N / (ms / nl * 1e-3) / 1e9
+            passes[kname] = {"avg_ms": round(ms / nl, 4), "launches": nl, "bytes_per_node": bpn,
+                             "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    ker_ms, ker_steps = sim.timing()
+    kname = sim.kernel_name()
+    obs = sim.observables()
+    sim.close()
+    pop_bpn = algorithmic_bytes_per_node(19, precision, True, True)
+    step_ms = ker_ms / max(ker_steps, 1)
+    return {"workload": "D3Q19 384x384x192 sessile cap R=96 on a wall (lid at z=191), density ratio "
+                        "10, tau 1.0/0.6, A=5e-4, beta 0.7, Gamma 0.305, phi(x) = 1e-5 (1 + 0.2 r/96) "
+                        f"+ U(-1e-7, 1e-7) seed 1001, {precision}",
+            "steps": steps, "kernel": kname, "mlups": round(N * steps / wall / 1e6, 1),
+            "ms_per_step": round(wall / steps * 1e3, 4), "kernel_ms_per_step": round(step_ms, 4),
+            "kernels": passes,
+            "population_equivalent_frac": round(pop_bpn * N / (step_ms * 1e-3) / 1e9
+                                                / HBM_PEAK_GBS, 4),
+            "v_mass_start": hist[0][1], "v_mass_end": obs["v_mass"],
+            "sink_total": obs["sink_total"], "site_steps": obs["site_steps"],
+            "vapour_rho_b_mean": [[h[0], round(h[2], 7)] for h in hist],
+            "vapour_rho_b_drift": (hist[-1][2] - hist[0][2]) / hist[0][2],
+            "vapour_nodes_start_end": [hist[0][4], hist[-1][4]],
+            "n_negative_end": obs["n_negative"]}
+
+
 def copy_probe_gbs(nbytes=1 << 30, reps=5):
     """Achievable HBM bandwidth: the library's streaming copy kernel over nbytes, timed with
     events on torch's current stream (the stream the probe is launched on); read + write."""
@@ -520,24 +704,61 @@ def copy_probe_gbs(nbytes=1 << 30, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def cpu_baseline(seconds_hint=15.0):
-    """The FP64 oracle (single thread) on a bounded sample of the workload: the same drop
-    scaled to 64^3 (R = 16), a fixed number of steps."""
+def _oracle_mlups(w, steps, threads):
     from oracle.oracle import Oracle  # cpu_baseline leg only
-    from paper_2412_14859_amd import inputs
-    w = inputs.workload("sphere3d", shape=(64, 64, 64), radius=16.0)
-    o = Oracle(w["params"])
+    o = Oracle(w["params"], solid=w["solid"], phi_field=w["phi_field"])
+    o.set_threads(threads)
     o.init_equilibrium(w["rho_r"], w["rho_b"])
-    o.step(1)
-    steps = 0
+    N = 1
+    for d in w["params"]["shape"]:
+        N *= d
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds_hint:
-        o.step(5)
-        steps += 5
+    o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": 64 ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"D3Q19 64^3 drop R=16 (the 256^3 workload scaled 1/4), {steps} steps, "
-                      "FP64, single thread"}
+    return round(N * steps / dt / 1e6, 3), round(dt, 2)
+
+
+def _gpu_mlups(w, steps, precision="fp64"):
+    import torch
+    from paper_2412_14859_amd import cgevap
+    sim = cgevap.Simulation(w["params"], w["rho_r"], w["rho_b"], solid=w["solid"],
+                            phi_field=w["phi_field"], precision=precision)
+    sim.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    N = 1
+    for d in w["params"]["shape"]:
+        N *= d
+    sim.close()
+    return {"mlups": round(N * steps / dt / 1e6, 1), "us_per_step": round(dt / steps * 1e6, 2)}
+
+
+def cpu_baseline():
+    """The FP64 oracle as it stands, timed on this host: the 64^3 downscale of the headline
+    drop (R = 16, the sample the value is quoted on) and the 128^2 D2Q9 drop of 2000 steps in
+    full, each single-threaded and with its per-node loops on every core this process may run
+    on (same results), next to the GPU's FP64 MLUPS on the same two workloads."""
+    from paper_2412_14859_amd import inputs
+    cores = len(os.sched_getaffinity(0))
+    w3 = inputs.workload("sphere3d", shape=(64, 64, 64), radius=16.0)
+    w2 = inputs.workload("drop2d")
+    s3_one = _oracle_mlups(w3, 40, 1)
+    s3_all = _oracle_mlups(w3, 100, cores)
+    c1_one = _oracle_mlups(w2, 2000, 1)
+    c1_all = _oracle_mlups(w2, 2000, cores)
+    return {"value": s3_all[0], "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "D3Q19 64^3 drop R=16 (the 256^3 workload scaled 1/4), 100 steps, FP64, "
+                      f"per-node loops on {cores} threads ({s3_all[1]} s)",
+            "single_thread": {"value": s3_one[0], "sample": f"the same, 40 steps ({s3_one[1]} s)"},
+            "c1_full": {"workload": "D2Q9 128^2 drop R=32, |rho^N| < 0.5 sites, phi 1e-5, 2000 "
+                                    "steps, FP64", "mlups_all_cores": c1_all[0],
+                        "seconds_all_cores": c1_all[1], "mlups_single_thread": c1_one[0],
+                        "seconds_single_thread": c1_one[1]},
+            "gpu_same_workloads_fp64": {"d3q19_64cube_100_steps": _gpu_mlups(w3, 100),
+                                        "d2q9_128sq_2000_steps": _gpu_mlups(w2, 2000)}}
 
 
 def main():
@@ -565,6 +786,12 @@ def main():
                          "height laws (runs instead of the bench line)")
     ap.add_argument("--flux-benchmark", action="store_true",
                     help="print only the height-dependent flux benchmark (hemisphere vs ODE)")
+    ap.add_argument("--c2", action="store_true",
+                    help="D2Q9 1024^2 film and ellipse over 20000 steps, FP32 storage against "
+                         "FP64 (runs instead of the bench line)")
+    ap.add_argument("--c4", action="store_true",
+                    help="D3Q19 384x384x192 sessile drop at density ratio 10 over 20000 steps "
+                         "(runs instead of the bench line)")
     ap.add_argument("--adjoint-only", type=int, default=0, metavar="N",
                     help="print only the adjoint cost leg on the D2Q9 N^2 drop (profiling)")
     args = ap.parse_args()
@@ -578,6 +805,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.feature_costs:
         print(json.dumps(feature_costs(steps=args.steps)), flush=True)
+        return
+    if args.c2:
+        print(json.dumps(c2_benchmark()), flush=True)
+        return
+    if args.c4:
+        print(json.dumps(c4_benchmark(steps=args.steps if args.steps != 200 else 20000)),
+              flush=True)
         return
     if args.gamma_calibration:
         print(json.dumps(gamma_calibration_benchmark()), flush=True)
@@ -618,10 +852,24 @@ def main():
             leg.pop("_site_mask")
     main_leg.pop("_site_mask")
     N = n ** 3
-    achieved = main_leg["achieved_gbs"]
     step_ms = main_leg["kernel_ms_per_step"]
-    tb = stored_traffic(main_leg["kernel"], n, args.precision)
-    traffic = None if tb is None else round(tb / (step_ms * 1e-3) / 1e9, 1)
+    passes = main_leg["passes"]
+    # the dominant kernel: the pass kernel with the most time in the timed region
+    dom = max(passes, key=lambda k: passes[k]["avg_ms"] * passes[k]["launches"])
+    dp = passes[dom]
+    tb = stored_traffic(dom, n, args.precision)
+    storage = {("fp32s", True): "fp32: 14-value post-collision records between the steps of a "
+                                "call (record form), shifted populations at call boundaries",
+               ("fp64", True): "fp64: 14-value post-collision records between the steps of a "
+                               "call (record form), populations at call boundaries",
+               ("fp32s", False): "fp32 shifted populations", ("fp64", False): "fp64 populations",
+               ("fp16s", False): "fp16 shifted populations, stochastic rounding"}
+    record = main_leg["kernel"] == "k_pull_record"
+    arithmetic = {("fp32s", True): "pulled populations rebuilt from the FP32 records in FP32; "
+                                   "moment sums, collision, perturbation and recolouring in FP64",
+                  ("fp64", True): "FP64", ("fp32s", False): "FP64 on FP32-stored values",
+                  ("fp64", False): "FP64", ("fp16s", False): "FP32 on FP16-stored values"}
+    pop_bpn = main_leg["population_equivalent_bytes_per_node"]
     out = {
         "metric": "MLUPS + % HBM roofline, D3Q19 CG+evap FP32 vs FP64; adjoint/forward time",
         "value": round(main_leg["mlups"], 1),
@@ -633,36 +881,46 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32s": "f64", "fp64": "f64", "fp16s": "f32"}[args.precision],
+        # the type the dominant kernel stores and rebuilds in (its moment sums are FP64)
+        "dtype": {"fp32s": "f32", "fp64": "f64", "fp16s": "f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"D3Q19 {n}^3 periodic, spherical drop R={64 * n // 256}, "
                                "unit density ratio, tau=1, A=5e-4, beta=0.7, phi=1e-5, "
                                "Gamma=0.305, Sbar=3",
-                   "nodes": N, "storage": {"fp32s": "fp32 shifted", "fp64": "fp64",
-                                           "fp16s": "fp16 shifted, stochastic rounding"}[args.precision],
-                   "kernel": main_leg["kernel"],
-                   "arithmetic": ("FP64 collision and moment sums; pulled populations rebuilt "
-                                  "from the FP32 post-collision record in FP32"
-                                  if main_leg["kernel"] == "k_pull_record" and args.precision != "fp64"
-                                  else {"fp32s": "FP64", "fp64": "FP64",
-                                        "fp16s": "FP32"}[args.precision])},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "traffic_bytes_per_step": tb,
-                     "kernel": STEP_KERNELS[main_leg["kernel"]][0],
-                     "kernel_ms_per_step": round(main_leg["kernel_ms_per_step"], 4),
-                     "bytes_per_node": main_leg["bytes_per_node"],
-                     # bytes the step form stores between steps (the record form: 14 values
-                     # per node instead of 2Q populations), and the HBM fraction they give
-                     "stored_state_bytes_per_node": main_leg["stored_state_bytes_per_node"],
-                     "stored_state_frac": round(
-                         main_leg["stored_state_bytes_per_node"] * N
-                         / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "nodes": N, "storage": storage[args.precision, record],
+                   "kernel": STEP_KERNELS[main_leg["kernel"]][0],
+                   "arithmetic": arithmetic[args.precision, record]},
+        "roofline": {"bound": "hbm", "kernel": dom,
+                     "achieved": round(dp["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(dp["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None if tb is None else round(tb / (dp["avg_ms"] * 1e-3) / 1e9, 1),
+                     "traffic_bytes_per_launch": tb,
+                     "bytes_per_node": dp["bytes_per_node"], "nodes_per_launch": N,
+                     "avg_launch_ms": round(dp["avg_ms"], 4), "launches": dp["launches"],
                      "copy_probe_gbs": round(copy_gbs, 1),
-                     "frac_of_copy": round(achieved / copy_gbs, 4)},
-        "legs": {k: {kk: (float(f"{vv:.9g}") if isinstance(vv, float) else vv)
-                     for kk, vv in v.items()} for k, v in legs.items()},
+                     "frac_of_copy": round(dp["achieved_gbs"] / copy_gbs, 4)},
+        "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"],
+                        "bytes_per_node": v["bytes_per_node"],
+                        "achieved_gbs": round(v["achieved_gbs"], 1),
+                        "frac": round(v["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+                    for k, v in passes.items()},
+        "step": {"kernel_ms": round(step_ms, 4),
+                 "bytes_per_node": round(main_leg["step_bytes_per_node"], 2),
+                 "achieved_gbs": round(main_leg["step_bytes_per_node"] * N / (step_ms * 1e-3)
+                                       / 1e9, 1),
+                 # the rate a step that streams the 2Q populations through HBM (read once,
+                 # written once, plus the site byte) would need for the same MLUPS
+                 "population_equivalent_bytes_per_node": pop_bpn,
+                 "population_equivalent_gbs": round(pop_bpn * N / (step_ms * 1e-3) / 1e9, 1),
+                 "population_equivalent_frac": round(pop_bpn * N / (step_ms * 1e-3) / 1e9
+                                                     / HBM_PEAK_GBS, 4)},
+        "legs": {k: dict({kk: (float(f"{vv:.9g}") if isinstance(vv, float) else vv)
+                          for kk, vv in v.items() if kk != "passes"},
+                         kernels={kk: {"avg_ms": round(vv["avg_ms"], 4),
+                                       "achieved_gbs": round(vv["achieved_gbs"], 1),
+                                       "frac": round(vv["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+                                  for kk, vv in v["passes"].items()})
+                 for k, v in legs.items()},
     }
     if not args.no_adjoint:
         out["adjoint"] = {"512": adjoint_leg(512, 2000, 100),

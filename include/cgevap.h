@@ -340,11 +340,17 @@ cge_status cge_observables_noalloc(const cge_params* params, const void* pop,
  * rho_r, rho_b, rhoN ([N]) and u ([D][N]).  Solid nodes get 0 (rhoN: wetting value). */
 cge_status cge_fields(cge_ctx* ctx, double* rho_r, double* rho_b, double* u, double* rhoN);
 
-/* Kernel timing: when on, HIP events bracket every launch of the step kernel(s) on the
- * context's stream.  cge_timing synchronises and returns the summed milliseconds and the
- * number of timed steps since timing was switched on. */
+/* Kernel timing: when on, HIP events on the context's stream mark the start of every step
+ * and the end of each of its passes.  cge_timing synchronises and returns the summed
+ * milliseconds and the number of timed steps since timing was switched on; cge_timing_kernel
+ * the milliseconds and launches of one pass kernel by name (e.g. "k_pull_record_zm",
+ * "k_finish_record", "k_moments", "k_finish", "k_finish_tile", "k_pull_record", "k_phase",
+ * "k_collide", "k_fused"; a pass's helper launches, such as the wetting of solid nodes,
+ * count with it), 0 and 0 for a kernel that has not run. */
 cge_status cge_set_timing(cge_ctx* ctx, int on);
 cge_status cge_timing(cge_ctx* ctx, double* total_ms, long long* steps);
+cge_status cge_timing_kernel(cge_ctx* ctx, const char* kernel, double* total_ms,
+                             long long* launches);
 
 /* Name of the step kernel the context launches (static string). */
 const char* cge_kernel_name(const cge_ctx* ctx);

@@ -1,7 +1,8 @@
 """Build the FP64 CPU oracle (test infrastructure only) into oracle/libcg_oracle.so.
 
 Plain gcc, -O2, no fused multiply-add contraction and no fast-math, so the oracle's
-arithmetic is the literal IEEE double sequence written in cg_oracle.c.
+arithmetic is the literal IEEE double sequence written in cg_oracle.c; OpenMP for the
+optional parallel per-node loops (off unless a thread count is set).
 """
 import os
 import subprocess
@@ -18,6 +19,8 @@ def build(sanitize: bool = False, out: str = None) -> str:
            "-Wall", "-Wextra", "-Wno-unused-parameter", SRC, "-o", out, "-lm"]
     if sanitize:
         cmd[3:3] = ["-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
+    else:  # per-node loops in parallel when asked for (ora_set_threads); same results
+        cmd[3:3] = ["-fopenmp"]
     subprocess.run(cmd, check=True)
     return out
 

@@ -49,6 +49,11 @@
  *   - Blue recolouring uses F_br = -F_rb, i.e. cos(theta_br) = -cos(theta_rb).
  *   - No clamp of negative populations; they are only counted.
  *
+ * Threads: with threads > 1 (ora_set_threads, OpenMP builds only) the loops over nodes that
+ * are independent node by node (phase field, collision, streaming) run in parallel; the sink
+ * loop, which adds up the bookkeeping, and every reduction stay sequential, so the results are
+ * the same bits for any thread count.
+ *
  * Storage: populations f[(k*Q + i)*N + n], k = 0 red (evaporating), k = 1 blue,
  * node n = x + nx*(y + ny*z).  The state between steps is the post-streaming,
  * pre-sink distribution.
@@ -103,6 +108,7 @@ typedef struct ora_ctx {
        contrast): out_lo, out_hi switch the planes at index 0 and the last index */
     int out_lo, out_hi;
     double out_rho;
+    int threads; /* OpenMP threads of the per-node loops (1 = sequential) */
 } ora_ctx;
 
 /* ------------------------------------------------------------------ lattices */
@@ -232,6 +238,7 @@ static void component_alphas(const ora_lattice* L, const double rho_in[2], doubl
 /* rho^N of every fluid node from the current populations (Sec. II.A) */
 static void phase_field_fluid(ora_ctx* s) {
     int Q = s->L.Q;
+#pragma omp parallel for schedule(static) num_threads(s->threads) if (s->threads > 1)
     for (long long n = 0; n < s->N; ++n) {
         if (is_solid(s, n)) continue;
         double rr = 0.0, rb = 0.0;
@@ -247,6 +254,7 @@ static void phase_field_fluid(ora_ctx* s) {
 static void phase_field_solid(ora_ctx* s) {
     if (!s->solid) return;
     int Q = s->L.Q;
+#pragma omp parallel for schedule(static) num_threads(s->threads) if (s->threads > 1)
     for (long long n = 0; n < s->N; ++n) {
         if (!is_solid(s, n)) continue;
         double num = 0.0, den = 0.0;
@@ -282,6 +290,7 @@ ora_ctx* ora_create(const ora_params* p, const unsigned char* solid, const doubl
         return NULL;
     }
     s->N = (long long)p->nx * p->ny * p->nz;
+    s->threads = 1;
     component_alphas(&s->L, p->rho_in, s->alpha);
     long long nf = 2LL * s->L.Q * s->N;
     s->f = (double*)calloc(nf, sizeof(double));
@@ -491,6 +500,7 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
     phase_field_solid(s);
 
     /* step 5: gradient, collision, perturbation, recolouring at every fluid node */
+#pragma omp parallel for schedule(static) num_threads(s->threads) if (s->threads > 1)
     for (long long n = 0; n < s->N; ++n) {
         if (is_solid(s, n)) {
             for (int k = 0; k < 2; ++k)
@@ -558,6 +568,7 @@ static void one_step(ora_ctx* s, const unsigned char* mask_in, unsigned char* ma
 
     /* step 6: streaming (pull form), halfway bounce-back from solid neighbours; then the
        populations that enter through an outlet plane */
+#pragma omp parallel for schedule(static) num_threads(s->threads) if (s->threads > 1)
     for (long long n = 0; n < s->N; ++n) {
         for (int i = 0; i < Q; ++i) {
             if (is_solid(s, n)) {
@@ -617,6 +628,13 @@ int ora_set_height_flux(ora_ctx* s, double phi_s, double K, double h_scale, long
     s->hf_phi = phi_s;
     s->hf_K = K;
     s->hf_hs = h_scale;
+    return 0;
+}
+
+/* Threads of the per-node loops (>= 1; without OpenMP the loops stay sequential). */
+int ora_set_threads(ora_ctx* s, int threads) {
+    if (threads < 1) return 1;
+    s->threads = threads;
     return 0;
 }
 

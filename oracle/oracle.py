@@ -59,6 +59,7 @@ def lib():
         L.ora_recompute_fmag.argtypes = [C.c_void_p]
         L.ora_set_counters.argtypes = [C.c_void_p, C.c_longlong, C.c_longlong, C.c_double]
         L.ora_step.argtypes = [C.c_void_p, C.c_longlong, up, up]
+        L.ora_set_threads.argtypes = [C.c_void_p, C.c_int]
         L.ora_set_height_flux.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double,
                                           C.c_longlong]
         L.ora_get_phi_field.argtypes = [C.c_void_p, dp]
@@ -170,6 +171,11 @@ class Oracle:
         if lib().ora_get_phi_field(self._ctx, _dp(out)) != 0:
             return None
         return out
+
+    def set_threads(self, n):
+        """OpenMP threads of the per-node loops (results do not depend on it)."""
+        if lib().ora_set_threads(self._ctx, int(n)) != 0:
+            raise ValueError("threads must be >= 1")
 
     def set_counters(self, step=0, site_steps=0, sink_total=0.0):
         lib().ora_set_counters(self._ctx, step, site_steps, sink_total)

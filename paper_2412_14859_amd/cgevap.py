@@ -25,7 +25,7 @@ EXPORTS = ["cge_create", "cge_scratch_bytes", "cge_create_with_scratch", "cge_po
            "cge_load_state", "cge_verify_state", "cge_adjoint_bytes", "cge_segment_bytes", "cge_forward_ckpt", "cge_backward",
            "cge_reset_sites", "cge_set_site_threshold", "cge_set_height_flux", "cge_set_outlet",
            "cge_set_counters", "cge_set_zchunk",
-           "cge_step", "cge_observables", "cge_observables_noalloc", "cge_fields", "cge_set_timing", "cge_timing",
+           "cge_timing_kernel", "cge_step", "cge_observables", "cge_observables_noalloc", "cge_fields", "cge_set_timing", "cge_timing",
            "cge_kernel_name", "cge_lattice_tables", "cge_copy_probe", "cge_last_error",
            "cge_destroy"]
 
@@ -103,6 +103,7 @@ def lib():
         L.cge_fields.argtypes = [vp, vp, vp, vp, vp]
         L.cge_set_timing.argtypes = [vp, C.c_int]
         L.cge_timing.argtypes = [vp, dp, P(C.c_longlong)]
+        L.cge_timing_kernel.argtypes = [vp, C.c_char_p, dp, P(C.c_longlong)]
         L.cge_kernel_name.argtypes = [vp]
         L.cge_kernel_name.restype = C.c_char_p
         L.cge_lattice_tables.argtypes = [C.c_int, dp, dp, dp, dp, P(C.c_int), P(C.c_int), dp]
@@ -346,6 +347,12 @@ class Simulation:
     def timing(self):
         ms, n = C.c_double(), C.c_longlong()
         self._check(lib().cge_timing(self._ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def timing_kernel(self, name):
+        """(milliseconds, launches) of one pass kernel since timing was switched on."""
+        ms, n = C.c_double(), C.c_longlong()
+        self._check(lib().cge_timing_kernel(self._ctx, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
     def kernel_name(self):

@@ -56,37 +56,50 @@ Phys<M> phys(const cge_ctx* c) {
 template Phys<float> phys<float>(const cge_ctx*);
 template Phys<double> phys<double>(const cge_ctx*);
 
-void timing_begin(cge_ctx* c, const char* step_name) {
-    roctxRangePushA(step_name);
-    if (!c->timing) return;
-    if (c->ev_used + 2 > c->ev.size()) {
-        for (int k = 0; k < 2; ++k) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return;
-            c->ev.push_back(e);
-        }
+// record the next event of the pool with a label (nullptr: a step starts)
+static bool timing_record(cge_ctx* c, const char* label) {
+    if (c->ev_used == c->ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        c->ev.push_back(e);
+        c->ev_lab.push_back(nullptr);
     }
-    (void)hipEventRecord(c->ev[c->ev_used], c->stream);
+    if (hipEventRecord(c->ev[c->ev_used], c->stream) != hipSuccess) return false;
+    c->ev_lab[c->ev_used++] = label;
+    return true;
 }
 
+// sum the recorded intervals: each labelled event closes an interval of that kernel
 static void timing_fold(cge_ctx* c) {
     if (c->ev_used == 0) return;
     (void)hipEventSynchronize(c->ev[c->ev_used - 1]);
-    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    for (size_t k = 1; k < c->ev_used; ++k) {
+        const char* lab = c->ev_lab[k];
+        if (!lab) continue;
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]) == hipSuccess) c->timed_ms += ms;
+        if (hipEventElapsedTime(&ms, c->ev[k - 1], c->ev[k]) != hipSuccess) continue;
+        c->timed_ms += ms;
+        auto it = c->ktime.begin();
+        while (it != c->ktime.end() && it->first != lab) ++it;
+        if (it == c->ktime.end()) it = c->ktime.insert(it, {std::string(lab), {0.0, 0}});
+        it->second.first += ms;
+        it->second.second += 1;
     }
     c->ev_used = 0;
 }
 
-void timing_end(cge_ctx* c) {
-    roctxRangePop();
-    if (!c->timing || c->ev_used + 2 > c->ev.size()) return;
-    (void)hipEventRecord(c->ev[c->ev_used + 1], c->stream);
-    c->ev_used += 2;
-    c->timed_steps += 1;
-    if (c->ev_used >= 2048) timing_fold(c);
+void timing_begin(cge_ctx* c, const char* step_name) {
+    roctxRangePushA(step_name);
+    if (!c->timing) return;
+    if (c->ev_used + 8 > 4096) timing_fold(c);  // a step records at most 3 events
+    if (timing_record(c, nullptr)) c->timed_steps += 1;
 }
+
+void timing_pass(cge_ctx* c, const char* kernel) {
+    if (c->timing && c->ev_used > 0) (void)timing_record(c, kernel);
+}
+
+void timing_end(cge_ctx* c) { roctxRangePop(); }
 
 __global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                               long long n16) {
@@ -526,6 +539,7 @@ cge_status cge_set_timing(cge_ctx* c, int on) {
         c->timed_ms = 0.0;
         c->timed_steps = 0;
         c->ev_used = 0;
+        c->ktime.clear();
     }
     if (!on) timing_fold(c);
     c->timing = on != 0;
@@ -537,6 +551,20 @@ cge_status cge_timing(cge_ctx* c, double* total_ms, long long* steps) {
     timing_fold(c);
     *total_ms = c->timed_ms;
     *steps = c->timed_steps;
+    return CGE_OK;
+}
+
+cge_status cge_timing_kernel(cge_ctx* c, const char* kernel, double* total_ms,
+                             long long* launches) {
+    if (!c || !kernel || !total_ms || !launches) return fail(c, CGE_EINVAL, "NULL argument");
+    timing_fold(c);
+    *total_ms = 0.0;
+    *launches = 0;
+    for (const auto& kv : c->ktime)
+        if (kv.first == kernel) {
+            *total_ms = kv.second.first;
+            *launches = kv.second.second;
+        }
     return CGE_OK;
 }
 

@@ -353,6 +353,7 @@ static cge_status fused_impl(cge_ctx* c, long long nsteps) {
                                    dim3(kFTX * kFTY), 0, c->stream, src, dst, mask[m],
                                    mask[1 - m], c->phi_field, c->acc_sink, c->acc_sites, c->g, P,
                                    salt, fs);
+            timing_pass(c, "k_fused");
             timing_end(c);
             if (cge_status s = check(c, hipGetLastError(), "fused step launch")) return s;
             m = 1 - m;

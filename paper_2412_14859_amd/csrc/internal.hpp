@@ -5,6 +5,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/cgevap.h"
@@ -58,10 +59,13 @@ struct cge_ctx {
     double sink_offset = 0.0;
     // timing
     bool timing = false;
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t> ev;     // event pool
+    std::vector<const char*> ev_lab;  // per recorded event: nullptr = a step starts, else the
+                                      // kernel (pass) that ran since the previous event
     size_t ev_used = 0;
     long long timed_steps = 0;
     double timed_ms = 0.0;
+    std::vector<std::pair<std::string, std::pair<double, long long>>> ktime;  // per kernel
     std::string err;
 };
 
@@ -129,8 +133,11 @@ cge_status observables_noalloc(const cge_params* p, const void* pop, const unsig
 cge_status copy_probe(void* dst, const void* src, size_t nbytes, hipStream_t s);
 
 // timing helpers around the kernel launches of one step; they also open and close a roctx range
-// named after the step form (rocprofv3 --marker-trace shows the steps and their kernels)
+// named after the step form (rocprofv3 --marker-trace shows the steps and their kernels).
+// timing_pass after each pass's launches attributes the time since the previous mark to the
+// named kernel (its helper launches, e.g. the wetting pass, included).
 void timing_begin(cge_ctx* c, const char* step_name);
+void timing_pass(cge_ctx* c, const char* kernel);
 void timing_end(cge_ctx* c);
 
 // roctx range over a scope (an entry point, a segment of the adjoint)

@@ -635,14 +635,17 @@ static cge_status split_one(cge_ctx* c, const void* carry_in, void* carry_out, v
     hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
                        carry_in, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
     if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+    timing_pass(c, "k_moments");
     if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
         const dim3 tb(kTileX, kTileY, 1);
         const dim3 tg((c->g.nx + kTileX - 1) / kTileX, (c->g.ny + kTileY - 1) / kTileY, c->g.nz);
         hipLaunchKernelGGL((k_finish_tile<S, M>), tg, tb, 0, c->stream, dst, carry_out, rhoN, mom,
                            c->g, P, salt);
+        timing_pass(c, "k_finish_tile");
     } else {
         hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
                            carry_out, rhoN, mom, c->g, P, salt);
+        timing_pass(c, "k_finish");
     }
     timing_end(c);
     if (cge_status s = check(c, hipGetLastError(), "split step launch")) return s;
@@ -686,7 +689,9 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
     const S* src = static_cast<const S*>(c->pop[c->cur]);
     S* dst = static_cast<S*>(c->pop[1 - c->cur]);
     const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
-    timing_begin(c, first ? "record step (from populations)" : (last ? "record step (to populations)" : "record step"));
+    timing_begin(c, first ? "record step (from populations)"
+                          : (last ? "record step (to populations)" : "record step"));
+    const char* pass1 = "k_moments";
     if (first)
         hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
                            c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
@@ -700,25 +705,32 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
                                    c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P,
                                    zc);
                 marched = true;
+                pass1 = "k_pull_record_zm";
             }
         }
-        if (!marched)
+        if (!marched) {
             hipLaunchKernelGGL((k_pull_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec,
                                c->flags, c->carry, c->phi_field, rhoN, mom, c->acc_sink,
                                c->acc_sites, c->g, P);
+            pass1 = "k_pull_record";
+        }
     }
     if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+    timing_pass(c, pass1);
     if (!last) {
         hipLaunchKernelGGL((k_finish_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec, c->flags,
                            c->carry, rhoN, mom, c->g, P);
+        timing_pass(c, "k_finish_record");
     } else if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
         const dim3 tb(kTileX, kTileY, 1);
         const dim3 tg((c->g.nx + kTileX - 1) / kTileX, (c->g.ny + kTileY - 1) / kTileY, c->g.nz);
         hipLaunchKernelGGL((k_finish_tile<S, M>), tg, tb, 0, c->stream, dst, c->carry, rhoN, mom,
                            c->g, P, salt);
+        timing_pass(c, "k_finish_tile");
     } else {
         hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
                            c->carry, rhoN, mom, c->g, P, salt);
+        timing_pass(c, "k_finish");
     }
     timing_end(c);
     if (cge_status s = check(c, hipGetLastError(), "record step launch")) return s;

@@ -121,9 +121,11 @@ static cge_status twopass_impl(cge_ctx* c, long long nsteps) {
                            c->flags, c->carry, c->phi_field, rhoN, c->g, P, 1);
         if (WALLS)
             hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
+        timing_pass(c, "k_phase");
         hipLaunchKernelGGL((k_collide<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, dst, c->flags,
                            c->carry, c->phi_field, rhoN, c->acc_sink, c->acc_sites, c->g, P,
                            salt);
+        timing_pass(c, "k_collide");
         timing_end(c);
         if (cge_status s = check(c, hipGetLastError(), "step kernel launch")) return s;
         c->cur = 1 - c->cur;

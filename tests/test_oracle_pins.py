@@ -560,3 +560,18 @@ def test_wall_thickness_does_not_change_the_fluid():
         o.step(40)
         runs.append(o.populations()[:, :, :, layers:ny - layers, :])
     assert np.array_equal(runs[0], runs[1])
+
+
+def test_threads_do_not_change_the_oracle():
+    """The per-node loops may run on several threads (the CPU baseline's mode): the same bits
+    as one thread, observables included."""
+    w = inputs.workload("sessile3d", shape=(12, 14, 18), radius=5.0, phi=1e-3)
+    runs = []
+    for t in (1, 4):
+        o = Oracle(w["params"], solid=w["solid"], phi_field=w["phi_field"])
+        o.set_threads(t)
+        o.init_equilibrium(w["rho_r"], w["rho_b"])
+        o.step(6)
+        runs.append((o.populations(), o.observables()))
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert runs[0][1] == runs[1][1]
