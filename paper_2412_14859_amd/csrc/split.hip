@@ -327,62 +327,94 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
     }
 }
 
-// Pass 1 from records for D3Q19 with FP32 records: a block takes a 64 x 4 tile of nodes
-// through zc consecutive planes (zm_chunk).  The records of three planes (the tile and one node
-// around it) sit in an LDS ring, with their solid flags beside them when there are walls;
-// the next plane is loaded into registers while the current one is computed, then stored
-// over the plane that is no longer needed.  Each record value then passes through L1 about
-// (zc + 2) / zc x 66 x 6 / (64 x 4) times instead of once per pulling neighbour.  The
-// arithmetic is k_pull_record's, bounce-back included.
-constexpr int kZmX = 64, kZmY = 4;
-constexpr int kZmW = kZmX + 2, kZmH = kZmY + 2;
-constexpr int kZmP = kRec * kZmH * kZmW;  // staged values per plane
-constexpr int kZmT = kZmX * kZmY;
-constexpr int kZmSeg = kRec * kZmH;     // 64-node row segments of a staged plane
-constexpr int kZmSegW = kZmSeg / 4;      // segments per wave
-constexpr int kZmPer = kZmSegW + 1;      // staged values per thread and plane (+ halo)
-constexpr int kZmF = kZmH * kZmW;        // staged flags per plane (two per thread at most)
-static_assert(kZmSeg % 4 == 0 && 2 * kZmSeg <= kZmT && kZmF <= 2 * kZmT, "staging layout");
+// Pass 1 from records for D3Q19 with FP32 records: a block takes a 64 x TY tile of nodes
+// through zc consecutive planes (zm_chunk).  One plane of records (the tile and one node
+// around it) is staged in LDS at a time, in two buffers: while plane p is read, plane p + 1
+// is loaded into registers and then stored into the other buffer, one barrier per plane.
+// Each thread keeps the partial moments of its nodes in planes p - 1, p and p + 1: staged
+// plane p gives node p - 1 its directions with c_z = -1 (the node is then complete and
+// finished), node p those with c_z = 0 and node p + 1 those with c_z = +1.  Every pulled
+// population is rebuilt once, as in k_pull_record, and summed in the order in which the
+// planes arrive.  With walls the solid flags of planes p - 1 .. p + 1 sit in a ring of four
+// beside the records, and a direction whose source is solid takes the node's own record
+// (halfway bounce-back) while the node's own plane is staged.  Staging one plane instead of
+// three lets taller tiles fit (fewer halo rows per node) with more waves per CU.
+template <int TY>
+struct Zm {
+    static constexpr int X = 64, W = X + 2, H = TY + 2;
+    static constexpr int T = X * TY;                // threads
+    static constexpr int P = kRec * H * W;          // staged floats per buffer
+    static constexpr int HaloSeg = 2 * kRec;        // 64-node segments of the two halo rows
+    static constexpr int F = H * W;                 // staged flags per plane
+    // blocks per CU as the LDS allows (two buffers of records, four of flags, the block
+    // reduction)
+    static constexpr int LdsBytes = 2 * P * 4 + 4 * F + 256;
+    static constexpr int PerCU = (160 * 1024) / LdsBytes < 2048 / T ? (160 * 1024) / LdsBytes
+                                                                     : 2048 / T;
+    static constexpr int Waves = PerCU * TY / 4;    // waves per SIMD
+    static_assert(2 * kRec * H <= T && F <= 2 * T && PerCU >= 1, "staging layout");
+};
+constexpr int kZmY = 8;
 
-// Site data of a node read ahead of its pull: the carried mask byte or ||F|| (as site_weight
-// reads it) and the node's flux (node_phi).  The z-marching pass issues these loads before
-// a plane's record loads, so their latency overlaps the pull instead of following it.
+// Site data of a node read a plane ahead of its finish, as loaded: the carried mask byte or
+// the bits of ||F|| (as site_weight reads them) and the node's flux as stored (node_phi).
+// Nothing is converted at the load, so no wait for it follows until the node is finished.
+template <typename S>
+struct SiteRaw {
+    double c2;     // ||F|| (soft rule)
+    uint32_t c0;   // mask byte (gradient rule)
+    PhiT<S> phi;   // flux of the node (with a flux field)
+};
+
 template <typename S, typename M>
 __device__ __forceinline__ void site_ahead(const Phys<M>& P, const void* __restrict__ carry,
                                            const void* __restrict__ phi_field, long long n,
-                                           double& c, M& phi) {
-    c = P.site_rule == 2 ? static_cast<const double*>(carry)[n]
-                         : (P.site_rule == 0 ? static_cast<double>(static_cast<const uint8_t*>(carry)[n])
-                                             : 0.0);
-    phi = node_phi<S, M>(P, phi_field, n);
+                                           SiteRaw<S>& r) {
+    if (P.site_rule == 2) r.c2 = static_cast<const double*>(carry)[n];
+    if (P.site_rule == 0) r.c0 = static_cast<const uint8_t*>(carry)[n];
+    if (phi_field) r.phi = static_cast<const PhiT<S>*>(phi_field)[n];
 }
 
 // site_sink on the data site_ahead read: the same weight and sink arithmetic.
-template <typename M>
-__device__ __forceinline__ M site_sink_ahead(const Phys<M>& P, double c, M phi, M rho, M dsum,
+template <typename S, typename M>
+__device__ __forceinline__ M site_sink_ahead(const Phys<M>& P, const SiteRaw<S>& r,
+                                             const void* __restrict__ phi_field, M rho, M dsum,
                                              M& w) {
-    if (P.site_rule == 2) w = M(1) / (M(1) + exp(-(static_cast<M>(c) - P.gamma) * P.inv_kappa));
-    else if (P.site_rule == 0) w = c != 0.0 ? M(1) : M(0);
+    if (P.site_rule == 2) w = M(1) / (M(1) + exp(-(static_cast<M>(r.c2) - P.gamma) * P.inv_kappa));
+    else if (P.site_rule == 0) w = r.c0 != 0u ? M(1) : M(0);
     else w = fabs(dsum / rho) < P.gamma ? M(1) : M(0);
     if (w == M(0)) return M(0);
+    const M phi = phi_field ? static_cast<M>(r.phi) : P.phi;
     return w * (phi * P.inv_sbar);
 }
 
-template <typename S, typename M, bool WALLS>
-__global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_pull_record_zm(const float* __restrict__ rec,
-                                                         const uint8_t* __restrict__ flags,
-                                                         const void* __restrict__ carry,
-                                                         const void* __restrict__ phi_field,
-                                                         float* __restrict__ rhoN,
-                                                         float* __restrict__ mom,
-                                                         double* __restrict__ acc_sink,
-                                                         long long* __restrict__ acc_sites,
-                                                         Geo g, Phys<M> P, int zc) {
+// Partial moments of one node: delta rho, the colour sum, j and the pulled rho^N per weight
+// class (ref_part).
+template <typename M>
+struct PullSums {
+    M drho, dsum, j[3], rn[3];
+    __device__ __forceinline__ void clear() {
+        drho = dsum = M(0);
+        j[0] = j[1] = j[2] = M(0);
+        rn[0] = rn[1] = rn[2] = M(0);
+    }
+};
+
+template <typename S, typename M, bool WALLS, int TY>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(Zm<TY>::Waves, Zm<TY>::Waves))) void
+k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flags,
+                 const void* __restrict__ carry, const void* __restrict__ phi_field,
+                 float* __restrict__ rhoN, float* __restrict__ mom, double* __restrict__ acc_sink,
+                 long long* __restrict__ acc_sites, Geo g, Phys<M> P, int zc) {
     constexpr int Q = 19;
     using L = RecLayout<float>;
-    __shared__ float ring[3 * kZmP];
-    __shared__ uint8_t fring[WALLS ? 3 * kZmF : 1];  // solid flags of the ring's planes
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kZmX * ty;
+    using Z = Zm<TY>;
+    // the two record buffers (plane p in ring0 when p - z0 is odd) and the flags of plane p
+    // in slot p & 3 of fring
+    __shared__ float ring0[Z::P];
+    __shared__ float ring1[Z::P];
+    __shared__ uint8_t fring[WALLS ? 4 * Z::F : 1];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + Z::X * ty;
     // tiles in XCD-contiguous order: XCD k (blocks are dealt round-robin by id) takes a run of
     // consecutive tiles, x fastest, then y, then the z-chunk, so tiles that share halo rows and
     // columns read them through the same L2 at about the same time
@@ -393,161 +425,210 @@ __global__ __launch_bounds__(kZmT) __attribute__((amdgpu_waves_per_eu(2, 2))) vo
     const int bx = __builtin_amdgcn_readfirstlane((int)(tile % gridDim.x));
     const int by = __builtin_amdgcn_readfirstlane((int)((tile / gridDim.x) % gridDim.y));
     const int bz = __builtin_amdgcn_readfirstlane((int)(tile / (gridDim.x * gridDim.y)));
-    const int x0 = bx * kZmX, y0 = by * kZmY;
+    const int x0 = bx * Z::X, y0 = by * TY;
     const int z0 = bz * zc, z1 = min(z0 + zc, g.nz);
     const long long rlen = L::row_len(g.nx);
     const long long plane = (long long)g.ny * rlen;
-    // Staging of one plane: the tile's rows (value sl, row ry) are kZmSeg segments of 64
-    // nodes; wave w loads segments w, w + 4, ... with one lane per node (the segment base is
-    // uniform), and threads tid < 2 kZmSeg load the two halo columns x0 - 1 and x0 + 64.
+    // Staging of one plane: row ry of value sl of the window (64 nodes) is row sl H + ry of a
+    // buffer.  The rows are copied from HBM straight into LDS (global_load_lds: lane l's value
+    // lands at the row's LDS base + 4 l, so a row takes one uniform LDS address and no
+    // registers): wave w copies window row w + 1 (a row of the tile) of every value, from one
+    // scalar row address with the value's 256-byte chunk slot as the immediate offset, and
+    // the Z::HaloSeg rows 0 and H - 1 of the values are shared out over the waves.  Threads
+    // tid < 2 kRec H load the two halo columns x0 - 1 and x0 + 64 through a register.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const uint32_t xin = L::in_row(wrapm(x0 + lane, g.nx)) * (uint32_t)sizeof(float);
     const int hseg = tid >> 1, hside = tid & 1;
-    const bool halo = tid < 2 * kZmSeg;
+    const bool halo = tid < 2 * kRec * Z::H;
     const uint32_t hoff =
-        halo ? (uint32_t)(((long long)wrapm(y0 - 1 + hseg % kZmH, g.ny) * rlen +
-                           L::in_row(wrapm(hside ? x0 + kZmX : x0 - 1, g.nx)) +
-                           (hseg / kZmH) * L::W) * (long long)sizeof(float))
+        halo ? (uint32_t)(((long long)wrapm(y0 - 1 + hseg % Z::H, g.ny) * rlen +
+                           L::in_row(wrapm(hside ? x0 + Z::X : x0 - 1, g.nx)) +
+                           (hseg / Z::H) * L::W) * (long long)sizeof(float))
              : 0u;
-    const int hlds = hseg * kZmW + (hside ? kZmW - 1 : 0);
-    // plane-relative byte offsets of the segments (below 2^31: checked at launch), read back
-    // as LDS broadcasts
-    __shared__ int segoff[kZmSeg];
-    if (tid < kZmSeg)
-        segoff[tid] = (int)(((long long)wrapm(y0 - 1 + tid % kZmH, g.ny) * rlen +
-                             (tid / kZmH) * L::W) * (long long)sizeof(float));
-    __syncthreads();
-    // flags: positions tid and tid + kZmT of the (kZmH x kZmW) plane window, in-plane index
+    const int hlds = hseg * Z::W + (hside ? Z::W - 1 : 0);
+    // plane-relative byte offsets (below 2^31: checked at launch) of the wave's tile row and of
+    // the two halo rows
+    const uint32_t row_own = (uint32_t)((long long)wrapm(y0 + wave, g.ny) * rlen * 4);
+    const uint32_t row_lo = (uint32_t)((long long)wrapm(y0 - 1, g.ny) * rlen * 4);
+    const uint32_t row_hi = (uint32_t)((long long)wrapm(y0 + TY, g.ny) * rlen * 4);
+    // flags: positions tid and tid + Z::T of the (H x W) plane window, in-plane index
     long long fo[2] = {0, 0};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int pos = tid + kZmT * h;
-        if (WALLS && pos < kZmF)
-            fo[h] = wrapm(x0 - 1 + pos % kZmW, g.nx) +
-                    (long long)g.nx * wrapm(y0 - 1 + pos / kZmW, g.ny);
+        const int pos = tid + Z::T * h;
+        if (WALLS && pos < Z::F)
+            fo[h] = wrapm(x0 - 1 + pos % Z::W, g.nx) +
+                    (long long)g.nx * wrapm(y0 - 1 + pos / Z::W, g.ny);
     }
-    const long long fplane = (long long)g.nx * g.ny;
-    auto load_plane = [&](int zp, float (&buf)[kZmPer], uint8_t (&fb)[2]) {
-        const float* base = rec + (long long)wrapc(zp, g.nz) * plane;
-#pragma unroll
-        for (int m = 0; m < kZmSegW; ++m) buf[m] = ld_at(base, (uint32_t)segoff[wave + 4 * m] + xin);
-        if (halo) buf[kZmSegW] = ld_at(base, hoff);
-        if constexpr (WALLS) {
-            const uint8_t* fbase = flags + (long long)wrapc(zp, g.nz) * fplane;
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                if (tid + kZmT * h < kZmF) fb[h] = fbase[fo[h]];
-        }
-    };
-    auto store_plane = [&](int slot, const float (&buf)[kZmPer], const uint8_t (&fb)[2]) {
-        float* r = ring + slot * kZmP;
-#pragma unroll
-        for (int m = 0; m < kZmSegW; ++m) r[(wave + 4 * m) * kZmW + 1 + lane] = buf[m];
-        if (halo) r[hlds] = buf[kZmSegW];
-        if constexpr (WALLS) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                if (tid + kZmT * h < kZmF) fring[slot * kZmF + tid + kZmT * h] = fb[h];
-        }
-    };
-    float buf[kZmPer];
-    uint8_t fbuf[2] = {0, 0};
-    load_plane(z0 - 1, buf, fbuf);
-    store_plane(0, buf, fbuf);
-    load_plane(z0, buf, fbuf);
-    store_plane(1, buf, fbuf);
-    load_plane(z0 + 1, buf, fbuf);
-    store_plane(2, buf, fbuf);
     __syncthreads();
+    const long long fplane = (long long)g.nx * g.ny;
+    // start the copy of plane zp into dst; its halo columns come back in hb
+    auto issue_plane = [&](int zp, float* dst, float& hb) {
+        const char* base = reinterpret_cast<const char*>(rec + (long long)wrapm(zp, g.nz) * plane);
+        const char* own = base + row_own;
+#pragma unroll
+        for (int sl = 0; sl < kRec; ++sl)
+            __builtin_amdgcn_global_load_lds(own + xin + sl * L::W * 4,
+                                             dst + (sl * Z::H + 1 + wave) * Z::W + 1, 4, 0, 0);
+#pragma unroll
+        for (int m = 0; m < (Z::HaloSeg + TY - 1) / TY; ++m) {
+            const int k = wave + TY * m;  // halo row segment: value k % kRec, row 0 or H - 1
+            if (k < Z::HaloSeg) {
+                const int sl = k % kRec, hi = k / kRec;
+                __builtin_amdgcn_global_load_lds(
+                    base + (hi ? row_hi : row_lo) + sl * L::W * 4 + xin,
+                    dst + (sl * Z::H + (hi ? Z::H - 1 : 0)) * Z::W + 1, 4, 0, 0);
+            }
+        }
+        if (halo) hb = ld_at(reinterpret_cast<const float*>(base), hoff);
+    };
+    auto load_flags = [&](int zp, uint8_t (&fb)[2]) {
+        const uint8_t* fbase = flags + (long long)wrapm(zp, g.nz) * fplane;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (tid + Z::T * h < Z::F) fb[h] = fbase[fo[h]];
+    };
+    auto store_flags = [&](int zp, const uint8_t (&fb)[2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (tid + Z::T * h < Z::F) fring[(zp & 3) * Z::F + tid + Z::T * h] = fb[h];
+    };
+    // the copies into LDS are complete (s_waitcnt 0) before the barrier publishes them
+    auto publish = [&]() {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+    {
+        float hb = 0.0f;
+        issue_plane(z0 - 1, ring0, hb);
+        if (halo) ring0[hlds] = hb;
+        uint8_t fb[2] = {0, 0};
+        if constexpr (WALLS) {
+            load_flags(z0 - 1, fb);
+            store_flags(z0 - 1, fb);
+            load_flags(z0, fb);
+            store_flags(z0, fb);
+        }
+        publish();
+    }
     const int x = x0 + tx, y = y0 + ty;
     const bool valid = x < g.nx && y < g.ny;
+    const int cen = (ty + 1) * Z::W + (tx + 1);
+    auto solid = [&](int zp, int at) { return WALLS && fring[(zp & 3) * Z::F + at] != 0; };
+    auto node = [&](int zp) { return x + (long long)g.nx * (y + (long long)g.ny * zp); };
+    // direction i of a node from the record at src (sgn -1: the node's own, bounce-back)
+    auto add = [&](PullSums<M>& s, int i, const float* src, float sgn) {
+        float ar, dr, rr;
+        record_dir<Q, float>(i, sgn, [&](int sl) { return src[sl * Z::H * Z::W]; }, ar, dr, rr);
+        const M a = static_cast<M>(ar);
+        s.drho += a;
+        s.dsum += static_cast<M>(dr);
+        s.rn[norm2<Q>(i)] += static_cast<M>(rr);
+        if (Lat<Q>::cx[i]) s.j[0] += Lat<Q>::cx[i] * a;
+        if (Lat<Q>::cy[i]) s.j[1] += Lat<Q>::cy[i] * a;
+        if (Lat<Q>::cz[i]) s.j[2] += Lat<Q>::cz[i] * a;
+        // one direction at a time: the empty asm makes the sums of this direction exist here
+        // (otherwise they sink to the node's finish and every direction's record values stay
+        // live until then), and the scheduling barrier keeps the LDS reads of later
+        // directions from being hoisted above it
+        asm volatile("" : "+v"(s.drho), "+v"(s.dsum), "+v"(s.j[0]), "+v"(s.j[1]), "+v"(s.j[2]),
+                     "+v"(s.rn[0]), "+v"(s.rn[1]), "+v"(s.rn[2]));
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    PullSums<M> sa, sb;  // nodes p - 1 and p
+    sa.clear();
+    sb.clear();
+    SiteRaw<S> site_fin{0.0, 0u, PhiT<S>(0)};
     double v[2] = {0.0, 0.0};
-    int sm = 0, sc = 1, sp = 2;  // ring slots of planes z - 1, z, z + 1
-    for (int z = z0; z < z1; ++z) {
-        const bool next = z + 1 < z1;
-        const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
-        // solid nodes hold no state and are skipped, as in k_pull_record
-        const bool fluid =
-            valid && !(WALLS && fring[sc * kZmF + (ty + 1) * kZmW + (tx + 1)]);
-        double cpre = 0.0;
-        M phin = M(0);
-        if (fluid) site_ahead<S, M>(P, carry, phi_field, n, cpre, phin);
-        if (next) load_plane(z + 2, buf, fbuf);
-        if (fluid) {
-            M j[3] = {M(0), M(0), M(0)}, drho = M(0), dsum = M(0), rn[3] = {M(0), M(0), M(0)};
-            const int slot[3] = {sp, sc, sm};  // plane of x - c_i by c_z = -1, 0, +1
+    // one plane: pl holds plane p, the copy of plane p + 1 goes to nxt
+    auto march = [&](int p, const float* pl, float* nxt) {
+        const bool next = p < z1;
+        const bool own = valid && p >= z0 && p < z1 && !solid(p, cen);
+        SiteRaw<S> site_next{0.0, 0u, PhiT<S>(0)};
+        if (own) site_ahead<S, M>(P, carry, phi_field, node(p), site_next);
+        float hb = 0.0f;
+        uint8_t fb[2] = {0, 0};
+        if (next) {
+            issue_plane(p + 1, nxt, hb);
+            if constexpr (WALLS) load_flags(p + 2, fb);
+        }
+        // node p - 1: the directions with c_z = -1, then the node is complete
+        if (p - 1 >= z0 && valid && !solid(p - 1, cen)) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (Lat<Q>::cz[i] != -1) continue;
+                const int at = (ty + 1 - Lat<Q>::cy[i]) * Z::W + (tx + 1 - Lat<Q>::cx[i]);
+                if (!solid(p, at)) add(sa, i, pl + at, 1.0f);
+            }
+            const M dsum = sa.dsum + ref_part<Q, M>(P, sa.rn);
+            const M rho = P.rho_ref + sa.drho;
+            M wgt;
+            const M s = site_sink_ahead<S, M>(P, site_fin, phi_field, rho, dsum, wgt);
+            const long long n = node(p - 1);
+            v[0] += static_cast<double>(s);
+            v[1] += is_site(wgt) ? 1.0 : 0.0;
+            rhoN[n] = static_cast<float>((dsum - M(2) * s) / rho);
+            mom[n] = static_cast<float>(sa.drho);
+            mom[g.N + n] = static_cast<float>(sa.j[0]);
+            mom[2 * g.N + n] = static_cast<float>(sa.j[1]);
+            mom[3 * g.N + n] = static_cast<float>(sa.j[2]);
+        }
+        // node p: the directions with c_z = 0, and every direction whose source is solid
+        if (own) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
-                const int at = (ty + 1 - cy) * kZmW + (tx + 1 - cx);
-                const float* src = ring + slot[1 + cz] * kZmP + at;
-                float sgn = 1.0f;
-                // halfway bounce-back: from a solid x - c_i the node's own f_opp(i)*
-                if (WALLS && i != 0 && fring[slot[1 + cz] * kZmF + at]) {
-                    src = ring + sc * kZmP + (ty + 1) * kZmW + (tx + 1);
-                    sgn = -1.0f;
-                }
-                float ar, dr, rr;
-                record_dir<Q, float>(i, sgn, [&](int sl) { return src[sl * kZmH * kZmW]; }, ar,
-                                     dr, rr);
-                const M a = static_cast<M>(ar);
-                drho += a;
-                dsum += static_cast<M>(dr);
-                rn[norm2<Q>(i)] += static_cast<M>(rr);
-                if (cx) j[0] += cx * a;
-                if (cy) j[1] += cy * a;
-                if (cz) j[2] += cz * a;
-                // one direction at a time: keeps the LDS reads of later directions from being
-                // hoisted into registers (the block's LDS already limits it to 2 waves per SIMD)
-                __builtin_amdgcn_sched_barrier(0);
+                const int at = (ty + 1 - cy) * Z::W + (tx + 1 - cx);
+                if (i != 0 && solid(p - cz, at)) add(sb, i, pl + cen, -1.0f);
+                else if (cz == 0) add(sb, i, pl + at, 1.0f);
             }
-            dsum += ref_part<Q, M>(P, rn);
-            const M rho = P.rho_ref + drho;
-            M wgt;
-            const M s = site_sink_ahead<M>(P, cpre, phin, rho, dsum, wgt);
-            dsum -= M(2) * s;
-            v[0] += static_cast<double>(s);
-            v[1] += is_site(wgt) ? 1.0 : 0.0;
-            rhoN[n] = static_cast<float>(dsum / rho);
-            mom[n] = static_cast<float>(drho);
-            mom[g.N + n] = static_cast<float>(j[0]);
-            mom[2 * g.N + n] = static_cast<float>(j[1]);
-            mom[3 * g.N + n] = static_cast<float>(j[2]);
         }
-        __syncthreads();  // every read of plane z - 1 is done
-        if (next) store_plane(sm, buf, fbuf);
-        __syncthreads();
-        const int t = sm;
-        sm = sc;
-        sc = sp;
-        sp = t;
+        // node p + 1: the directions with c_z = +1 (sa is free again)
+        sa = sb;
+        sb.clear();
+        if (p + 1 < z1 && valid && !solid(p + 1, cen)) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (Lat<Q>::cz[i] != 1) continue;
+                const int at = (ty + 1 - Lat<Q>::cy[i]) * Z::W + (tx + 1 - Lat<Q>::cx[i]);
+                if (!solid(p, at)) add(sb, i, pl + at, 1.0f);
+            }
+        }
+        site_fin = site_next;
+        if (next) {
+            if (halo) nxt[hlds] = hb;
+            if constexpr (WALLS) store_flags(p + 2, fb);
+        }
+        publish();
+    };
+    for (int p = z0 - 1; p <= z1; p += 2) {
+        march(p, ring0, ring1);
+        if (p + 1 <= z1) march(p + 1, ring1, ring0);
     }
     const bool is_max[2] = {false, false};
     double out[2];
-    block_reduce<2>(v, is_max, tid, kZmT, out);
+    block_reduce<2>(v, is_max, tid, Z::T, out);
     if (tid == 0) {
         acc_sink[bid] += out[0];
         acc_sites[bid] += static_cast<long long>(out[1]);
     }
 }
 
-// Planes per z-chunk.  A chunk's first three planes are loaded before any is computed, and
-// blocks run in rounds of two per CU (two fit a CU's LDS), so the pass takes about
-// rounds x (planes per chunk + 3) plane-times; the chunk count that minimises this is taken.
-// At 256^3 that is 2 chunks of 128 planes (measured per step: 32 planes 0.72 ms, 64 0.70,
-// 128 0.69); at 192^3 7 chunks of 28 (32 planes: 0.47 ms, 48 planes, whose 576 blocks leave
-// a second round nearly empty: 0.58 ms).
+// Planes per z-chunk.  A chunk's blocks stage zc + 2 planes, and blocks run in rounds of
+// Zm::PerCU per CU, so the pass takes about rounds x (planes per chunk + 2) plane-times; the
+// chunk count that minimises this is taken.
 static int zm_chunk(const cge_ctx* c) {
+    using Z = Zm<kZmY>;
     const Geo& g = c->g;
     if (c->zchunk > 0) return c->zchunk < g.nz ? c->zchunk : g.nz;
-    const long long tiles = (long long)((g.nx + kZmX - 1) / kZmX) * ((g.ny + kZmY - 1) / kZmY);
-    const long long slots = 2ll * (c->cus > 0 ? c->cus : 1);
+    const long long tiles = (long long)((g.nx + Z::X - 1) / Z::X) * ((g.ny + kZmY - 1) / kZmY);
+    const long long slots = (long long)Z::PerCU * (c->cus > 0 ? c->cus : 1);
     long long best = -1, best_zc = g.nz;
     for (long long chunks = 1; chunks <= g.nz && chunks <= 4096; ++chunks) {
         const long long zc = (g.nz + chunks - 1) / chunks;
         const long long used = (g.nz + zc - 1) / zc;  // chunks of zc planes that cover nz
         const long long rounds = (tiles * used + slots - 1) / slots;
-        const long long cost = rounds * (zc + 3);
+        const long long cost = rounds * (zc + 2);
         if (best < 0 || cost < best) {
             best = cost;
             best_zc = zc;
@@ -557,7 +638,8 @@ static int zm_chunk(const cge_ctx* c) {
 }
 
 static dim3 zm_grid(const Geo& g, int zc) {
-    return dim3((g.nx + kZmX - 1) / kZmX, (g.ny + kZmY - 1) / kZmY, (g.nz + zc - 1) / zc);
+    return dim3((g.nx + Zm<kZmY>::X - 1) / Zm<kZmY>::X, (g.ny + kZmY - 1) / kZmY,
+                (g.nz + zc - 1) / zc);
 }
 
 // Pass 2 to records: gradient and moments as k_finish, then the node's record instead of its
@@ -700,8 +782,8 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
         if constexpr (Q == 19 && std::is_same<MomT<S>, float>::value) {
             if (zm_ok(c)) {
                 const int zc = zm_chunk(c);
-                hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS>), zm_grid(c->g, zc),
-                                   dim3(kZmX, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
+                hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS, kZmY>), zm_grid(c->g, zc),
+                                   dim3(Zm<kZmY>::X, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
                                    c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P,
                                    zc);
                 marched = true;

@@ -10,7 +10,7 @@ the rounding of the record and of the rebuilt populations:
     FP32 values and the FP32 rebuild of each pulled population, against the split form's
     FP32-stored populations), the same sites and sink total to 1e-9 (1e-7 with the soft
     site rule, whose logistic weights amplify rounding differences of ||F|| by 1 / kappa).
-Shapes cover the z-marching pull of D3Q19 at FP32 storage (64 x 4 tiles) with ragged tiles,
+Shapes cover the z-marching pull of D3Q19 at FP32 storage (64 x 8 tiles) with ragged tiles,
 chunks of 1, 3, 5 and 32 planes (forced with cge_set_zchunk: on a 256-CU device the automatic
 choice gives these small grids one plane per chunk) with ragged last chunks, one and two
 planes and solid nodes, and the general pull: D2Q9, FP64, the |rho^N| < Gamma and soft site
