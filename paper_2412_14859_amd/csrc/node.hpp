@@ -496,6 +496,20 @@ __device__ __forceinline__ void record_dir(int i, E sgn, Load&& L, E& a, E& dp, 
     dp = rn * a + L(k == 1 ? kG1 : kG2) * Fc;
 }
 
+// The record slots record_dir reads for direction i (bit sl set), for callers that load them
+// ahead of the call.
+template <int Q>
+__host__ __device__ constexpr uint32_t dir_slots(int i) {
+    const int k = norm2<Q>(i);
+    if (k == 0) return (1u << kRhoN) | (1u << kB0);
+    uint32_t m = (1u << kRhoN) | (1u << (k == 1 ? kB1 : kB2)) | (1u << kA3) | (1u << kP1) |
+                 (1u << (k == 1 ? kG1 : kG2));
+    if (Lat<Q>::cx[i]) m |= (1u << kUx) | (1u << kFx);
+    if (Lat<Q>::cy[i]) m |= (1u << kUy) | (1u << kFy);
+    if (Lat<Q>::cz[i]) m |= (1u << kUz) | (1u << kFz);
+    return m;
+}
+
 // Neutral wetting: a solid node takes the W-weighted mean of rho^N over its fluid neighbours.
 template <int Q, typename R>
 __global__ __launch_bounds__(kTPBX) void k_wet(const uint8_t* __restrict__ flags,

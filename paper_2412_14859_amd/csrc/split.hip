@@ -330,15 +330,15 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
 // Pass 1 from records for D3Q19 with FP32 records: a block takes a 64 x TY tile of nodes
 // through zc consecutive planes (zm_chunk).  One plane of records (the tile and one node
 // around it) is staged in LDS at a time, in two buffers: while plane p is read, plane p + 1
-// is loaded into registers and then stored into the other buffer, one barrier per plane.
-// Each thread keeps the partial moments of its nodes in planes p - 1, p and p + 1: staged
-// plane p gives node p - 1 its directions with c_z = -1 (the node is then complete and
-// finished), node p those with c_z = 0 and node p + 1 those with c_z = +1.  Every pulled
-// population is rebuilt once, as in k_pull_record, and summed in the order in which the
-// planes arrive.  With walls the solid flags of planes p - 1 .. p + 1 sit in a ring of four
-// beside the records, and a direction whose source is solid takes the node's own record
-// (halfway bounce-back) while the node's own plane is staged.  Staging one plane instead of
-// three lets taller tiles fit (fewer halo rows per node) with more waves per CU.
+// is copied into the other buffer, one barrier per plane.  Each thread keeps the partial
+// moments of its nodes in planes p - 1, p and p + 1: staged plane p gives node p - 1 its
+// directions with c_z = -1 (the node is then complete and finished), node p those with
+// c_z = 0 and node p + 1 those with c_z = +1.  Every pulled population is rebuilt once, as
+// in k_pull_record, and summed in the order in which the planes arrive (PullSums gives the
+// precision of the sums).  With walls the solid flags of planes p - 1 .. p + 1 sit in a
+// ring of four beside the records, and a direction whose source is solid takes the node's
+// own record (halfway bounce-back) while the node's own plane is staged.  Staging one plane
+// instead of three lets taller tiles fit (fewer halo rows per node) with more waves per CU.
 template <int TY>
 struct Zm {
     static constexpr int X = 64, W = X + 2, H = TY + 2;
@@ -388,17 +388,33 @@ __device__ __forceinline__ M site_sink_ahead(const Phys<M>& P, const SiteRaw<S>&
     return w * (phi * P.inv_sbar);
 }
 
-// Partial moments of one node: delta rho, the colour sum, j and the pulled rho^N per weight
-// class (ref_part).
+// Partial moments of one node: delta rho, the colour sum and j in FP32, and the pulled rho^N
+// per weight class (ref_part) in the arithmetic type.  The FP32 sums take 5 to 9 FP32
+// rebuilds of FP32 record values and are stored as FP32 moments straight after, so they
+// add a few units in the last place before that rounding; the class sums of rho^N, which
+// ref_part weights by t_ref,k, stay in M, where FP32 rounding would repeat at every node and
+// step.
 template <typename M>
 struct PullSums {
-    M drho, dsum, j[3], rn[3];
+    float drho, dsum, j[3];
+    M rn[3];
     __device__ __forceinline__ void clear() {
-        drho = dsum = M(0);
-        j[0] = j[1] = j[2] = M(0);
+        drho = dsum = 0.0f;
+        j[0] = j[1] = j[2] = 0.0f;
         rn[0] = rn[1] = rn[2] = M(0);
     }
 };
+
+// The D3Q19 directions with c_z = cz, in index order.
+struct CzList {
+    int n, i[9];
+};
+constexpr CzList cz_list(int cz) {
+    CzList l{0, {0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    for (int d = 0; d < 19; ++d)
+        if (Lat<19>::cz[d] == cz) l.i[l.n++] = d;
+    return l;
+}
 
 template <typename S, typename M, bool WALLS, int TY>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(Zm<TY>::Waves, Zm<TY>::Waves))) void
@@ -516,32 +532,63 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
     const int cen = (ty + 1) * Z::W + (tx + 1);
     auto solid = [&](int zp, int at) { return WALLS && fring[(zp & 3) * Z::F + at] != 0; };
     auto node = [&](int zp) { return x + (long long)g.nx * (y + (long long)g.ny * zp); };
-    // direction i of a node from the record at src (sgn -1: the node's own, bounce-back)
-    auto add = [&](PullSums<M>& s, int i, const float* src, float sgn) {
+    // The record values direction i reads from its source (dir_slots); without walls they are
+    // fetched one direction ahead of their use, so the LDS latency of one direction overlaps
+    // the arithmetic of the previous one.
+    auto fetch = [&](int i, const float* src, float (&r)[kRec]) {
+#pragma unroll
+        for (int sl = 0; sl < kRec; ++sl)
+            if ((dir_slots<Q>(i) >> sl) & 1u) r[sl] = src[sl * Z::H * Z::W];
+    };
+    // direction i of a node from fetched record values (sgn -1: the node's own, bounce-back)
+    auto accum = [&](PullSums<M>& s, int i, const float (&r)[kRec], float sgn) {
         float ar, dr, rr;
-        record_dir<Q, float>(i, sgn, [&](int sl) { return src[sl * Z::H * Z::W]; }, ar, dr, rr);
-        const M a = static_cast<M>(ar);
-        s.drho += a;
-        s.dsum += static_cast<M>(dr);
+        record_dir<Q, float>(i, sgn, [&](int sl) { return r[sl]; }, ar, dr, rr);
+        s.drho += ar;
+        s.dsum += dr;
         s.rn[norm2<Q>(i)] += static_cast<M>(rr);
-        if (Lat<Q>::cx[i]) s.j[0] += Lat<Q>::cx[i] * a;
-        if (Lat<Q>::cy[i]) s.j[1] += Lat<Q>::cy[i] * a;
-        if (Lat<Q>::cz[i]) s.j[2] += Lat<Q>::cz[i] * a;
-        // one direction at a time: the empty asm makes the sums of this direction exist here
-        // (otherwise they sink to the node's finish and every direction's record values stay
-        // live until then), and the scheduling barrier keeps the LDS reads of later
-        // directions from being hoisted above it
+        if (Lat<Q>::cx[i]) s.j[0] += Lat<Q>::cx[i] * ar;
+        if (Lat<Q>::cy[i]) s.j[1] += Lat<Q>::cy[i] * ar;
+        if (Lat<Q>::cz[i]) s.j[2] += Lat<Q>::cz[i] * ar;
+        // the empty asm makes the sums of this direction exist here (otherwise they sink to the
+        // node's finish and every direction's record values stay live until then)
         asm volatile("" : "+v"(s.drho), "+v"(s.dsum), "+v"(s.j[0]), "+v"(s.j[1]), "+v"(s.j[2]),
                      "+v"(s.rn[0]), "+v"(s.rn[1]), "+v"(s.rn[2]));
-        __builtin_amdgcn_sched_barrier(0);
     };
-    PullSums<M> sa, sb;  // nodes p - 1 and p
+    // The directions with c_z = CZ (the tag's value) into s: direction i from the record at
+    // src_of(i) with sign sgn_of(i), skipped where take(i) is false.
+    auto stage = [&](PullSums<M>& s, auto cz_tag, auto src_of, auto sgn_of, auto take) {
+        constexpr CzList D = cz_list(decltype(cz_tag)::value);
+        float r0[kRec], r1[kRec];
+        if constexpr (WALLS) {  // no look-ahead: the flag ring leaves too few registers
+#pragma unroll
+            for (int k = 0; k < D.n; ++k) {
+                fetch(D.i[k], src_of(D.i[k]), r0);
+                if (take(D.i[k])) accum(s, D.i[k], r0, sgn_of(D.i[k]));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+            fetch(D.i[0], src_of(D.i[0]), r0);
+#pragma unroll
+            for (int k = 0; k < D.n; ++k) {
+                if (k + 1 < D.n) fetch(D.i[k + 1], src_of(D.i[k + 1]), (k & 1) ? r0 : r1);
+                if (take(D.i[k])) accum(s, D.i[k], (k & 1) ? r1 : r0, sgn_of(D.i[k]));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+    using Down = std::integral_constant<int, -1>;
+    using Level = std::integral_constant<int, 0>;
+    using Up = std::integral_constant<int, 1>;
+    auto at_of = [&](int i) { return (ty + 1 - Lat<Q>::cy[i]) * Z::W + (tx + 1 - Lat<Q>::cx[i]); };
+    PullSums<M> sa, sb;
     sa.clear();
     sb.clear();
     SiteRaw<S> site_fin{0.0, 0u, PhiT<S>(0)};
     double v[2] = {0.0, 0.0};
-    // one plane: pl holds plane p, the copy of plane p + 1 goes to nxt
-    auto march = [&](int p, const float* pl, float* nxt) {
+    // One plane: pl holds plane p, the copy of plane p + 1 goes to nxt; prev holds the partial
+    // moments of node p - 1 and cur those of node p, and prev takes node p + 1's afterwards.
+    auto march = [&](int p, const float* pl, float* nxt, PullSums<M>& prev, PullSums<M>& cur) {
         const bool next = p < z1;
         const bool own = valid && p >= z0 && p < z1 && !solid(p, cen);
         SiteRaw<S> site_next{0.0, 0u, PhiT<S>(0)};
@@ -552,48 +599,49 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
             issue_plane(p + 1, nxt, hb);
             if constexpr (WALLS) load_flags(p + 2, fb);
         }
+        auto from_plane = [&](int i) { return pl + at_of(i); };
+        auto plus = [&](int i) { return 1.0f; };
+        auto fluid_src = [&](int i) { return !solid(p, at_of(i)); };
         // node p - 1: the directions with c_z = -1, then the node is complete
         if (p - 1 >= z0 && valid && !solid(p - 1, cen)) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if (Lat<Q>::cz[i] != -1) continue;
-                const int at = (ty + 1 - Lat<Q>::cy[i]) * Z::W + (tx + 1 - Lat<Q>::cx[i]);
-                if (!solid(p, at)) add(sa, i, pl + at, 1.0f);
-            }
-            const M dsum = sa.dsum + ref_part<Q, M>(P, sa.rn);
-            const M rho = P.rho_ref + sa.drho;
+            stage(prev, Down{}, from_plane, plus, fluid_src);
+            const M dsum = static_cast<M>(prev.dsum) + ref_part<Q, M>(P, prev.rn);
+            const M rho = P.rho_ref + static_cast<M>(prev.drho);
             M wgt;
             const M s = site_sink_ahead<S, M>(P, site_fin, phi_field, rho, dsum, wgt);
             const long long n = node(p - 1);
             v[0] += static_cast<double>(s);
             v[1] += is_site(wgt) ? 1.0 : 0.0;
             rhoN[n] = static_cast<float>((dsum - M(2) * s) / rho);
-            mom[n] = static_cast<float>(sa.drho);
-            mom[g.N + n] = static_cast<float>(sa.j[0]);
-            mom[2 * g.N + n] = static_cast<float>(sa.j[1]);
-            mom[3 * g.N + n] = static_cast<float>(sa.j[2]);
+            mom[n] = static_cast<float>(prev.drho);
+            mom[g.N + n] = static_cast<float>(prev.j[0]);
+            mom[2 * g.N + n] = static_cast<float>(prev.j[1]);
+            mom[3 * g.N + n] = static_cast<float>(prev.j[2]);
         }
-        // node p: the directions with c_z = 0, and every direction whose source is solid
+        // node p: the directions with c_z = 0 (from the node's own record where the source is
+        // solid), then those with c_z = +-1 whose source is solid
         if (own) {
+            auto own_or_src = [&](int i) {
+                return (i != 0 && solid(p, at_of(i))) ? pl + cen : pl + at_of(i);
+            };
+            auto own_sgn = [&](int i) { return (i != 0 && solid(p, at_of(i))) ? -1.0f : 1.0f; };
+            auto all = [&](int i) { return true; };
+            stage(cur, Level{}, own_or_src, own_sgn, all);
+            if constexpr (WALLS) {
+                float r[kRec];
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
-                const int at = (ty + 1 - cy) * Z::W + (tx + 1 - cx);
-                if (i != 0 && solid(p - cz, at)) add(sb, i, pl + cen, -1.0f);
-                else if (cz == 0) add(sb, i, pl + at, 1.0f);
+                for (int i = 1; i < Q; ++i) {
+                    if (Lat<Q>::cz[i] == 0 || !solid(p - Lat<Q>::cz[i], at_of(i))) continue;
+                    fetch(i, pl + cen, r);
+                    accum(cur, i, r, -1.0f);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
-        // node p + 1: the directions with c_z = +1 (sa is free again)
-        sa = sb;
-        sb.clear();
-        if (p + 1 < z1 && valid && !solid(p + 1, cen)) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                if (Lat<Q>::cz[i] != 1) continue;
-                const int at = (ty + 1 - Lat<Q>::cy[i]) * Z::W + (tx + 1 - Lat<Q>::cx[i]);
-                if (!solid(p, at)) add(sb, i, pl + at, 1.0f);
-            }
-        }
+        // node p + 1: the directions with c_z = +1
+        prev.clear();
+        if (p + 1 < z1 && valid && !solid(p + 1, cen))
+            stage(prev, Up{}, from_plane, plus, fluid_src);
         site_fin = site_next;
         if (next) {
             if (halo) nxt[hlds] = hb;
@@ -602,8 +650,8 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
         publish();
     };
     for (int p = z0 - 1; p <= z1; p += 2) {
-        march(p, ring0, ring1);
-        if (p + 1 <= z1) march(p + 1, ring1, ring0);
+        march(p, ring0, ring1, sa, sb);
+        if (p + 1 <= z1) march(p + 1, ring1, ring0, sb, sa);
     }
     const bool is_max[2] = {false, false};
     double out[2];
