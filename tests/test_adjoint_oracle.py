@@ -124,3 +124,59 @@ def test_red_mass_sensitivity_with_walls():
     expect = -masks * fl / p["sbar"]
     assert float((masks * fl).sum()) > 0
     assert float((ph.grad - expect).abs().max()) < 1e-13
+
+
+def _c5_instance():
+    """The adjoint benchmark's finite-difference instance: the D2Q9 drop scaled to 32 x 32
+    (R = 6), flux 1e-5 U(0.9, 1.1) (seed 1002), the wobbly target of seed 1003 scaled the same
+    way (r0 = 5.625), soft sites with kappa = 0.01, 200 steps, FP64.  Probes: three random
+    directions (seed 1004) scaled by phi, and eight interface nodes (|rho^N| < 0.5 at the
+    start) drawn with the same generator."""
+    w = case("adjoint2d", (1, 32, 32), site_rule="soft", kappa=0.01)
+    p = w["params"]
+    phi = torch.as_tensor(w["phi_field"], dtype=DT)
+    rng = np.random.default_rng(1004)
+    dirs = [torch.as_tensor(rng.standard_normal(phi.shape), dtype=DT) * phi for _ in range(3)]
+    rhoN0 = (w["rho_r"] - w["rho_b"]) / (w["rho_r"] + w["rho_b"])
+    iface = np.flatnonzero(np.abs(rhoN0) < 0.5)
+    nodes = rng.choice(iface, size=8, replace=False)
+    for k in nodes:
+        v = torch.zeros(phi.numel(), dtype=DT)
+        v[int(k)] = phi.reshape(-1)[int(k)]
+        dirs.append(v.reshape(phi.shape))
+    return w, p, phi, torch.as_tensor(w["target"], dtype=DT), dirs
+
+
+def test_c5_instance_gradients_match_central_differences():
+    """On the finite-difference instance of the adjoint benchmark, <dL/dphi, v> for the three
+    random directions and the eight single interface nodes equals central differences with
+    relative step 1e-3 within 1e-6: over +-1e-3 the loss is linear in phi to below its
+    rounding (the differences agree to 4e-10 .. 3e-8, and move away as the step shrinks and
+    the rounding of L ~ 6.5 grows against the difference), so any wrong term shows far above
+    this bound; at step 1e-4 they still agree within 2e-5.  dL/dGamma is curved enough for
+    the O(eps^2) truncation to show: within 2e-3 at 1e-3 and falling ~100x at 1e-4."""
+    w, p, phi, target, dirs = _c5_instance()
+    n = 200
+    res = A.gradients(p, w["rho_r"], w["rho_b"], phi, n, target)
+    g = res["grad_phi"]
+
+    def loss(ph, gamma=None):
+        gm = None if gamma is None else torch.tensor(gamma, dtype=DT)
+        return float(A.loss_rhoN(A.run(p, w["rho_r"], w["rho_b"], ph, n, gamma=gm), target))
+
+    for k, v in enumerate(dirs):
+        ad = float((g * v).sum())
+        assert ad != 0.0, k
+        err = []
+        for eps in (1e-3, 1e-4):
+            fd = (loss(phi + eps * v) - loss(phi - eps * v)) / (2 * eps)
+            err.append(abs(fd - ad) / abs(ad))
+        assert err[0] < 1e-6 and err[1] < 2e-5, (k, err)
+    gg = res["grad_gamma"]
+    err = []
+    for rel in (1e-3, 1e-4):
+        eps = rel * p["gamma"]
+        fd = (loss(phi, p["gamma"] + eps) - loss(phi, p["gamma"] - eps)) / (2 * eps)
+        err.append(abs(fd - gg) / abs(gg))
+    assert err[0] < 2e-3 and err[1] < 2e-5, err
+    assert err[1] < err[0] / 30 or max(err) < 1e-7, err

@@ -220,16 +220,26 @@ def test_checkpointed_run_does_not_depend_on_the_context_step_form(precision):
         assert r["loss"] == res[0]["loss"]
 
 
-def test_central_differences_on_32x32_soft_sites():
-    """Directional derivatives of the GPU's own FP64 forward (central differences with
-    relative step 1e-3) against the adjoint, for phi and Gamma."""
+def test_c5_instance_central_differences():
+    """The adjoint benchmark's finite-difference instance (tests/test_adjoint_oracle.py,
+    _c5_instance: 32 x 32, R = 6, soft sites kappa = 0.01, 200 steps, FP64, checkpoints every
+    100 steps): the GPU adjoint against central differences of the GPU's own FP64 forward
+    with relative step 1e-3, for the three random directions and the eight interface nodes
+    (within 1e-6: the loss is linear in phi to below its rounding over that step) and for
+    Gamma (within 2e-3: the truncation of the curved Gamma dependence is 3e-5), and against
+    the CPU adjoint reference on the same instance within 1e-10."""
     import torch
-    w = case("adjoint2d", (1, 32, 32), radius=9.0, phi=3e-3, site_rule="soft", kappa=0.02)
-    target = _target((1, 32, 32), 9.5)
-    p = w["params"]
-    nsteps, K = 40, 10
-    _flush("[adjoint FD] d2q9 32x32 soft, 40 steps")
+    from oracle import adjoint as A
+    from tests.test_adjoint_oracle import _c5_instance
+    w, p, phi, target, dirs = _c5_instance()
+    target = target.numpy()
+    nsteps, K = 200, 100
+    _flush("[adjoint FD] C5 instance: d2q9 32x32 soft, 200 steps")
     got = _gpu_gradients(w, target, nsteps, K)
+    ref = A.gradients(p, w["rho_r"], w["rho_b"], phi, nsteps, target)
+    assert _rel(got["grad_phi"], ref["grad_phi"].numpy()) < 1e-10
+    assert abs(got["grad_gamma"] - ref["grad_gamma"]) <= 1e-10 * abs(ref["grad_gamma"])
+    assert abs(got["loss"] - ref["loss"]) <= 1e-12 * abs(ref["loss"])
 
     def loss(phi_field, gamma):
         ww = dict(w, phi_field=phi_field, params=dict(p, gamma=gamma))
@@ -239,18 +249,17 @@ def test_central_differences_on_32x32_soft_sites():
         sim.close()
         return float(((rn - target) ** 2).sum())
 
-    rng = np.random.default_rng(3)
-    for trial in range(2):
-        v = rng.standard_normal(w["phi_field"].shape) * w["phi_field"]
+    eps = 1e-3
+    for k, v in enumerate(dirs):
+        v = v.numpy()
         ad = float((got["grad_phi"] * v).sum())
-        eps = 1e-3
         fd = (loss(w["phi_field"] + eps * v, p["gamma"]) -
               loss(w["phi_field"] - eps * v, p["gamma"])) / (2 * eps)
-        _flush(f"  phi dir {trial}: adjoint {ad:.8e} fd {fd:.8e}")
-        assert abs(fd - ad) <= 2e-3 * abs(ad), (trial, fd, ad)
-    eps = 1e-3 * p["gamma"]
-    fd = (loss(w["phi_field"], p["gamma"] + eps) - loss(w["phi_field"], p["gamma"] - eps)) / (2 * eps)
-    _flush(f"  gamma: adjoint {got['grad_gamma']:.8e} fd {fd:.8e}")
+        _flush(f"  probe {k}: adjoint {ad:.10e} fd {fd:.10e}")
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (k, fd, ad)
+    eg = eps * p["gamma"]
+    fd = (loss(w["phi_field"], p["gamma"] + eg) - loss(w["phi_field"], p["gamma"] - eg)) / (2 * eg)
+    _flush(f"  gamma: adjoint {got['grad_gamma']:.10e} fd {fd:.10e}")
     assert abs(fd - got["grad_gamma"]) <= 2e-3 * abs(got["grad_gamma"])
     del torch
 

@@ -155,12 +155,19 @@ def test_fp64_full_drop2d_2000_steps():
     sim.close()
 
 
-def test_fp32_drop2d_volume_and_frozen_error():
-    """FP32 shifted storage on the 128^2 drop: free run volume within 0.1 % of the oracle's
-    over 2000 steps; frozen-mask population error <= 1e-5 at steps 1, 100, 2000."""
+@pytest.mark.parametrize("precision,tol_v,tol_f", [("fp32s", 1e-3, 1e-5), ("fp16s", 1e-3, 5e-3)])
+def test_drop2d_volume_and_frozen_error(precision, tol_v, tol_f):
+    """Reduced-precision storage on the 128^2 drop against the FP64 oracle: free-run volume
+    within tol_v over 2000 steps, and the population error with the oracle's site sets
+    imposed (frozen masks) at steps 1, 100 and 2000 within tol_f.  Measured on MI355X: FP32
+    shifted storage 6.7e-8, 2.8e-7, 5.3e-6 (volume 9e-7); FP16 storage with stochastic
+    rounding 5.3e-4 after one step (one FP16 rounding, about one unit in the last place of
+    the largest scaled population, 2^-11), 1.5e-3 and 3.1e-3 as the independent roundings
+    of later steps add up, damped by the relaxation (volume 5e-5).  The rounding is seeded,
+    so the run is repeatable; the FP16 bound 5e-3 leaves a factor 1.6."""
     import torch
     w = case("drop2d", None)
-    _flush("[parity fp32s] drop2d 128x128 2000 steps")
+    _flush(f"[parity {precision}] drop2d 128x128 2000 steps")
     ora = oracle_for(w)
     masks = []
     v_ora = []
@@ -170,7 +177,7 @@ def test_fp32_drop2d_volume_and_frozen_error():
             v_ora.append(ora.observables()["v_mass"])
     f_ora_end = ora.populations()
     # free run
-    sim = gpu_for(w, "fp32s")
+    sim = gpu_for(w, precision)
     v_gpu = []
     done = 0
     for n in (1, 100, 500, 1000, 2000):
@@ -179,12 +186,12 @@ def test_fp32_drop2d_volume_and_frozen_error():
         v_gpu.append(sim.observables()["v_mass"])
     rel = max(abs(a - b) / b for a, b in zip(v_gpu, v_ora))
     _flush(f"  free-run volume rel. error {rel:.3e}")
-    assert rel < 1e-3
+    assert rel < tol_v
     sim.close()
     # frozen masks: the GPU takes the oracle's site sets through the carried mask
     p = dict(w["params"], site_rule="grad")
     w2 = dict(w, params=p)
-    sim = gpu_for(w2, "fp32s")
+    sim = gpu_for(w2, precision)
     ora2 = oracle_for(w)
     errs = {}
     for n in range(1, 2001):
@@ -195,7 +202,7 @@ def test_fp32_drop2d_volume_and_frozen_error():
             errs[n] = e_pop(sim.populations().cpu().numpy(), ora2.populations(), 9, (1.0, 1.0))
     errs[2000] = e_pop(sim.populations().cpu().numpy(), f_ora_end, 9, (1.0, 1.0))
     _flush(f"  frozen-mask e_pop {errs}")
-    assert max(errs.values()) < 1e-5
+    assert max(errs.values()) < tol_f
     sim.close()
 
 
