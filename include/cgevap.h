@@ -294,11 +294,12 @@ cge_status cge_set_height_flux(cge_ctx* ctx, double phi_s, double K, double h_sc
  * adjoint returns CGE_EUNSUPPORTED while outlets are on. */
 cge_status cge_set_outlet(cge_ctx* ctx, int lo, int hi, double rho_out);
 
-/* Launch shape of the record form's z-marching pull (D3Q19, FP32 records): planes per
- * z-chunk of a block's march.  0 (the default) chooses it from the grid and the device's
- * compute-unit count; planes > 0 takes that many (at most nz).  Results do not depend on it
- * beyond the grouping of the FP64 sink partials (1e-15 relative).  For tuning, and for tests
- * of chunked marches on small grids.  CGE_EINVAL for planes < 0. */
+/* Launch shape of the z-marching kernels (the record form's pull at FP32 records, the fused
+ * step): planes per z-chunk of a block's march.  0 (the default) chooses it from the grid
+ * (and, for the record pull, the device's compute-unit count); planes > 0 takes that many
+ * (at most nz).  Results do not depend on it beyond the grouping of the FP64 sink partials
+ * (1e-15 relative).  For tuning, and for tests of chunked marches on small grids.
+ * CGE_EINVAL for planes < 0. */
 cge_status cge_set_zchunk(cge_ctx* ctx, int planes);
 
 /* Restore the step counter and the FP64 sink bookkeeping (checkpoint resume). */

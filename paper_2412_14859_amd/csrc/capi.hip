@@ -274,6 +274,9 @@ static cge_status create_ctx(const cge_params* params, void* hip_stream, void* s
               hipMalloc(&c->acc_sites, c->acc_len * sizeof(long long)) == hipSuccess &&
               hipMalloc(&c->obs_res, (CGE_NOBS + 2) * sizeof(double)) == hipSuccess &&
               hipMalloc(&c->ck, 32) == hipSuccess;
+    if (ok && c->Q == 19)  // the fused step's z-plane table (a few bytes per plane)
+        ok = hipMalloc(&c->pkind, (size_t)c->g.nz) == hipSuccess &&
+             hipMalloc(&c->pcount, (size_t)c->g.nz * sizeof(unsigned)) == hipSuccess;
     if (!ok) {
         cge_destroy(c);
         return CGE_ENOMEM;
@@ -305,14 +308,19 @@ cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
     if (!c) return CGE_EINVAL;
     if (!pop_a || !pop_b || !carry) return fail(c, CGE_EINVAL, "pop_a, pop_b, carry required");
     if (pop_a == pop_b) return fail(c, CGE_EINVAL, "pop_a and pop_b must differ");
-    if (flags && c->p.kernel == CGE_KERNEL_FUSED)
-        return fail(c, CGE_EUNSUPPORTED, "the fused step does not support solid nodes");
     c->pop[0] = pop_a;
     c->pop[1] = pop_b;
     c->cur = 0;
     c->carry = carry;
     c->flags = flags;
     c->phi_field = phi_field;
+    c->plane_walls = false;
+    if (flags && c->Q == 19 && c->p.site_rule != CGE_SITE_SOFT)
+        if (cge_status s = fused_classify(c)) return s;
+    if (flags && c->p.kernel == CGE_KERNEL_FUSED && !c->plane_walls)
+        return fail(c, CGE_EUNSUPPORTED,
+                    "the fused step supports solid nodes only as whole z-planes, none with "
+                    "fluid on both sides");
     switch (c->p.kernel) {
         case CGE_KERNEL_TWOPASS: c->kernel = CGE_KERNEL_TWOPASS; break;
         case CGE_KERNEL_FUSED:
@@ -618,6 +626,8 @@ void cge_destroy(cge_ctx* c) {
     (void)hipFree(c->acc_sites);
     (void)hipFree(c->obs_res);
     (void)hipFree(c->ck);
+    (void)hipFree(c->pkind);
+    (void)hipFree(c->pcount);
     delete c;
 }
 

@@ -1,10 +1,10 @@
-// Single-pass fused step for D3Q19 on periodic domains (no solid nodes).
+// Single-pass fused step for D3Q19: periodic domains, and solid walls that fill whole z-planes.
 //
 // The colour gradient at a node needs the post-sink phase field rho^N of its 18 neighbours,
 // which exists only after those neighbours have pulled their populations.  Instead of
 // writing rho^N to memory and reading the populations a second time (two-pass form), each
-// workgroup owns a TX x TY tile of the x-y plane and marches along a chunk of z:
-//   for plane p = z0-1 .. z1:
+// workgroup owns a 64 x kFTY tile of the x-y plane and marches along a chunk of z:
+//   for plane p:
 //     pull the populations of the tile's nodes at plane p, apply the sink, reduce them to
 //     what the collision needs (colour-blind populations and FP64 moments) and keep that in
 //     registers; compute rho^N of the tile and of its one-node ring (the ring nodes' pulls
@@ -13,11 +13,22 @@
 //     finish plane p-1: gradient from LDS planes p-2, p-1, p, collision, perturbation,
 //     recolouring, store, next site mask.
 // Every population is read once from HBM and written once; the extra reads are the ring
-// and the two end planes of each z-chunk.
+// and the end planes of each z-chunk.
 //
-// Memory access goes through buffer resources: each thread computes the byte offsets of its
-// nine (x, y) neighbours once (periodic wrap included); the population slot and the z plane
-// enter as a scalar offset, so a load costs no vector address arithmetic.
+// Walls (halfway bounce-back, neutral wetting) are served when every z-plane is wholly solid
+// or wholly fluid and no solid plane has fluid on both sides: the floors, lids and slabs of
+// the wall-bounded workloads.  A pulled direction then bounces back exactly when its source
+// plane is solid, a test on the plane alone.  A solid plane's rho^N is the wetting value of
+// its nodes, the W-weighted mean over their fluid neighbours (as k_wet forms it), all of
+// which lie in its one fluid neighbour plane: a lid (fluid below) takes it from the plane
+// pulled before it, a floor (fluid above) from the plane pulled after it, one plane before
+// the floor is needed as a neighbour.  The wetting values of the ring's nodes need rho^N one
+// node further out, so a fluid plane next to a wall also pulls a second ring (rho^N only).
+//
+// Memory access goes through buffer resources, one per component spanning its Q slots (an
+// unsigned 32-bit byte range, up to 4 GiB): each thread computes the byte offsets of its nine
+// (x, y) neighbours once (periodic wrap included); the population slot and the z plane enter
+// as a scalar offset, so a load costs no vector address arithmetic.
 //
 // The site mask is double-buffered (read cin, write cout): a ring node's mask is read by the
 // neighbouring tile while its owner writes the next one.
@@ -26,23 +37,38 @@
 // pulled populations enter the collision only through their moments: the plane waiting to be
 // finished is then held as six FP64 moments per node instead of 19 populations.
 //
-// Tile -> workgroup mapping: consecutive workgroups go to different XCDs, so workgroup b
-// takes tile (b % 8) * (nb / 8) + b / 8 when nb % 8 == 0: each XCD gets a contiguous range
-// of tiles (x fastest, then y, then z-chunk), and tiles that share ring data share an L2.
+// Tile -> workgroup mapping: workgroups are dealt to the XCDs round-robin by id, so XCD k
+// takes a contiguous run of tiles (x fastest, then y, then z-chunk), and tiles that share
+// ring data share an L2.
 #include "internal.hpp"
 #include "node.hpp"
 
 namespace cge {
 
 constexpr int kFTX = 64;  // tile width in x: one wavefront per row
-constexpr int kFTY = 4;   // tile rows per workgroup
+// Tile rows per workgroup.  At general relaxation times a thread holds one pulled node's
+// moments and the 38 loads of a pull in flight, and the FP64 collision: 170 registers at FP32
+// storage, two waves per SIMD.  Four rows (two workgroups per CU that do not wait on each
+// other's barriers) ran the 384 x 384 x 192 sessile drop in 3.05 ms per step, eight rows in
+// 3.25 ms; capping the registers for three waves per SIMD left fewer loads in flight per wave
+// (5.4 ms).
+constexpr int kFTY = 4;
+
+// Kinds of the z-planes under plane walls.
+enum : uint8_t {
+    kPlaneSolid = 1,       // the plane is solid
+    kPlaneFluidBelow = 2,  // a solid plane whose plane z - 1 is fluid (a lid)
+    kPlaneFluidAbove = 4,  // a solid plane whose plane z + 1 is fluid (a floor)
+    kPlaneNearWall = 8,    // a fluid plane next to a solid one
+};
 
 struct FusedShape {
     int ntx, nty, nzc, zlen;
     long long nb;
 };
 
-static FusedShape fused_shape(const Geo& g) {
+// zchunk > 0: planes per z-chunk (cge_set_zchunk), else chosen here
+static FusedShape fused_shape(const Geo& g, int zchunk) {
     FusedShape s;
     s.ntx = (g.nx + kFTX - 1) / kFTX;
     s.nty = (g.ny + kFTY - 1) / kFTY;
@@ -52,13 +78,14 @@ static FusedShape fused_shape(const Geo& g) {
     const long long maxc = (g.nz + 15) / 16;
     if (want > maxc) want = maxc;
     if (want < 1) want = 1;
-    s.zlen = (int)((g.nz + want - 1) / want);
+    s.zlen = zchunk > 0 ? (zchunk < g.nz ? zchunk : g.nz) : (int)((g.nz + want - 1) / want);
     s.nzc = (g.nz + s.zlen - 1) / s.zlen;
     s.nb = tiles * s.nzc;
     return s;
 }
 
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int wrapf(int v, int n) { return ((v % n) + n) % n; }
 
 // Loads and stores of one storage element through a buffer resource at byte offset
 // voff (per lane) + soff (uniform).
@@ -117,36 +144,43 @@ __device__ __forceinline__ Plane9<S> plane9(const Geo& g, int x, int y) {
     return p;
 }
 
-// What the finishing half of the step needs of a pulled node: the colour-blind populations
-// ft_i (the colour differences enter only through their sum) and the post-sink moments.
-// With unit relaxation times the collision needs the moments only.
+// What the finishing half of the step needs of a pulled node: the post-sink moments (in
+// registers) and, unless both relaxation times are 1, the colour-blind populations ft_i (the
+// colour differences enter only through their sum), which the pull leaves in the thread's
+// own LDS slots (ftl below).
 template <int Q, typename S, typename M, bool UNIT>
 struct Pulled {
-    S ft[UNIT ? 1 : Q];
     M drho, dsum, j[3], s;  // dsum is post-sink; s is the sink applied
 };
 
 // Pull (Eq. Stream) of the node whose plane offsets are `pl`, at plane z: direction i comes
-// from (x, y, z) - c_i.  zoff[1 + d] is the byte offset of plane z + d (wrapped).  Returns
-// the post-sink rho^N (rounded to the storage precision, as the other step forms store it);
-// with FULL, also fills the reduced node for the collision.
-template <int Q, typename S, typename M, bool FULL, bool UNIT>
+// from (x, y, z) - c_i, or, where the plane of the source is solid (bit 1 + c_z of bb, plane
+// walls), from the node itself in the opposite direction (halfway bounce-back).  zoff[1 + d]
+// is the byte offset of plane z + d (wrapped).  Returns the post-sink rho^N (rounded to the
+// storage precision, as the other step forms store it); with FULL, also fills the reduced
+// node for the collision.
+template <int Q, typename S, typename M, bool FULL, bool UNIT, bool PW>
 __device__ __forceinline__ M pull_node(__amdgpu_buffer_rsrc_t rft, __amdgpu_buffer_rsrc_t rdd,
                                        const Plane9<S>& pl, const uint32_t (&zoff)[3],
-                                       uint32_t slot_bytes, const Phys<M>& P,
+                                       uint32_t slot_bytes, uint32_t bb, const Phys<M>& P,
                                        const uint8_t* __restrict__ cin,
                                        const void* __restrict__ phi_field, uint32_t n,
-                                       Pulled<Q, S, M, UNIT>& pn) {
+                                       Pulled<Q, S, M, UNIT>& pn, S* __restrict__ ft_out,
+                                       int ft_stride) {
     // the site byte and flux do not depend on the populations: fetch them first
     const uint8_t cb = cin[n];
     const M phi = phi_field ? static_cast<M>(static_cast<const PhiT<S>*>(phi_field)[n]) : P.phi;
     M drho = M(0), dsum = M(0), j[3] = {M(0), M(0), M(0)};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const uint32_t vo = pl.o[1 - Lat<Q>::cy[i]][1 - Lat<Q>::cx[i]];
-        const uint32_t so = (uint32_t)i * slot_bytes + zoff[1 - Lat<Q>::cz[i]];
+        uint32_t vo = pl.o[1 - Lat<Q>::cy[i]][1 - Lat<Q>::cx[i]];
+        uint32_t so = (uint32_t)i * slot_bytes + zoff[1 - Lat<Q>::cz[i]];
+        if (PW && i != 0 && ((bb >> (1 + Lat<Q>::cz[i])) & 1u)) {
+            vo = pl.o[1][1];
+            so = (uint32_t)Lat<Q>::opp[i] * slot_bytes + zoff[1];
+        }
         const S a = Buf<S>::ld(rft, vo, so);
-        if (FULL && !UNIT) pn.ft[i] = a;
+        if (FULL && !UNIT) ft_out[i * ft_stride] = a;
         const M am = static_cast<M>(a);
         drho += am;
         dsum += static_cast<M>(Buf<S>::ld(rdd, vo, so));
@@ -171,18 +205,47 @@ __device__ __forceinline__ M pull_node(__amdgpu_buffer_rsrc_t rft, __amdgpu_buff
     return static_cast<M>(static_cast<MomT<S>>(dpost / rho));
 }
 
-template <int Q, typename S, typename M, bool UNIT>
+// Position t of the ring at distance d around a w x h tile (tile coordinates): its top row,
+// bottom row, left column, right column.
+__device__ __forceinline__ void ring_at(int t, int d, int w, int h, int& rx, int& ry) {
+    const int row = w + 2 * d, col = h + 2 * d - 2;
+    if (t < row) {
+        rx = t - d;
+        ry = -d;
+    } else if ((t -= row) < row) {
+        rx = t - d;
+        ry = h - 1 + d;
+    } else if ((t -= row) < col) {
+        rx = -d;
+        ry = t - d + 1;
+    } else {
+        t -= col;
+        rx = w - 1 + d;
+        ry = t - d + 1;
+    }
+}
+
+// PW: the solid flags are plane walls, described per plane by pkind.
+template <int Q, typename S, typename M, bool UNIT, bool PW>
 __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     const S* __restrict__ src, S* __restrict__ dst, const uint8_t* __restrict__ cin,
-    uint8_t* __restrict__ cout, const void* __restrict__ phi_field, double* __restrict__ acc_sink,
+    uint8_t* __restrict__ cout, const void* __restrict__ phi_field,
+    const uint8_t* __restrict__ pkind, double* __restrict__ acc_sink,
     long long* __restrict__ acc_sites, Geo g, Phys<M> P, uint64_t salt, FusedShape fs) {
     static_assert(Q == 19, "the fused step is written for D3Q19");
-    __shared__ M rn[3][kFTY + 2][kFTX + 2];
+    constexpr int R = PW ? 2 : 1;  // rings of rho^N held around the tile
+    constexpr int NW = kFTY;       // waves per workgroup
+    __shared__ M rn[3][kFTY + 2 * R][kFTX + 2 * R];
+    // the colour-blind populations of the pulled own nodes, by plane parity: thread t keeps
+    // direction i of its node at ftl[p & 1][i][t] (written by its pull of plane p, read by its
+    // finish of plane p one plane later; no other thread touches the slot)
+    __shared__ S ftl[UNIT ? 1 : 2][UNIT ? 1 : Q][kFTX * kFTY];
 
     const int tid = threadIdx.x;
     const int lx = tid % kFTX, ly = tid / kFTX;
-    long long b = blockIdx.x;
-    if (fs.nb % 8 == 0) b = (b % 8) * (fs.nb / 8) + b / 8;
+    const unsigned nb = gridDim.x, bid = blockIdx.x;
+    const unsigned xq = nb / kXcds, xrem = nb % kXcds, xk = bid % kXcds;
+    const long long b = (long long)(xk * xq + (xk < xrem ? xk : xrem) + bid / kXcds);
     const int tx = (int)(b % fs.ntx);
     const int ty = (int)((b / fs.ntx) % fs.nty);
     const int zc = (int)(b / ((long long)fs.ntx * fs.nty));
@@ -192,36 +255,30 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     const bool own = lx < w && ly < h;
     const int x = own ? x0 + lx : x0, y = own ? y0 + ly : y0;
 
-    // Ring nodes in order: top row, bottom row, left column, right column.  Each wave takes a
-    // contiguous quarter of the list (rows stay coalesced, waves stay balanced).
-    int rx = 0, ry = 0;
-    bool ring;
+    // Ring nodes: each wave takes a contiguous share of each ring's list (rows stay
+    // coalesced, waves stay balanced).
+    const int lane = tid % 64, wave = tid / 64;
+    int rx = 0, ry = 0, r2x = 0, r2y = 0;
+    bool ring, ring2 = false;
     {
-        const int row = w + 2, nring = 2 * row + 2 * h;
-        const int per = (nring + kFTY - 1) / kFTY;  // kFTY waves of 64 lanes each
-        const int lane = tid % 64, wave = tid / 64;
-        int t = wave * per + lane;
-        ring = lane < per && t < nring;
-        if (t < row) {
-            rx = t - 1;
-            ry = -1;
-        } else if ((t -= row) < row) {
-            rx = t - 1;
-            ry = h;
-        } else if ((t -= row) < h) {
-            rx = -1;
-            ry = t;
-        } else {
-            t -= h;
-            rx = w;
-            ry = t;
+        const int n1 = 2 * w + 2 * h + 4, per = (n1 + NW - 1) / NW;
+        const int t = wave * per + lane;
+        ring = lane < per && t < n1;
+        if (ring) ring_at(t, 1, w, h, rx, ry);
+        if (PW) {
+            const int n2 = 2 * w + 2 * h + 12, per2 = (n2 + NW - 1) / NW;
+            const int t2 = wave * per2 + lane;
+            ring2 = lane < per2 && t2 < n2;
+            if (ring2) ring_at(t2, 2, w, h, r2x, r2y);
         }
     }
-    const int gx = wrap1(x0 + rx, g.nx), gy = wrap1(y0 + ry, g.ny);
+    const int gx = wrapf(x0 + rx, g.nx), gy = wrapf(y0 + ry, g.ny);
 
     const uint32_t E = sizeof(S);
     const uint32_t slot_bytes = (uint32_t)g.N * E;
     const uint32_t plane_bytes = (uint32_t)g.nx * (uint32_t)g.ny * E;
+    // the record count of a raw buffer is an unsigned 32-bit byte count (fused_supported
+    // keeps Q slots below 2^32 bytes)
     const int range = (int)((uint32_t)Q * slot_bytes);
     const long long QN = (long long)Q * g.N;
     const __amdgpu_buffer_rsrc_t sft =
@@ -238,67 +295,137 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     const uint32_t ring_xy = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy;
     const uint32_t nplane = (uint32_t)g.nx * (uint32_t)g.ny;
 
+    auto kind = [&](int zp) -> uint32_t {
+        return PW ? (uint32_t)__builtin_amdgcn_readfirstlane(pkind[wrapf(zp, g.nz)]) : 0u;
+    };
+    // wetting value of the solid node at LDS position (yy, xx) of a plane from the fluid
+    // plane in LDS slot sf on the side dz (the neighbours x + c_i with c_z = dz), summed in
+    // the order of k_wet and rounded as a stored rho^N field holds it
+    auto wet_at = [&](int sf, int dz, int yy, int xx) -> M {
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            if (Lat<Q>::cz[i] != dz) continue;
+            num += weight<Q>(i) *
+                   static_cast<double>(rn[sf][yy + Lat<Q>::cy[i]][xx + Lat<Q>::cx[i]]);
+            den += weight<Q>(i);
+        }
+        return static_cast<M>(static_cast<MomT<S>>(den > 0.0 ? num / den : 0.0));
+    };
+    auto put_wet = [&](int slot, int sf, int dz) {
+        if (own) rn[slot][ly + R][lx + R] = wet_at(sf, dz, ly + R, lx + R);
+        if (ring) rn[slot][ry + R][rx + R] = wet_at(sf, dz, ry + R, rx + R);
+    };
+
     Pulled<Q, S, M, UNIT> cur, nxt;  // plane waiting to be finished, plane being pulled
     cur.s = M(0);
     double acc_s = 0.0, acc_n = 0.0;
 
-    for (int p = z0 - 1; p <= z1; ++p) {
-        const int pz = wrap1(p, g.nz);
-        const uint32_t zoff[3] = {(uint32_t)wrap1(pz - 1, g.nz) * plane_bytes,
-                                  (uint32_t)pz * plane_bytes,
-                                  (uint32_t)wrap1(pz + 1, g.nz) * plane_bytes};
-        const int slot = (p - z0 + 1) % 3;
-        M r_ring = M(0), r_own = M(0);
-        if (ring)
-            r_ring = pull_node<Q, S, M, false, UNIT>(sft, sdd, pr, zoff, slot_bytes, P, cin,
-                                                     phi_field, ring_xy + (uint32_t)pz * nplane, nxt);
-        if (own)
-            r_own = pull_node<Q, S, M, true, UNIT>(sft, sdd, po, zoff, slot_bytes, P, cin,
-                                                   phi_field, own_xy + (uint32_t)pz * nplane, nxt);
-        __syncthreads();  // every thread is done reading the slot about to be overwritten
-        if (own) rn[slot][ly + 1][lx + 1] = r_own;
-        if (ring) rn[slot][ry + 1][rx + 1] = r_ring;
+    // a lid just below the chunk takes its wetting values from the plane below it
+    const int ps = (PW && (kind(z0 - 1) & kPlaneFluidBelow)) ? z0 - 2 : z0 - 1;
+    auto slot_of = [&](int zp) { return (zp - ps + 3) % 3; };
+    for (int p = ps; p <= z1; ++p) {
+        const int pz = wrapf(p, g.nz);
+        const uint32_t kp = kind(p);
+        const int slot = slot_of(p);
+        if (!(kp & kPlaneSolid)) {
+            const uint32_t zoff[3] = {(uint32_t)wrap1(pz - 1, g.nz) * plane_bytes,
+                                      (uint32_t)pz * plane_bytes,
+                                      (uint32_t)wrap1(pz + 1, g.nz) * plane_bytes};
+            // bounce-back where the source plane is solid: c_z = -1 from plane p + 1 (bit 0),
+            // c_z = +1 from plane p - 1 (bit 2)
+            const uint32_t bb = PW ? (((kind(p + 1) & kPlaneSolid) ? 1u : 0u) |
+                                      ((kind(p - 1) & kPlaneSolid) ? 4u : 0u))
+                                   : 0u;
+            M r_ring = M(0), r_own = M(0), r_ring2 = M(0);
+            if (ring)
+                r_ring = pull_node<Q, S, M, false, UNIT, PW>(sft, sdd, pr, zoff, slot_bytes, bb, P,
+                                                             cin, phi_field,
+                                                             ring_xy + (uint32_t)pz * nplane, nxt,
+                                                             nullptr, 0);
+            if (own)
+                r_own = pull_node<Q, S, M, true, UNIT, PW>(sft, sdd, po, zoff, slot_bytes, bb, P,
+                                                           cin, phi_field,
+                                                           own_xy + (uint32_t)pz * nplane, nxt,
+                                                           &ftl[UNIT ? 0 : (p & 1)][0][tid],
+                                                           kFTX * kFTY);
+            const bool far = PW && (kp & kPlaneNearWall) && ring2;
+            if (far) {  // the second ring, for the wetting values of the wall next to plane p
+                const int g2x = wrapf(x0 + r2x, g.nx), g2y = wrapf(y0 + r2y, g.ny);
+                const Plane9<S> p2 = plane9<S>(g, g2x, g2y);
+                r_ring2 = pull_node<Q, S, M, false, UNIT, PW>(
+                    sft, sdd, p2, zoff, slot_bytes, bb, P, cin, phi_field,
+                    (uint32_t)g2x + (uint32_t)g.nx * (uint32_t)g2y + (uint32_t)pz * nplane, nxt,
+                    nullptr, 0);
+            }
+            __syncthreads();  // every thread is done reading the slot about to be overwritten
+            if (own) rn[slot][ly + R][lx + R] = r_own;
+            if (ring) rn[slot][ry + R][rx + R] = r_ring;
+            if (far) rn[slot][r2y + R][r2x + R] = r_ring2;
+        } else {
+            __syncthreads();
+            if (kp & kPlaneFluidBelow)  // a lid: wetting values from the plane below
+                put_wet(slot, slot_of(p - 1), -1);
+            else if (!(kp & kPlaneFluidAbove)) {  // no fluid neighbour: the wetting value 0
+                if (own) rn[slot][ly + R][lx + R] = M(0);
+                if (ring) rn[slot][ry + R][rx + R] = M(0);
+            }  // a floor waits for the plane above it
+        }
         __syncthreads();
+        if (PW && p - 1 >= ps) {  // a floor below plane p: its wetting values from plane p
+            const uint32_t km = kind(p - 1);
+            if ((km & kPlaneSolid) && (km & kPlaneFluidAbove)) {
+                put_wet(slot_of(p - 1), slot, 1);
+                __syncthreads();
+            }
+        }
 
         const int pc = p - 1;  // plane to finish
         if (pc >= z0 && own) {
             const uint32_t n = own_xy + (uint32_t)pc * nplane;
-            if (cur.s != M(0)) {
-                acc_s += static_cast<double>(cur.s);
-                acc_n += 1.0;
-            }
-            const M rho = P.rho_ref + cur.drho;
-            const M inv_rho = M(1) / rho;
-            const M u[3] = {cur.j[0] * inv_rho, cur.j[1] * inv_rho, cur.j[2] * inv_rho};
-            const M rN = static_cast<M>(static_cast<MomT<S>>(cur.dsum / rho));  // as in the ring
-            // gradient from the LDS ring: planes pc-1, pc, pc+1 are slots of p-2, p-1, p
-            const int sl[3] = {(p - z0 + 2) % 3, (p - z0) % 3, slot};  // cz = -1, 0, +1
-            M F[3] = {M(0), M(0), M(0)};
+            if (PW && (kind(pc) & kPlaneSolid)) {
+                cout[n] = 0;  // solid nodes carry no site
+            } else {
+                if (cur.s != M(0)) {
+                    acc_s += static_cast<double>(cur.s);
+                    acc_n += 1.0;
+                }
+                const M rho = P.rho_ref + cur.drho;
+                const M inv_rho = M(1) / rho;
+                const M u[3] = {cur.j[0] * inv_rho, cur.j[1] * inv_rho, cur.j[2] * inv_rho};
+                const M rN = static_cast<M>(static_cast<MomT<S>>(cur.dsum / rho));  // as in the ring
+                // gradient from the LDS ring: planes pc-1, pc, pc+1
+                const int sl[3] = {slot_of(pc - 1), slot_of(pc), slot};  // cz = -1, 0, +1
+                M F[3] = {M(0), M(0), M(0)};
 #pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
-                const M v = M(weight<Q>(i)) * rn[sl[cz + 1]][ly + 1 + cy][lx + 1 + cx];
-                if (cx) F[0] += cx * v;
-                if (cy) F[1] += cy * v;
-                if (cz) F[2] += cz * v;
+                for (int i = 1; i < Q; ++i) {
+                    const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
+                    const M v = M(weight<Q>(i)) * rn[sl[cz + 1]][ly + R + cy][lx + R + cx];
+                    if (cx) F[0] += cx * v;
+                    if (cy) F[1] += cy * v;
+                    if (cz) F[2] += cz * v;
+                }
+                F[0] *= M(3);
+                F[1] *= M(3);
+                F[2] *= M(3);
+                const uint32_t vo = po.o[1][1];
+                const uint32_t zo = (uint32_t)pc * plane_bytes;
+                const M Fn = collide<Q, M, UNIT>(
+                    [&](int i) {
+                        return UNIT ? M(0) : static_cast<M>(ftl[UNIT ? 0 : (pc & 1)][UNIT ? 0 : i][tid]);
+                    },
+                    cur.drho, rho,
+                    rN, u, F, P,
+                    [&](int i, M a, M d) {
+                        const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N + (uint64_t)n;
+                        const uint32_t so = (uint32_t)i * slot_bytes + zo;
+                        Buf<S>::st(enc<S, M>(a, key), dft, vo, so);
+                        Buf<S>::st(enc<S, M>(d, key + (uint64_t)g.N), ddd, vo, so);
+                    });
+                cout[n] = Fn > P.gamma ? 1 : 0;
             }
-            F[0] *= M(3);
-            F[1] *= M(3);
-            F[2] *= M(3);
-            const uint32_t vo = po.o[1][1];
-            const uint32_t zo = (uint32_t)pc * plane_bytes;
-            const M Fn = collide<Q, M, UNIT>(
-                [&](int i) { return static_cast<M>(cur.ft[UNIT ? 0 : i]); }, cur.drho, rho, rN, u,
-                F, P,
-                [&](int i, M a, M d) {
-                    const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N + (uint64_t)n;
-                    const uint32_t so = (uint32_t)i * slot_bytes + zo;
-                    Buf<S>::st(enc<S, M>(a, key), dft, vo, so);
-                    Buf<S>::st(enc<S, M>(d, key + (uint64_t)g.N), ddd, vo, so);
-                });
-            cout[n] = Fn > P.gamma ? 1 : 0;
         }
-        if (own && p < z1) cur = nxt;
+        if (own && p < z1 && !(kp & kPlaneSolid)) cur = nxt;
     }
 
     double v[2] = {acc_s, acc_n};
@@ -306,8 +433,8 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     double out[2];
     block_reduce<2>(v, is_max, tid, kFTX * kFTY, out);
     if (tid == 0) {
-        acc_sink[b] += out[0];
-        acc_sites[b] += static_cast<long long>(out[1]);
+        acc_sink[bid] += out[0];
+        acc_sites[bid] += static_cast<long long>(out[1]);
     }
 }
 
@@ -317,26 +444,96 @@ __global__ __launch_bounds__(256) void k_copy_bytes(const uint8_t* __restrict__ 
     if (i < n) dst[i] = src[i];
 }
 
-// The Q slots of one component must fit a buffer resource's signed 32-bit byte range.
-bool fused_supported(const cge_ctx* c) {
-    const long long elem = c->p.precision == CGE_FP64 ? 8 : (c->p.precision == CGE_FP32S ? 4 : 2);
-    return c->Q == 19 && c->flags == nullptr && c->p.site_rule != CGE_SITE_SOFT &&
-           19ll * c->g.N * elem < (1ll << 31);
+// Solid nodes per z-plane: blocks blockIdx.y, blockIdx.y + gridDim.y, ... take planes; each
+// block adds its count of a plane once.
+__global__ __launch_bounds__(256) void k_plane_count(const uint8_t* __restrict__ flags,
+                                                     long long plane, int nz,
+                                                     unsigned* __restrict__ cnt) {
+    __shared__ unsigned sh[4];
+    for (int z = blockIdx.y; z < nz; z += gridDim.y) {
+        const uint8_t* f = flags + (long long)z * plane;
+        unsigned c = 0;
+        for (long long i = blockIdx.x * 256ll + threadIdx.x; i < plane;
+             i += (long long)gridDim.x * 256)
+            c += f[i] != 0 ? 1u : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(cnt + z, sh[0] + sh[1] + sh[2] + sh[3]);
+        __syncthreads();
+    }
 }
 
-long long fused_blocks(const cge_ctx* c) { return fused_shape(c->g).nb; }
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+cge_status fused_classify(cge_ctx* c) {
+    c->plane_walls = false;
+    if (!c->flags || !c->pkind || !c->pcount) return CGE_OK;
+    const int nz = c->g.nz;
+    const long long plane = (long long)c->g.nx * c->g.ny;
+    hipLaunchKernelGGL(k_zero_u32, dim3((nz + 255) / 256), dim3(256), 0, c->stream, c->pcount, nz);
+    const long long bx = (plane + 255) / 256;
+    hipLaunchKernelGGL(k_plane_count, dim3((unsigned)(bx < 64 ? bx : 64), (unsigned)(nz < 4096 ? nz : 4096)),
+                       dim3(256), 0, c->stream, c->flags, plane, nz, c->pcount);
+    if (cge_status s = check(c, hipGetLastError(), "plane classification launch")) return s;
+    std::vector<unsigned> cnt((size_t)nz);
+    if (cge_status s = check(c, hipMemcpyAsync(cnt.data(), c->pcount, nz * sizeof(unsigned),
+                                               hipMemcpyDeviceToHost, c->stream),
+                             "plane classification"))
+        return s;
+    if (cge_status s = check(c, hipStreamSynchronize(c->stream), "plane classification"))
+        return s;
+    std::vector<unsigned char> kind((size_t)nz, 0);
+    auto solid = [&](int z) { return cnt[(size_t)((z % nz + nz) % nz)] == (unsigned)plane; };
+    for (int z = 0; z < nz; ++z) {
+        if (cnt[z] != 0 && cnt[z] != (unsigned)plane) return CGE_OK;  // a mixed plane
+        if (solid(z)) {
+            const bool below = !solid(z - 1), above = !solid(z + 1);
+            if (below && above) return CGE_OK;  // fluid on both sides (or nz < 3)
+            kind[z] = kPlaneSolid | (below ? kPlaneFluidBelow : 0) | (above ? kPlaneFluidAbove : 0);
+        } else if (solid(z - 1) || solid(z + 1)) {
+            kind[z] = kPlaneNearWall;
+        }
+    }
+    if (cge_status s = check(c, hipMemcpyAsync(c->pkind, kind.data(), (size_t)nz,
+                                               hipMemcpyHostToDevice, c->stream),
+                             "plane classification"))
+        return s;
+    if (cge_status s = check(c, hipStreamSynchronize(c->stream), "plane classification"))
+        return s;
+    c->plane_walls = true;
+    return CGE_OK;
+}
+
+// The Q slots of one component must fit a raw buffer's unsigned 32-bit byte range; solid
+// nodes only as plane walls.
+bool fused_supported(const cge_ctx* c) {
+    const long long elem = c->p.precision == CGE_FP64 ? 8 : (c->p.precision == CGE_FP32S ? 4 : 2);
+    return c->Q == 19 && (c->flags == nullptr || c->plane_walls) &&
+           c->p.site_rule != CGE_SITE_SOFT && 19ll * c->g.N * elem < (1ll << 32);
+}
+
+// workgroups of the fused step at one plane per chunk, the most any chunk length gives
+long long fused_blocks(const cge_ctx* c) { return fused_shape(c->g, 1).nb; }
 
 template <int Q, typename S, typename M, bool WALLS>
 static cge_status fused_impl(cge_ctx* c, long long nsteps) {
-    if constexpr (Q != 19 || WALLS) {
-        return fail(c, CGE_EUNSUPPORTED, "fused step needs D3Q19 without solid nodes");
+    if constexpr (Q != 19) {
+        return fail(c, CGE_EUNSUPPORTED, "fused step needs D3Q19");
     } else {
+        if (WALLS && !c->plane_walls)
+            return fail(c, CGE_EUNSUPPORTED, "fused step: solid nodes other than plane walls");
         const Phys<M> P = phys<M>(c);
-        const FusedShape fs = fused_shape(c->g);
+        const FusedShape fs = fused_shape(c->g, c->zchunk);
         if (fs.nb > c->acc_len) return fail(c, CGE_ESTATE, "accumulator too small");
         const uint64_t seedmix = mix64(c->p.seed);
         const bool unit = c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0;
         uint8_t* mask[2] = {c->carry, c->carry2};
+        const uint8_t* pk = WALLS ? c->pkind : nullptr;
         int m = 0;
         for (long long t = 0; t < nsteps; ++t) {
             const S* src = static_cast<const S*>(c->pop[c->cur]);
@@ -344,15 +541,15 @@ static cge_status fused_impl(cge_ctx* c, long long nsteps) {
             const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
             timing_begin(c, "fused step");
             if (unit)
-                hipLaunchKernelGGL((k_fused<Q, S, M, true>), dim3((unsigned)fs.nb),
+                hipLaunchKernelGGL((k_fused<Q, S, M, true, WALLS>), dim3((unsigned)fs.nb),
                                    dim3(kFTX * kFTY), 0, c->stream, src, dst, mask[m],
-                                   mask[1 - m], c->phi_field, c->acc_sink, c->acc_sites, c->g, P,
-                                   salt, fs);
+                                   mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites, c->g,
+                                   P, salt, fs);
             else
-                hipLaunchKernelGGL((k_fused<Q, S, M, false>), dim3((unsigned)fs.nb),
+                hipLaunchKernelGGL((k_fused<Q, S, M, false, WALLS>), dim3((unsigned)fs.nb),
                                    dim3(kFTX * kFTY), 0, c->stream, src, dst, mask[m],
-                                   mask[1 - m], c->phi_field, c->acc_sink, c->acc_sites, c->g, P,
-                                   salt, fs);
+                                   mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites, c->g,
+                                   P, salt, fs);
             timing_pass(c, "k_fused");
             timing_end(c);
             if (cge_status s = check(c, hipGetLastError(), "fused step launch")) return s;

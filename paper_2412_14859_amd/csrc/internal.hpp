@@ -44,6 +44,11 @@ struct cge_ctx {
     long long obs_blocks = 0;
     double* obs_res = nullptr;      // [CGE_NOBS + 2] final values (device)
     unsigned char* ck = nullptr;    // 32 bytes: the checksum of a state being loaded
+    // z-plane kinds of the fused step's plane walls ([nz] bytes, D3Q19), the solid-node count
+    // per plane they are classified from ([nz]), and whether the bound flags are plane walls
+    unsigned char* pkind = nullptr;
+    unsigned* pcount = nullptr;
+    bool plane_walls = false;
     // blue pressure outlets on the end planes of the last axis
     int out_lo = 0, out_hi = 0;
     double out_rho = 1.0;
@@ -93,6 +98,8 @@ size_t record_bytes(const cge_params* p);
 cge_status split_step_into(cge_ctx* c, const void* carry_in, void* carry_out, void* rhoN,
                            void* mom);
 bool fused_supported(const cge_ctx* c);
+// classify the bound solid flags for the fused step (sets plane_walls and pkind; synchronises)
+cge_status fused_classify(cge_ctx* c);
 long long twopass_blocks(const cge_ctx* c);
 long long fused_blocks(const cge_ctx* c);
 

@@ -25,6 +25,10 @@ CASES = {
     "d3q19_chunks": ("sphere3d", (40, 10, 70), dict(radius=4.5, phi=1e-3)),
     # relaxation times other than 1 (the general collision path of the fused step)
     "d3q19_tau": ("sphere3d", (20, 12, 70), dict(radius=4.0, phi=1e-3, tau=(1.0, 0.8))),
+    # plane walls (a floor at z = 0 and a lid at z = nz - 1) for the fused step: a flat film,
+    # and a hemisphere on the floor with its height-dependent flux field
+    "d3q19_flat_walls": ("flat3d", (21, 12, 70), dict(phi=1e-3)),
+    "d3q19_hemisphere": ("hemisphere3d", (24, 20, 70), dict(radius=6.0, phi=1e-3)),
     # logistic (soft) site weights of the gradient magnitude; Gamma / kappa = 30 keeps the
     # bulk weight near 6e-14 (a weight of 1e-7 or more in the bulk drains the lighter colour
     # below zero far from the drop within the run, where recolouring turns anti-diffusive and
@@ -40,10 +44,11 @@ CASES = {
 }
 
 # step implementations to check per case: the two-pass step covers everything, the fused
-# single-pass step D3Q19 without solid nodes, the split step unit relaxation times
+# single-pass step D3Q19 without solid nodes or with plane walls (hard site rules), the split
+# step unit relaxation times
 def _kernels(wl, over):
     ks = ["twopass"]
-    if wl == "sphere3d" and over.get("site_rule") != "soft":
+    if wl in ("sphere3d", "sessile3d", "flat3d", "hemisphere3d") and over.get("site_rule") != "soft":
         ks.append("fused")
     tau = over.get("tau", (1.0, 1.0) if wl != "sessile3d" else (1.0, 0.6))
     if tuple(tau) == (1.0, 1.0):
