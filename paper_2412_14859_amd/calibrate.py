@@ -21,6 +21,15 @@ half-maximum contour.  Summed over the snapshots, the site count at Gamma is the
 pooled gradient values above Gamma, so the calibrated Gamma is the threshold with
 Sbar * sum_t A(t) pooled values above it.  The trajectory depends weakly on the threshold it
 ran with; `iterations` > 1 runs again from the previous result.
+
+The criterion above needs the interface measure, and a measure taken from the half-maximum
+radius is not the one whose rate of change fixes the mass: the drop's red mass is that of a
+sphere of its equimolar radius, which lies outside the half-maximum contour by an amount that
+grows with the interface width.  The paper compares the measured radius (or height) with the
+analytical law directly, so `criterion="curve"` matches that instead: the least-squares slope
+of the measured position over the run at the threshold it ran with, scaled by the pooled site
+count at a trial threshold over that at the run's (the sink, and so the slope, is proportional
+to the site count), must equal the law's slope -phi / rho0.
 """
 import math
 
@@ -118,19 +127,22 @@ def _position(sim, kind, dim, solid_layers):
 
 def calibrate_dynamic(workload, kind, phi, equil=4000, t_star=0.8, snapshots=40, sbar=3.0,
                       gamma0=None, kappa=1e-4, precision="fp32s", outlet=None, solid_layers=1,
-                      floor=0.05, iterations=1, device="cuda:0"):
+                      floor=0.05, iterations=1, criterion="rate", device="cuda:0"):
     """Gamma matching the mass-loss rate over an evaporating run (see the module notes).
 
     workload: an `inputs.workload` dict; kind: 'sphere', 'hemisphere' or 'flat' (the
     interface measure); phi: the flux of the run, which lasts until t* = t phi / (x0 rho0) =
     t_star (x0 the initial radius or film height, rho0 the equilibrium red density); outlet:
     (lo, hi) blue outlets switched on for the evaporation; solid_layers: wall thickness under
-    a film.  Returns (Gamma, details)."""
+    a film; criterion: "rate" (sites against Sbar times the interface measure) or "curve"
+    (the slope of the measured position against the law's).  Returns (Gamma, details)."""
     from paper_2412_14859_amd import cgevap
     if snapshots < 1 or iterations < 1 or not phi > 0:
         raise ValueError("snapshots and iterations must be >= 1 and phi > 0")
     if kind not in ("sphere", "hemisphere", "flat"):
         raise ValueError(kind)
+    if criterion not in ("rate", "curve"):
+        raise ValueError(criterion)
     w = workload
     p0 = w["params"]
     dim = 2 if int(p0["Q"]) == 9 else 3
@@ -157,24 +169,32 @@ def calibrate_dynamic(workload, kind, phi, equil=4000, t_star=0.8, snapshots=40,
             return interface_measure(kind, R=x, dim=dim)
 
         A0 = measure(x0)
-        pool, measures = [], []
+        pool, measures, xs = [], [], [x0]
         for _ in range(snapshots):
             sim.step(chunk)
             fm = sim.carry.cpu().numpy()
             vals = fm if fluid is None else fm[fluid]
             pool.append(vals[vals > floor].copy())
             x, _ = _position(sim, kind, dim, solid_layers)
+            xs.append(x)
             measures.append(measure(x))
         obs = sim.observables()
         sim.close()
-        target = sbar * float(np.sum(measures))
+        ts = chunk * np.arange(snapshots + 1, dtype=np.float64)
+        slope = float(np.polyfit(ts, np.asarray(xs), 1)[0])  # measured position per step
+        slope_law = -phi / rho0
+        if criterion == "rate":
+            target = sbar * float(np.sum(measures))
+        else:
+            n_run = float(sum(int((a > g).sum()) for a in pool))
+            target = n_run * slope_law / slope
         g_new, interval = gamma_for_rate(pool, target)
         # the realised rate of this run against the analytical one, phi times the integral
         # of A over the run (trapezoidal rule over the snapshots and the start)
         integral = chunk * (0.5 * A0 + float(np.sum(measures[:-1])) + 0.5 * measures[-1])
         realised = obs["sink_total"] / (phi * integral)
         history.append({"gamma_run": g, "gamma": g_new, "interval": interval,
-                        "realised_rate_ratio": realised, "x0": x0, "rho0": rho0,
-                        "steps": chunk * snapshots, "x_end": x})
+                        "realised_rate_ratio": realised, "slope_ratio": slope / slope_law,
+                        "x0": x0, "rho0": rho0, "steps": chunk * snapshots, "x_end": x})
         g = g_new
     return g, {"history": history, "sites_target": target}

@@ -417,10 +417,9 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
                     cur.drho, rho,
                     rN, u, F, P,
                     [&](int i, M a, M d) {
-                        const uint64_t key = salt + (uint64_t)(2 * i) * (uint64_t)g.N + (uint64_t)n;
                         const uint32_t so = (uint32_t)i * slot_bytes + zo;
-                        Buf<S>::st(enc<S, M>(a, key), dft, vo, so);
-                        Buf<S>::st(enc<S, M>(d, key + (uint64_t)g.N), ddd, vo, so);
+                        Buf<S>::st(enc<S, M>(a, sr_bits(salt, n, 2 * i)), dft, vo, so);
+                        Buf<S>::st(enc<S, M>(d, sr_bits(salt, n, 2 * i + 1)), ddd, vo, so);
                     });
                 cout[n] = Fn > P.gamma ? 1 : 0;
             }

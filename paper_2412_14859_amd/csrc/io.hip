@@ -10,9 +10,9 @@ namespace cge {
 // stochastically, as the step does: a uniform initial state rounded to nearest would give every
 // bulk node the same rounding error, which adds up to a mass offset over the domain.
 template <typename S>
-__device__ __forceinline__ S enc_import(double v, uint64_t key) {
+__device__ __forceinline__ S enc_import(double v, uint32_t bits) {
     if constexpr (std::is_same<S, _Float16>::value)
-        return enc<_Float16, float>(static_cast<float>(v), key);
+        return enc<_Float16, float>(static_cast<float>(v), bits);
     else
         return static_cast<S>(v);
 }
@@ -33,9 +33,8 @@ __device__ __forceinline__ void store_prestream(S* __restrict__ dst, const uint8
     // the shift and encoding depend on the direction the value is stored under; the
     // bounce-back pair (i, opp(i)) shares the same rest weight, so either index gives it
     const double tref = rho_ref * (restA<Q>(i) + restB<Q>(i) * alpha_ref);
-    const uint64_t key = salt + (uint64_t)(2 * di) * (uint64_t)g.N + (uint64_t)sn;
-    dst[(long long)di * g.N + sn] = enc_import<S>(fr + fb - tref, key);
-    dst[(long long)(Q + di) * g.N + sn] = enc_import<S>(fr - fb, key + (uint64_t)g.N);
+    dst[(long long)di * g.N + sn] = enc_import<S>(fr + fb - tref, sr_bits(salt, sn, 2 * di));
+    dst[(long long)(Q + di) * g.N + sn] = enc_import<S>(fr - fb, sr_bits(salt, sn, 2 * di + 1));
 }
 
 template <int Q, typename S, bool WALLS>

@@ -61,9 +61,7 @@ __device__ __forceinline__ _Float16 sr_half(float v, uint32_t r) {
 }
 
 // 32-bit finaliser of MurmurHash3 (Appleby): a bijection with full avalanche, used to turn a
-// rounding key into random bits.  Within one step the keys of all stored values differ in
-// their low 32 bits while 2 Q N < 2^32 (above that, values far apart share random bits, which
-// leaves each rounding unbiased), and the per-step salt randomises those bits.
+// node's rounding key into random bits.
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     h ^= h >> 16;
     h *= 0x85EBCA6Bu;
@@ -72,23 +70,35 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h ^ (h >> 16);
 }
 
-// rounding to the storage type: nearest for double/float, stochastic for half
+// Random bits for the stochastic rounding of stored value `slot` (0 .. 2Q - 1: ft_i in slot
+// 2i, dd_i in slot 2i + 1) of node n in the step whose salt is `salt`: the finaliser of the
+// node's key salt + n, then a Weyl sequence over the slots (increment 2^32 over the golden
+// ratio), so the 2Q values of a node cost one hash.  Each value's bits are uniform wherever the
+// node's hash is, which is all the rounding's unbiasedness needs.  Within one step the nodes'
+// keys differ while N < 2^32, and the per-step salt randomises them.
+__device__ __forceinline__ uint32_t sr_bits(uint64_t salt, long long n, int slot) {
+    return fmix32(static_cast<uint32_t>(salt + static_cast<uint64_t>(n))) +
+           static_cast<uint32_t>(slot) * 0x9E3779B9u;
+}
+
+// rounding to the storage type: nearest for double/float, stochastic for half (bits from
+// sr_bits)
 template <typename S, typename M>
-__device__ __forceinline__ S enc(M v, uint64_t key) {
+__device__ __forceinline__ S enc(M v, uint32_t bits) {
     return static_cast<S>(v);
 }
 template <>
-__device__ __forceinline__ _Float16 enc<_Float16, float>(float v, uint64_t key) {
-    return sr_half(v, fmix32(static_cast<uint32_t>(key)));
+__device__ __forceinline__ _Float16 enc<_Float16, float>(float v, uint32_t bits) {
+    return sr_half(v, bits);
 }
 template <typename S, typename M>
-__device__ __forceinline__ void st(S* p, M v, uint64_t key) {
-    *p = enc<S, M>(v, key);
+__device__ __forceinline__ void st(S* p, M v, uint32_t bits) {
+    *p = enc<S, M>(v, bits);
 }
 // The same with a streaming (non-temporal) hint: the value is not read again in this step.
 template <typename S, typename M>
-__device__ __forceinline__ void st_nt(S* p, M v, uint64_t key) {
-    __builtin_nontemporal_store(enc<S, M>(v, key), p);
+__device__ __forceinline__ void st_nt(S* p, M v, uint32_t bits) {
+    __builtin_nontemporal_store(enc<S, M>(v, bits), p);
 }
 
 // neighbour coordinates with periodic wrap
@@ -208,6 +218,17 @@ __device__ __forceinline__ RowOff row_offsets_at(const Geo& g, const RowPos& p, 
         r.xo[d] = (uint32_t)wrapc(x - 1 + d, g.nx) * (uint32_t)sizeof(T);
     }
     return r;
+}
+
+// A pointer known to be the same in every lane, kept in scalar registers: the address of an
+// access through it plus a 32-bit lane offset is then the scalar-base form of the instruction
+// (no 64-bit vector address arithmetic per access).
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return reinterpret_cast<T*>((static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 template <typename T>

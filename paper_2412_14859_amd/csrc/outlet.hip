@@ -73,9 +73,9 @@ __global__ __launch_bounds__(kTPBX) void k_outlet(S* __restrict__ pop,
             di = Lat<Q>::opp[i];
         }
         const double tref = P.rho_ref * (restA<Q>(di) + restB<Q>(di) * P.alpha_ref);
-        const uint64_t key = salt + (uint64_t)(2 * di) * (uint64_t)g.N + (uint64_t)sn;
-        st(pop + (long long)di * g.N + sn, static_cast<M>(f - tref), key);   // f^r = 0
-        st(pop + (long long)(Q + di) * g.N + sn, static_cast<M>(-f), key + (uint64_t)g.N);
+        st(pop + (long long)di * g.N + sn, static_cast<M>(f - tref),
+           sr_bits(salt, sn, 2 * di));  // f^r = 0
+        st(pop + (long long)(Q + di) * g.N + sn, static_cast<M>(-f), sr_bits(salt, sn, 2 * di + 1));
     }
 }
 
