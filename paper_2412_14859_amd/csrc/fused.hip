@@ -418,8 +418,8 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
                     rN, u, F, P,
                     [&](int i, M a, M d) {
                         const uint32_t so = (uint32_t)i * slot_bytes + zo;
-                        Buf<S>::st(enc<S, M>(a, sr_bits(salt, n, 2 * i)), dft, vo, so);
-                        Buf<S>::st(enc<S, M>(d, sr_bits(salt, n, 2 * i + 1)), ddd, vo, so);
+                        Buf<S>::st(enc<S, M>(a, sr_bits(salt, g.N, n, 2 * i)), dft, vo, so);
+                        Buf<S>::st(enc<S, M>(d, sr_bits(salt, g.N, n, 2 * i + 1)), ddd, vo, so);
                     });
                 cout[n] = Fn > P.gamma ? 1 : 0;
             }

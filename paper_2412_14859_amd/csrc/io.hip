@@ -33,8 +33,8 @@ __device__ __forceinline__ void store_prestream(S* __restrict__ dst, const uint8
     // the shift and encoding depend on the direction the value is stored under; the
     // bounce-back pair (i, opp(i)) shares the same rest weight, so either index gives it
     const double tref = rho_ref * (restA<Q>(i) + restB<Q>(i) * alpha_ref);
-    dst[(long long)di * g.N + sn] = enc_import<S>(fr + fb - tref, sr_bits(salt, sn, 2 * di));
-    dst[(long long)(Q + di) * g.N + sn] = enc_import<S>(fr - fb, sr_bits(salt, sn, 2 * di + 1));
+    dst[(long long)di * g.N + sn] = enc_import<S>(fr + fb - tref, sr_bits(salt, g.N, sn, 2 * di));
+    dst[(long long)(Q + di) * g.N + sn] = enc_import<S>(fr - fb, sr_bits(salt, g.N, sn, 2 * di + 1));
 }
 
 template <int Q, typename S, bool WALLS>

@@ -71,14 +71,16 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 }
 
 // Random bits for the stochastic rounding of stored value `slot` (0 .. 2Q - 1: ft_i in slot
-// 2i, dd_i in slot 2i + 1) of node n in the step whose salt is `salt`: the finaliser of the
-// node's key salt + n, then a Weyl sequence over the slots (increment 2^32 over the golden
-// ratio), so the 2Q values of a node cost one hash.  Each value's bits are uniform wherever the
-// node's hash is, which is all the rounding's unbiasedness needs.  Within one step the nodes'
-// keys differ while N < 2^32, and the per-step salt randomises them.
-__device__ __forceinline__ uint32_t sr_bits(uint64_t salt, long long n, int slot) {
-    return fmix32(static_cast<uint32_t>(salt + static_cast<uint64_t>(n))) +
-           static_cast<uint32_t>(slot) * 0x9E3779B9u;
+// 2i, dd_i in slot 2i + 1) of node n in the step whose salt is `salt`: the finaliser of the key
+// salt + slot N + n.  Within one step the keys of all stored values differ in their low 32
+// bits while 2 Q N < 2^32 (above that, values far apart share random bits, which leaves each
+// rounding unbiased), and the per-step salt randomises those bits.  Every value has bits of
+// its own: deriving a node's values from one hash (a Weyl sequence over the slots) ties their
+// low bits to one random offset, and the population error of the 128^2 drop after 2000 steps
+// at frozen site sets grew from 3.1e-3 to 5.9e-3.
+__device__ __forceinline__ uint32_t sr_bits(uint64_t salt, long long N, long long n, int slot) {
+    return fmix32(static_cast<uint32_t>(salt + static_cast<uint64_t>(slot) * static_cast<uint64_t>(N) +
+                                        static_cast<uint64_t>(n)));
 }
 
 // rounding to the storage type: nearest for double/float, stochastic for half (bits from

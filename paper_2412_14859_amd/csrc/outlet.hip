@@ -74,8 +74,8 @@ __global__ __launch_bounds__(kTPBX) void k_outlet(S* __restrict__ pop,
         }
         const double tref = P.rho_ref * (restA<Q>(di) + restB<Q>(di) * P.alpha_ref);
         st(pop + (long long)di * g.N + sn, static_cast<M>(f - tref),
-           sr_bits(salt, sn, 2 * di));  // f^r = 0
-        st(pop + (long long)(Q + di) * g.N + sn, static_cast<M>(-f), sr_bits(salt, sn, 2 * di + 1));
+           sr_bits(salt, g.N, sn, 2 * di));  // f^r = 0
+        st(pop + (long long)(Q + di) * g.N + sn, static_cast<M>(-f), sr_bits(salt, g.N, sn, 2 * di + 1));
     }
 }
 

