@@ -47,11 +47,12 @@ namespace cge {
 
 constexpr int kFTX = 64;  // tile width in x: one wavefront per row
 // Tile rows per workgroup.  At general relaxation times a thread holds one pulled node's
-// moments and the 38 loads of a pull in flight, and the FP64 collision: 170 registers at FP32
-// storage, two waves per SIMD.  Four rows (two workgroups per CU that do not wait on each
-// other's barriers) ran the 384 x 384 x 192 sessile drop in 3.05 ms per step, eight rows in
-// 3.25 ms; capping the registers for three waves per SIMD left fewer loads in flight per wave
-// (5.4 ms).
+// moments and the 38 loads of a pull in flight, and the FP64 collision: 167 registers at FP32
+// storage with plane walls, three waves per SIMD (three workgroups per CU by their LDS).  The
+// 384 x 384 x 192 sessile drop runs in 2.52 ms per step.  Eight rows ran slower (fewer
+// workgroups per CU, which then wait on each other's barriers), and so did issuing a plane's
+// own pull one plane ahead of the previous plane's collision (2.77 ms: the loads held across
+// the collision take two waves per SIMD).
 constexpr int kFTY = 4;
 
 // Kinds of the z-planes under plane walls.
@@ -164,12 +165,16 @@ __device__ __forceinline__ M pull_node(__amdgpu_buffer_rsrc_t rft, __amdgpu_buff
                                        const Plane9<S>& pl, const uint32_t (&zoff)[3],
                                        uint32_t slot_bytes, uint32_t bb, const Phys<M>& P,
                                        const uint8_t* __restrict__ cin,
-                                       const void* __restrict__ phi_field, uint32_t n,
+                                       __amdgpu_buffer_rsrc_t rphi, bool has_phi, uint32_t n,
                                        Pulled<Q, S, M, UNIT>& pn, S* __restrict__ ft_out,
                                        int ft_stride) {
-    // the site byte and flux do not depend on the populations: fetch them first
+    // The site byte and flux do not depend on the populations: fetch them first, and convert
+    // the flux only after the population loads are issued, so no wait for it comes first (a
+    // wait for one load is a wait for every earlier load and store of the wave).  The flux
+    // goes through a buffer resource with no records when no field is bound (the load then
+    // returns 0 and touches no memory), so the load needs no branch and stays up front.
     const uint8_t cb = cin[n];
-    const M phi = phi_field ? static_cast<M>(static_cast<const PhiT<S>*>(phi_field)[n]) : P.phi;
+    const PhiT<S> phi_raw = Buf<PhiT<S>>::ld(rphi, n * (uint32_t)sizeof(PhiT<S>), 0);
     M drho = M(0), dsum = M(0), j[3] = {M(0), M(0), M(0)};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -191,6 +196,7 @@ __device__ __forceinline__ M pull_node(__amdgpu_buffer_rsrc_t rft, __amdgpu_buff
         }
     }
     const M rho = P.rho_ref + drho;
+    const M phi = has_phi ? static_cast<M>(phi_raw) : P.phi;
     const M s = site_sink_pre<M>(P, cb, phi, rho, dsum);
     const M dpost = dsum - M(2) * s;
     if (FULL) {
@@ -240,6 +246,8 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     // direction i of its node at ftl[p & 1][i][t] (written by its pull of plane p, read by its
     // finish of plane p one plane later; no other thread touches the slot)
     __shared__ S ftl[UNIT ? 1 : 2][UNIT ? 1 : Q][kFTX * kFTY];
+    // plane kinds of the chunk (plane walls): fused_kinds_bytes(zlen) bytes of dynamic LDS
+    extern __shared__ uint8_t kinds[];
 
     const int tid = threadIdx.x;
     const int lx = tid % kFTX, ly = tid / kFTX;
@@ -288,6 +296,10 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     const __amdgpu_buffer_rsrc_t dft = __builtin_amdgcn_make_buffer_rsrc(dst, 0, range, 0x00020000);
     const __amdgpu_buffer_rsrc_t ddd =
         __builtin_amdgcn_make_buffer_rsrc(dst + QN, 0, range, 0x00020000);
+    const bool has_phi = phi_field != nullptr;
+    const __amdgpu_buffer_rsrc_t rphi = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<void*>(phi_field), 0, has_phi ? (int)((uint32_t)g.N * (uint32_t)sizeof(PhiT<S>)) : 0,
+        0x00020000);
 
     const Plane9<S> po = plane9<S>(g, x, y);    // own node's neighbourhood
     const Plane9<S> pr = plane9<S>(g, gx, gy);  // ring node's neighbourhood
@@ -295,8 +307,16 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     const uint32_t ring_xy = (uint32_t)gx + (uint32_t)g.nx * (uint32_t)gy;
     const uint32_t nplane = (uint32_t)g.nx * (uint32_t)g.ny;
 
+    // Kinds of the planes z0 - 3 .. z1 + 1 (every plane the chunk asks about), copied once into
+    // LDS: read from global memory in the loop, each would cost a wait for all of the wave's
+    // loads and stores in flight.
+    const int z0k = z0 - 3;
+    if (PW) {
+        for (int t = tid; t < z1 - z0 + 5; t += kFTX * kFTY) kinds[t] = pkind[wrapf(z0k + t, g.nz)];
+        __syncthreads();
+    }
     auto kind = [&](int zp) -> uint32_t {
-        return PW ? (uint32_t)__builtin_amdgcn_readfirstlane(pkind[wrapf(zp, g.nz)]) : 0u;
+        return PW ? (uint32_t)__builtin_amdgcn_readfirstlane(kinds[zp - z0k]) : 0u;
     };
     // wetting value of the solid node at LDS position (yy, xx) of a plane from the fluid
     // plane in LDS slot sf on the side dz (the neighbours x + c_i with c_z = dz), summed in
@@ -340,12 +360,12 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
             M r_ring = M(0), r_own = M(0), r_ring2 = M(0);
             if (ring)
                 r_ring = pull_node<Q, S, M, false, UNIT, PW>(sft, sdd, pr, zoff, slot_bytes, bb, P,
-                                                             cin, phi_field,
+                                                             cin, rphi, has_phi,
                                                              ring_xy + (uint32_t)pz * nplane, nxt,
                                                              nullptr, 0);
             if (own)
                 r_own = pull_node<Q, S, M, true, UNIT, PW>(sft, sdd, po, zoff, slot_bytes, bb, P,
-                                                           cin, phi_field,
+                                                           cin, rphi, has_phi,
                                                            own_xy + (uint32_t)pz * nplane, nxt,
                                                            &ftl[UNIT ? 0 : (p & 1)][0][tid],
                                                            kFTX * kFTY);
@@ -354,7 +374,7 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
                 const int g2x = wrapf(x0 + r2x, g.nx), g2y = wrapf(y0 + r2y, g.ny);
                 const Plane9<S> p2 = plane9<S>(g, g2x, g2y);
                 r_ring2 = pull_node<Q, S, M, false, UNIT, PW>(
-                    sft, sdd, p2, zoff, slot_bytes, bb, P, cin, phi_field,
+                    sft, sdd, p2, zoff, slot_bytes, bb, P, cin, rphi, has_phi,
                     (uint32_t)g2x + (uint32_t)g.nx * (uint32_t)g2y + (uint32_t)pz * nplane, nxt,
                     nullptr, 0);
             }
@@ -516,6 +536,9 @@ bool fused_supported(const cge_ctx* c) {
            c->p.site_rule != CGE_SITE_SOFT && 19ll * c->g.N * elem < (1ll << 32);
 }
 
+// dynamic LDS of a workgroup: the kinds of the planes z0 - 3 .. z1 + 1 of its chunk
+static size_t fused_kinds_bytes(int zlen) { return ((size_t)zlen + 5 + 3) & ~(size_t)3; }
+
 // workgroups of the fused step at one plane per chunk, the most any chunk length gives
 long long fused_blocks(const cge_ctx* c) { return fused_shape(c->g, 1).nb; }
 
@@ -533,6 +556,7 @@ static cge_status fused_impl(cge_ctx* c, long long nsteps) {
         const bool unit = c->p.tau[0] == 1.0 && c->p.tau[1] == 1.0;
         uint8_t* mask[2] = {c->carry, c->carry2};
         const uint8_t* pk = WALLS ? c->pkind : nullptr;
+        const size_t kbytes = WALLS ? fused_kinds_bytes(fs.zlen) : 0;
         int m = 0;
         for (long long t = 0; t < nsteps; ++t) {
             const S* src = static_cast<const S*>(c->pop[c->cur]);
@@ -541,12 +565,12 @@ static cge_status fused_impl(cge_ctx* c, long long nsteps) {
             timing_begin(c, "fused step");
             if (unit)
                 hipLaunchKernelGGL((k_fused<Q, S, M, true, WALLS>), dim3((unsigned)fs.nb),
-                                   dim3(kFTX * kFTY), 0, c->stream, src, dst, mask[m],
+                                   dim3(kFTX * kFTY), kbytes, c->stream, src, dst, mask[m],
                                    mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites, c->g,
                                    P, salt, fs);
             else
                 hipLaunchKernelGGL((k_fused<Q, S, M, false, WALLS>), dim3((unsigned)fs.nb),
-                                   dim3(kFTX * kFTY), 0, c->stream, src, dst, mask[m],
+                                   dim3(kFTX * kFTY), kbytes, c->stream, src, dst, mask[m],
                                    mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites, c->g,
                                    P, salt, fs);
             timing_pass(c, "k_fused");
