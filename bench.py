@@ -677,6 +677,10 @@ def c4_benchmark(steps=20000, every=2000, precision="fp32s"):
                                                 / HBM_PEAK_GBS, 4),
             "v_mass_start": hist[0][1], "v_mass_end": obs["v_mass"],
             "sink_total": obs["sink_total"], "site_steps": obs["site_steps"],
+            # red mass removed (V_mass is M_r over the liquid density 1) against the sink's FP64
+            # bookkeeping: equal up to the rounding of the stored populations
+            "red_mass_balance_rel": ((hist[0][1] - obs["v_mass"]) - obs["sink_total"])
+                                    / obs["sink_total"],
             "vapour_rho_b_mean": [[h[0], round(h[2], 7)] for h in hist],
             "vapour_rho_b_drift": (hist[-1][2] - hist[0][2]) / hist[0][2],
             "vapour_nodes_start_end": [hist[0][4], hist[-1][4]],
@@ -810,8 +814,8 @@ def main():
         print(json.dumps(c2_benchmark()), flush=True)
         return
     if args.c4:
-        print(json.dumps(c4_benchmark(steps=args.steps if args.steps != 200 else 20000)),
-              flush=True)
+        print(json.dumps(c4_benchmark(steps=args.steps if args.steps != 200 else 20000,
+                                      precision=args.precision)), flush=True)
         return
     if args.gamma_calibration:
         print(json.dumps(gamma_calibration_benchmark()), flush=True)
