@@ -73,7 +73,7 @@ def pass_bytes_per_node(kernel, Q, precision, walls=False, phi_field=False):
     elem = {"fp64": 8, "fp32s": 4, "fp16s": 2}[precision]
     mom_e = 8 if precision == "fp64" else 4
     pops = 2 * Q * elem
-    rec = 14 * (8 if precision == "fp64" else 4)
+    rec = 14 * elem
     extra = (4 if phi_field else 0) + (1 if walls else 0)
     inter = 5 * mom_e  # rho^N + (drho, j)
     table = {
@@ -866,12 +866,18 @@ def main():
                                 "call (record form), shifted populations at call boundaries",
                ("fp64", True): "fp64: 14-value post-collision records between the steps of a "
                                "call (record form), populations at call boundaries",
+               ("fp16s", True): "fp16: 14-value post-collision records between the steps of a "
+                                "call (record form), shifted populations at call boundaries, "
+                                "stochastic rounding",
                ("fp32s", False): "fp32 shifted populations", ("fp64", False): "fp64 populations",
                ("fp16s", False): "fp16 shifted populations, stochastic rounding"}
     record = main_leg["kernel"] == "k_pull_record"
     arithmetic = {("fp32s", True): "pulled populations rebuilt from the FP32 records in FP32; "
                                    "moment sums, collision, perturbation and recolouring in FP64",
-                  ("fp64", True): "FP64", ("fp32s", False): "FP64 on FP32-stored values",
+                  ("fp64", True): "FP64",
+                  ("fp16s", True): "FP32 (pulled populations rebuilt from the half records in "
+                                   "FP32)",
+                  ("fp32s", False): "FP64 on FP32-stored values",
                   ("fp64", False): "FP64", ("fp16s", False): "FP32 on FP16-stored values"}
     pop_bpn = main_leg["population_equivalent_bytes_per_node"]
     out = {

@@ -79,15 +79,14 @@ typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } 
  *            recolouring (Eq. recolor)) instead of its 2Q populations.  The first step of
  *            a call pulls populations and the last writes them, so between calls the state
  *            is populations as for every other form; a call of one step is SPLIT's step.
- *            Same support as SPLIT, except FP16S (CGE_EUNSUPPORTED at cge_create: its FP32
- *            records would keep the state between steps at FP32, not half precision); needs
- *            14 N values of library scratch (FP64 at FP64 storage, FP32 otherwise; rows
- *            padded to 256 B), allocated at cge_create for RECORD, and for AUTO where AUTO
- *            selects it.
- *   AUTO:    at unit relaxation times RECORD for D3Q19 at FP64 and FP32 storage, SPLIT for
- *            D2Q9 (where the record pull has no LDS-staged form and is no faster) and at FP16
- *            storage (whose state between steps then stays in half precision); otherwise
- *            FUSED where supported, else TWOPASS.
+ *            Same support as SPLIT.  The record is stored like the populations: FP64, FP32,
+ *            or half precision with stochastic rounding at FP16S (then rebuilt in FP32), so
+ *            the state between steps keeps the storage precision.  Needs 14 N values of
+ *            library scratch in that type (rows padded to 256 B), allocated at cge_create for
+ *            RECORD, and for AUTO where AUTO selects it.
+ *   AUTO:    at unit relaxation times RECORD for D3Q19 and SPLIT for D2Q9 (where the record
+ *            pull has no LDS-staged form and is no faster); otherwise FUSED where supported,
+ *            else TWOPASS.
  * All give the same results up to rounding. */
 typedef enum {
     CGE_KERNEL_AUTO = 0,
@@ -294,8 +293,8 @@ cge_status cge_set_height_flux(cge_ctx* ctx, double phi_s, double K, double h_sc
  * adjoint returns CGE_EUNSUPPORTED while outlets are on. */
 cge_status cge_set_outlet(cge_ctx* ctx, int lo, int hi, double rho_out);
 
-/* Launch shape of the z-marching kernels (the record form's pull at FP32 records, the fused
- * step): planes per z-chunk of a block's march.  0 (the default) chooses it from the grid
+/* Launch shape of the z-marching kernels (the record form's pull at FP32 and half records,
+ * the fused step): planes per z-chunk of a block's march.  0 (the default) chooses it from the grid
  * (and, for the record pull, the device's compute-unit count); planes > 0 takes that many
  * (at most nz).  Results do not depend on it beyond the grouping of the FP64 sink partials
  * (1e-15 relative).  For tuning, and for tests of chunked marches on small grids.

@@ -192,10 +192,9 @@ static ScratchPlan scratch_plan(const cge_params* p) {
     const int Q = p->lattice;
     const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
     const bool unit = p->tau[0] == 1.0 && p->tau[1] == 1.0;
-    // records where the record form may run: selected, or chosen by AUTO (unit tau, D3Q19,
-    // FP64 or FP32 storage)
+    // records where the record form may run: selected, or chosen by AUTO (unit tau, D3Q19)
     const bool rec = unit && (p->kernel == CGE_KERNEL_RECORD ||
-                              (p->kernel == CGE_KERNEL_AUTO && p->precision != CGE_FP16S && Q == 19));
+                              (p->kernel == CGE_KERNEL_AUTO && Q == 19));
     const size_t mbytes = p->precision == CGE_FP16S ? 4 : 8;  // the widest use of the field
     const dim3 gr = node_grid(g);
     const size_t nblk = (size_t)gr.x * gr.y * gr.z;
@@ -235,15 +234,12 @@ static cge_status create_ctx(const cge_params* params, void* hip_stream, void* s
         delete c;
         return CGE_EDEVICE;
     }
-    // the fused step needs D3Q19 and no solid nodes (the latter is known at cge_bind); the
-    // split step needs unit relaxation times; the record form keeps FP32 records between the
-    // steps of a call, so at FP16 storage only a call's last step would store half precision:
-    // refused rather than mislabelled
+    // the fused step needs D3Q19 and no solid nodes other than plane walls (the latter is known
+    // at cge_bind); the split step and the record form need unit relaxation times
     const bool unit = split_supported(c);
     const bool soft = params->site_rule == CGE_SITE_SOFT;
     if ((params->kernel == CGE_KERNEL_FUSED && (c->Q != 19 || soft)) ||
-        ((params->kernel == CGE_KERNEL_SPLIT || params->kernel == CGE_KERNEL_RECORD) && !unit) ||
-        (params->kernel == CGE_KERNEL_RECORD && params->precision == CGE_FP16S)) {
+        ((params->kernel == CGE_KERNEL_SPLIT || params->kernel == CGE_KERNEL_RECORD) && !unit)) {
         delete c;
         return CGE_EUNSUPPORTED;
     }

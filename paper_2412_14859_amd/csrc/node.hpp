@@ -312,6 +312,13 @@ using MomT = typename std::conditional<std::is_same<S, double>::value, double, f
 template <typename S>
 using PhiT = typename std::conditional<std::is_same<S, double>::value, double, float>::type;
 
+// Post-collision record of the record form: stored like the populations (double, float or
+// half), rebuilt in the arithmetic type RecE (float for a half record).
+template <typename S>
+using RecT = typename std::conditional<std::is_same<S, float>::value, float, S>::type;
+template <typename R>
+using RecE = typename std::conditional<std::is_same<R, _Float16>::value, float, R>::type;
+
 template <typename S, typename M>
 __device__ __forceinline__ M node_phi(const Phys<M>& P, const void* __restrict__ phi_field,
                                       long long n) {
@@ -432,15 +439,18 @@ __device__ __forceinline__ M collide(Load&& load, M drho, M rho, M rhoN, const M
 
 // Post-collision record of a node at unit relaxation times (omega_r = omega_b = 1).  BGK
 // relaxation then returns the equilibrium, so collide()'s populations of the node are, per
-// weight class k and direction i of that class (h_k = W_k / W_1),
-//   ft_i* = b_k + h_k A (c_i.u)(1 + 1.5 c_i.u) + h_k P (F.c_i)^2
-//   dd_i* = rho^N (ft_i* + t_ref,k) + g_k (F.c_i)
-// with A = 3 W_1 rho, P = W_1 kp / |F| (0 where F.F <= kF2Cut), b_k = base_k - kc_k and
-// g_k = gs_k formed as in
-// collide (t_ref,k = rho_ref t_k(alpha_ref)).  The record is b_0, b_1, b_2, A, P, u, F,
-// rho^N, g_1, g_2: 14 values instead of 2Q populations.  Returns ||F||.
+// weight class k and direction i of that class (h_k = W_k / W_1), with n = F / |F| the unit
+// normal (0 where F.F <= kF2Cut):
+//   ft_i* = b_k + h_k A (c_i.u)(1 + 1.5 c_i.u) + h_k P (n.c_i)^2
+//   dd_i* = rho^N (ft_i* + t_ref,k) + g_k (n.c_i)
+// with A = 3 W_1 rho, P = W_1 kp |F| (so that h_k P (n.c_i)^2 is the perturbation's
+// W_k kp (F.c_i)^2 / |F|), b_k = base_k - kc_k and g_k = |F| gs_k (so that g_k (n.c_i) is the
+// recolouring term gs_k (F.c_i)), where base_k, kc_k and gs_k are formed as in collide and
+// t_ref,k = rho_ref t_k(alpha_ref).  The record is b_0, b_1, b_2, A, P, u, n, rho^N, g_1, g_2:
+// 14 values instead of 2Q populations, each bounded by the state (a record holding F and
+// kp / |F| instead would overflow half precision where F is tiny).  Returns ||F||.
 constexpr int kRec = 14;
-enum RecSlot { kB0 = 0, kB1, kB2, kA3, kP1, kUx, kUy, kUz, kFx, kFy, kFz, kRhoN, kG1, kG2 };
+enum RecSlot { kB0 = 0, kB1, kB2, kA3, kP1, kUx, kUy, kUz, kNx, kNy, kNz, kRhoN, kG1, kG2 };
 
 template <int Q, typename M>
 __device__ __forceinline__ M record_values(M drho, M rho, M rhoN, const M (&u)[3],
@@ -458,7 +468,8 @@ __device__ __forceinline__ M record_values(M drho, M rho, M rhoN, const M (&u)[3
     const M invFn = hg ? M(1) / Fn : M(0);
     const M kp = M(2.25) * P.sigma * omega;
     const M sep = M(0.5) * P.beta * (M(1) - rhoN * rhoN) * rho;
-    const M cosw = invFn * recolor_fade(Fn, P.inv_fade);
+    // |F| cos(theta) / (F.c_i / |c_i|) = 1, times the optional fade, where F.F > kF2Cut
+    const M fade = hg ? recolor_fade(Fn, P.inv_fade) : M(0);
     constexpr int i1 = 1, i2 = Q == 9 ? 5 : 7;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -466,28 +477,28 @@ __device__ __forceinline__ M record_values(M drho, M rho, M rhoN, const M (&u)[3
         const M A = M(restA<Q>(i)), B = M(restB<Q>(i)), W = M(weight<Q>(i));
         const M base = A * drho + B * dB - M(1.5) * (W * rho) * uu;
         r[kB0 + k] = base - kp * M(pertC<Q>(i)) * Fp;
-        if (k > 0) r[kG1 + k - 1] = sep * cosw * M(inv_len<Q>(i)) * (A + B * abar);
+        if (k > 0) r[kG1 + k - 1] = sep * fade * M(inv_len<Q>(i)) * (A + B * abar);
     }
     const M W1 = M(weight<Q>(i1));
     r[kA3] = M(3) * W1 * rho;
-    r[kP1] = W1 * (kp * invFn);
+    r[kP1] = W1 * (kp * Fp);
     r[kUx] = u[0];
     r[kUy] = u[1];
     r[kUz] = u[2];
-    r[kFx] = F[0];
-    r[kFy] = F[1];
-    r[kFz] = F[2];
+    r[kNx] = F[0] * invFn;
+    r[kNy] = F[1] * invFn;
+    r[kNz] = F[2] * invFn;
     r[kRhoN] = rhoN;
     return Fn;
 }
 
 // ft_i* and the colour difference of direction i (sgn = -1: of the opposite direction, for
-// the bounce-back) from the record, in the record's precision E; L(slot) loads one record
-// value of the source node.  dd_i* is returned in two parts, dd_i* = dp + rn t_ref,k:
-// dp = rho^N ft_i* + g_k (F.c_i) and the source's rn = rho^N.  The caller adds rn t_ref,k in
-// its arithmetic type: formed in E, the rounding of t_ref,k would repeat at every node and
-// step and move red mass steadily between the bulks.  Only the values direction i needs are
-// loaded.
+// the bounce-back) from the record, in the record's arithmetic type E; L(slot) loads one
+// record value of the source node as E.  dd_i* is returned in two parts, dd_i* = dp + rn
+// t_ref,k: dp = rho^N ft_i* + g_k (n.c_i) and the source's rn = rho^N.  The caller adds rn
+// t_ref,k in its arithmetic type: formed in E, the rounding of t_ref,k would repeat at every
+// node and step and move red mass steadily between the bulks.  Only the values direction i
+// needs are loaded.
 template <int Q, typename E, typename Load>
 __device__ __forceinline__ void record_dir(int i, E sgn, Load&& L, E& a, E& dp, E& rn) {
     const int k = norm2<Q>(i);
@@ -497,26 +508,26 @@ __device__ __forceinline__ void record_dir(int i, E sgn, Load&& L, E& a, E& dp, 
         dp = rn * a;
         return;
     }
-    E cu = E(0), Fc = E(0);
+    E cu = E(0), nc = E(0);
     if (Lat<Q>::cx[i]) {
         cu += E(Lat<Q>::cx[i]) * L(kUx);
-        Fc += E(Lat<Q>::cx[i]) * L(kFx);
+        nc += E(Lat<Q>::cx[i]) * L(kNx);
     }
     if (Lat<Q>::cy[i]) {
         cu += E(Lat<Q>::cy[i]) * L(kUy);
-        Fc += E(Lat<Q>::cy[i]) * L(kFy);
+        nc += E(Lat<Q>::cy[i]) * L(kNy);
     }
     if (Lat<Q>::cz[i]) {
         cu += E(Lat<Q>::cz[i]) * L(kUz);
-        Fc += E(Lat<Q>::cz[i]) * L(kFz);
+        nc += E(Lat<Q>::cz[i]) * L(kNz);
     }
     cu *= sgn;
-    Fc *= sgn;
+    nc *= sgn;
     constexpr double h = weight<Q>(Q == 9 ? 5 : 7) / weight<Q>(1);  // W_2 / W_1
     const E hk = k == 1 ? E(1) : E(h);
     a = L(k == 1 ? kB1 : kB2) + L(kA3) * (cu * (hk + E(1.5) * hk * cu));
-    a += (hk * L(kP1)) * (Fc * Fc);
-    dp = rn * a + L(k == 1 ? kG1 : kG2) * Fc;
+    a += (hk * L(kP1)) * (nc * nc);
+    dp = rn * a + L(k == 1 ? kG1 : kG2) * nc;
 }
 
 // The record slots record_dir reads for direction i (bit sl set), for callers that load them
@@ -527,9 +538,9 @@ __host__ __device__ constexpr uint32_t dir_slots(int i) {
     if (k == 0) return (1u << kRhoN) | (1u << kB0);
     uint32_t m = (1u << kRhoN) | (1u << (k == 1 ? kB1 : kB2)) | (1u << kA3) | (1u << kP1) |
                  (1u << (k == 1 ? kG1 : kG2));
-    if (Lat<Q>::cx[i]) m |= (1u << kUx) | (1u << kFx);
-    if (Lat<Q>::cy[i]) m |= (1u << kUy) | (1u << kFy);
-    if (Lat<Q>::cz[i]) m |= (1u << kUz) | (1u << kFz);
+    if (Lat<Q>::cx[i]) m |= (1u << kUx) | (1u << kNx);
+    if (Lat<Q>::cy[i]) m |= (1u << kUy) | (1u << kNy);
+    if (Lat<Q>::cz[i]) m |= (1u << kUz) | (1u << kNz);
     return m;
 }
 

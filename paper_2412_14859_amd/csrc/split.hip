@@ -240,7 +240,7 @@ __device__ __forceinline__ M ref_part(const Phys<M>& P, const M (&rn)[3]) {
 // x - c_i (of x itself, opposite direction, where x - c_i is solid), then the sink and the
 // moments exactly as k_moments.
 template <int Q, typename S, typename M, bool WALLS>
-__global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict__ rec,
+__global__ __launch_bounds__(kTPBX) void k_pull_record(const RecT<S>* __restrict__ rec,
                                                        const uint8_t* __restrict__ flags,
                                                        const void* __restrict__ carry,
                                                        const void* __restrict__ phi_field,
@@ -249,7 +249,8 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
                                                        double* __restrict__ acc_sink,
                                                        long long* __restrict__ acc_sites, Geo g,
                                                        Phys<M> P) {
-    using R = MomT<S>;
+    using R = RecT<S>;
+    using E = RecE<R>;  // the rebuild's arithmetic type
     using L = RecLayout<R>;
     int x, y, z;
     long long n;
@@ -271,25 +272,27 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
         const Nb b = WALLS ? wrap(g, x, y, z) : Nb{};
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            R ar, dr, rr;
+            E ar, dr, rr;
             if constexpr (WALLS) {
                 const int cx = Lat<Q>::cx[i], cy = Lat<Q>::cy[i], cz = Lat<Q>::cz[i];
                 int sx = cx == 1 ? b.xm : (cx == -1 ? b.xp : x);
                 int sy = cy == 1 ? b.ym : (cy == -1 ? b.yp : y);
                 int sz = cz == 1 ? b.zm : (cz == -1 ? b.zp : z);
-                R sgn = R(1);
+                E sgn = E(1);
                 if (i != 0 && flags[lin(g, sx, sy, sz)]) {  // halfway bounce-back: f_opp(i)*(x)
                     sx = x;
                     sy = y;
                     sz = z;
-                    sgn = R(-1);
+                    sgn = E(-1);
                 }
                 const R* base = rec + ((long long)sy + (long long)g.ny * sz) * rlen + L::in_row(sx);
-                record_dir<Q, R>(i, sgn, [&](int sl) { return base[sl * L::W]; }, ar, dr, rr);
+                record_dir<Q, E>(i, sgn, [&](int sl) { return static_cast<E>(base[sl * L::W]); },
+                                 ar, dr, rr);
             } else {
                 const R* base = rec + yr[1 - Lat<Q>::cy[i]] + zr[1 - Lat<Q>::cz[i]];
                 const uint32_t o = xo[1 - Lat<Q>::cx[i]];
-                record_dir<Q, R>(i, R(1), [&](int sl) { return ld_at(base + sl * L::W, o); },
+                record_dir<Q, E>(i, E(1),
+                                 [&](int sl) { return static_cast<E>(ld_at(base + sl * L::W, o)); },
                                  ar, dr, rr);
             }
             const M a = static_cast<M>(ar);
@@ -307,11 +310,11 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const MomT<S>* __restrict
         dsum -= M(2) * s;
         v[0] = static_cast<double>(s);
         v[1] = is_site(wgt) ? 1.0 : 0.0;
-        rhoN[n] = static_cast<R>(dsum / rho);
-        mom[n] = static_cast<R>(drho);
-        mom[g.N + n] = static_cast<R>(j[0]);
-        mom[2 * g.N + n] = static_cast<R>(j[1]);
-        mom[3 * g.N + n] = static_cast<R>(j[2]);
+        rhoN[n] = static_cast<MomT<S>>(dsum / rho);
+        mom[n] = static_cast<MomT<S>>(drho);
+        mom[g.N + n] = static_cast<MomT<S>>(j[0]);
+        mom[2 * g.N + n] = static_cast<MomT<S>>(j[1]);
+        mom[3 * g.N + n] = static_cast<MomT<S>>(j[2]);
     }
     const bool is_max[2] = {false, false};
     double out[2];
@@ -415,12 +418,14 @@ constexpr CzList cz_list(int cz) {
 
 template <typename S, typename M, bool WALLS, int TY>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(Zm<TY>::Waves, Zm<TY>::Waves))) void
-k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flags,
+k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
                  const void* __restrict__ carry, const void* __restrict__ phi_field,
                  float* __restrict__ rhoN, float* __restrict__ mom, double* __restrict__ acc_sink,
                  long long* __restrict__ acc_sites, Geo g, Phys<M> P, int zc) {
     constexpr int Q = 19;
-    using L = RecLayout<float>;
+    using R = RecT<S>;  // float, or half (then staged through registers, below)
+    constexpr bool kHalf = std::is_same<R, _Float16>::value;
+    using L = RecLayout<R>;
     using Z = Zm<TY>;
     // the two record buffers (plane p in ring0 when p - z0 is odd) and the flags of plane p
     // in slot p & 3 of fring
@@ -450,20 +455,32 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
     // the Z::HaloSeg rows 0 and H - 1 of the values are shared out over the waves.  Threads
     // tid < 2 kRec H load the two halo columns x0 - 1 and x0 + 64 through a register.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const uint32_t xin = L::in_row(wrapm(x0 + lane, g.nx)) * (uint32_t)sizeof(float);
+    const uint32_t xin = L::in_row(wrapm(x0 + lane, g.nx)) * (uint32_t)sizeof(R);
     const int hseg = tid >> 1, hside = tid & 1;
     const bool halo = tid < 2 * kRec * Z::H;
     const uint32_t hoff =
         halo ? (uint32_t)(((long long)wrapm(y0 - 1 + hseg % Z::H, g.ny) * rlen +
                            L::in_row(wrapm(hside ? x0 + Z::X : x0 - 1, g.nx)) +
-                           (hseg / Z::H) * L::W) * (long long)sizeof(float))
+                           (hseg / Z::H) * L::W) * (long long)sizeof(R))
              : 0u;
     const int hlds = hseg * Z::W + (hside ? Z::W - 1 : 0);
     // plane-relative byte offsets (below 2^31: checked at launch) of the wave's tile row and of
     // the two halo rows
-    const uint32_t row_own = (uint32_t)((long long)wrapm(y0 + wave, g.ny) * rlen * 4);
-    const uint32_t row_lo = (uint32_t)((long long)wrapm(y0 - 1, g.ny) * rlen * 4);
-    const uint32_t row_hi = (uint32_t)((long long)wrapm(y0 + TY, g.ny) * rlen * 4);
+    const uint32_t row_own = (uint32_t)((long long)wrapm(y0 + wave, g.ny) * rlen * (long long)sizeof(R));
+    const uint32_t row_lo = (uint32_t)((long long)wrapm(y0 - 1, g.ny) * rlen * (long long)sizeof(R));
+    const uint32_t row_hi = (uint32_t)((long long)wrapm(y0 + TY, g.ny) * rlen * (long long)sizeof(R));
+    // Half records: a row segment of 64 halves is 128 B, so a lane takes one dword, two nodes of
+    // one value: lanes 0..31 value 2v and lanes 32..63 value 2v + 1 (the two segments are 256 B
+    // apart in the record layout).  nx is even (checked at launch), so a pair never straddles
+    // the periodic wrap or a layout chunk.
+    const int pr_lane = lane & 31, pr_odd = lane >> 5;
+    const uint32_t xpair = L::in_row(wrapm(x0 + 2 * pr_lane, g.nx)) * (uint32_t)sizeof(R);
+    constexpr int kHaloPairs = kRec;  // (value pair, halo row) segments: 7 pairs x 2 rows
+    struct HalfRows {
+        uint32_t own[kRec / 2];
+        uint32_t halo[(kHaloPairs + TY - 1) / TY];
+        R col;
+    };
     // flags: positions tid and tid + Z::T of the (H x W) plane window, in-plane index
     long long fo[2] = {0, 0};
 #pragma unroll
@@ -495,6 +512,43 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
         }
         if (halo) hb = ld_at(reinterpret_cast<const float*>(base), hoff);
     };
+    // Half records: start the loads of plane zp into registers ...
+    auto issue_half = [&](int zp, HalfRows& hr) {
+        const char* base = reinterpret_cast<const char*>(rec + (long long)wrapm(zp, g.nz) * plane);
+        const char* own = base + row_own;
+#pragma unroll
+        for (int v = 0; v < kRec / 2; ++v)
+            hr.own[v] = ld_at(reinterpret_cast<const uint32_t*>(own),
+                              xpair + (uint32_t)((2 * v + pr_odd) * L::W * 2));
+#pragma unroll
+        for (int m = 0; m < (kHaloPairs + TY - 1) / TY; ++m) {
+            const int k = wave + TY * m;  // value pair k % 7, halo row k / 7 (0: y0 - 1)
+            if (k < kHaloPairs)
+                hr.halo[m] = ld_at(reinterpret_cast<const uint32_t*>(
+                                       base + ((k / (kRec / 2)) ? row_hi : row_lo)),
+                                   xpair + (uint32_t)((2 * (k % (kRec / 2)) + pr_odd) * L::W * 2));
+        }
+        if (halo) hr.col = ld_at(reinterpret_cast<const R*>(base), hoff);
+    };
+    // ... and put them into dst as floats, where issue_plane's copies land
+    auto land_half = [&](float* dst, const HalfRows& hr) {
+        auto put2 = [&](float* d, uint32_t w) {
+            d[0] = static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)));
+            d[1] = static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)));
+        };
+#pragma unroll
+        for (int v = 0; v < kRec / 2; ++v)
+            put2(dst + ((2 * v + pr_odd) * Z::H + 1 + wave) * Z::W + 1 + 2 * pr_lane, hr.own[v]);
+#pragma unroll
+        for (int m = 0; m < (kHaloPairs + TY - 1) / TY; ++m) {
+            const int k = wave + TY * m;
+            if (k < kHaloPairs)
+                put2(dst + ((2 * (k % (kRec / 2)) + pr_odd) * Z::H +
+                            ((k / (kRec / 2)) ? Z::H - 1 : 0)) * Z::W + 1 + 2 * pr_lane,
+                     hr.halo[m]);
+        }
+        if (halo) dst[hlds] = static_cast<float>(hr.col);
+    };
     auto load_flags = [&](int zp, uint8_t (&fb)[2]) {
         const uint8_t* fbase = flags + (long long)wrapm(zp, g.nz) * fplane;
 #pragma unroll
@@ -512,9 +566,15 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
         __syncthreads();
     };
     {
-        float hb = 0.0f;
-        issue_plane(z0 - 1, ring0, hb);
-        if (halo) ring0[hlds] = hb;
+        if constexpr (kHalf) {
+            HalfRows hr;
+            issue_half(z0 - 1, hr);
+            land_half(ring0, hr);
+        } else {
+            float hb = 0.0f;
+            issue_plane(z0 - 1, ring0, hb);
+            if (halo) ring0[hlds] = hb;
+        }
         uint8_t fb[2] = {0, 0};
         if constexpr (WALLS) {
             load_flags(z0 - 1, fb);
@@ -591,9 +651,11 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
         SiteRaw<S> site_next{0.0, 0u, PhiT<S>(0)};
         if (own) site_ahead<S, M>(P, carry, phi_field, node(p), site_next);
         float hb = 0.0f;
+        HalfRows hr;
         uint8_t fb[2] = {0, 0};
         if (next) {
-            issue_plane(p + 1, nxt, hb);
+            if constexpr (kHalf) issue_half(p + 1, hr);
+            else issue_plane(p + 1, nxt, hb);
             if constexpr (WALLS) load_flags(p + 2, fb);
         }
         auto from_plane = [&](int i) { return pl + at_of(i); };
@@ -641,7 +703,8 @@ k_pull_record_zm(const float* __restrict__ rec, const uint8_t* __restrict__ flag
             stage(prev, Up{}, from_plane, plus, fluid_src);
         site_fin = site_next;
         if (next) {
-            if (halo) nxt[hlds] = hb;
+            if constexpr (kHalf) land_half(nxt, hr);
+            else if (halo) nxt[hlds] = hb;
             if constexpr (WALLS) store_flags(p + 2, fb);
         }
         publish();
@@ -691,15 +754,15 @@ static dim3 zm_grid(const Geo& g, int zc) {
 // populations, and the next site data.
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) void
-k_finish_record(MomT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
+k_finish_record(RecT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
                 void* __restrict__ carry, const MomT<S>* __restrict__ rhoN,
-                const MomT<S>* __restrict__ mom, Geo g, Phys<M> P) {
-    using R = MomT<S>;
+                const MomT<S>* __restrict__ mom, Geo g, Phys<M> P, uint64_t salt) {
+    using R = RecT<S>;
     int x, y, z;
     long long n;
     const RowPos pos = xcd_row(g);
     const bool valid = node_xyz_at(g, pos, x, y, z, n);
-    const RowOff r = row_offsets_at<R>(g, pos, x < g.nx ? x : 0);
+    const RowOff r = row_offsets_at<MomT<S>>(g, pos, x < g.nx ? x : 0);
     if (!valid) return;
     if (WALLS && flags[n]) return;
     const M drho = static_cast<M>(mom[n]);
@@ -732,8 +795,9 @@ k_finish_record(MomT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
     R* at = rec + ((long long)y + (long long)g.ny * z) * L::row_len(g.nx) + L::in_row(x);
 #pragma unroll
     for (int sl = 0; sl < kRec; ++sl) {
-        if (Q == 9 && (sl == kUz || sl == kFz)) continue;  // no z component in 2D
-        __builtin_nontemporal_store(static_cast<R>(rv[sl]), at + sl * L::W);
+        if (Q == 9 && (sl == kUz || sl == kNz)) continue;  // no z component in 2D
+        // half records round stochastically, like half populations
+        __builtin_nontemporal_store(enc<R, M>(rv[sl], sr_bits(salt, g.N, n, sl)), at + sl * L::W);
     }
     carry_store(P, carry, n, Fn);
 }
@@ -793,14 +857,16 @@ static cge_status split_impl(cge_ctx* c, long long nsteps) {
 
 cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_impl, c, nsteps); }
 
-// The z-marching pass 1 serves D3Q19 with FP32 records (checked where it is launched) when
-// its blocks fit the per-block sink accumulators and a plane of records is addressable with
-// 32-bit offsets.
+// The z-marching pass 1 serves D3Q19 with FP32 or half records (checked where it is
+// launched) when its blocks fit the per-block sink accumulators and a plane of records is
+// addressable with 32-bit offsets; half records also need an even nx (two nodes per lane).
+template <typename R>
 static bool zm_ok(const cge_ctx* c) {
     const dim3 gz = zm_grid(c->g, zm_chunk(c));
     const long long blocks = (long long)gz.x * gz.y * gz.z;
-    const long long plane = (long long)c->g.ny * RecLayout<float>::row_len(c->g.nx) * 4;
-    return blocks <= c->acc_len && plane < (1ll << 31);
+    const long long plane = (long long)c->g.ny * RecLayout<R>::row_len(c->g.nx) * (long long)sizeof(R);
+    return blocks <= c->acc_len && plane < (1ll << 31) &&
+           (!std::is_same<R, _Float16>::value || c->g.nx % 2 == 0);
 }
 
 // One step of the record form: pass 1 from populations (first step of a call) or records,
@@ -812,7 +878,7 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
     const dim3 gr = node_grid(c->g), bl = node_block(c->g);
     MomT<S>* rhoN = static_cast<MomT<S>*>(c->rhoN);
     MomT<S>* mom = static_cast<MomT<S>*>(c->mom);
-    MomT<S>* rec = static_cast<MomT<S>*>(c->rec);
+    RecT<S>* rec = static_cast<RecT<S>*>(c->rec);
     const S* src = static_cast<const S*>(c->pop[c->cur]);
     S* dst = static_cast<S*>(c->pop[1 - c->cur]);
     const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
@@ -824,8 +890,8 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
                            c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
     else {
         bool marched = false;
-        if constexpr (Q == 19 && std::is_same<MomT<S>, float>::value) {
-            if (zm_ok(c)) {
+        if constexpr (Q == 19 && !std::is_same<RecT<S>, double>::value) {
+            if (zm_ok<RecT<S>>(c)) {
                 const int zc = zm_chunk(c);
                 hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS, kZmY>), zm_grid(c->g, zc),
                                    dim3(Zm<kZmY>::X, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
@@ -846,7 +912,7 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
     timing_pass(c, pass1);
     if (!last) {
         hipLaunchKernelGGL((k_finish_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec, c->flags,
-                           c->carry, rhoN, mom, c->g, P);
+                           c->carry, rhoN, mom, c->g, P, salt);
         timing_pass(c, "k_finish_record");
     } else if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
         const dim3 tb(kTileX, kTileY, 1);
@@ -879,8 +945,10 @@ cge_status record_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, record_i
 
 size_t record_bytes(const cge_params* p) {
     const size_t rows = (size_t)p->ny * p->nz;
-    return p->precision == CGE_FP64 ? rows * RecLayout<double>::row_len(p->nx) * sizeof(double)
-                                    : rows * RecLayout<float>::row_len(p->nx) * sizeof(float);
+    if (p->precision == CGE_FP64) return rows * RecLayout<double>::row_len(p->nx) * sizeof(double);
+    if (p->precision == CGE_FP16S)
+        return rows * RecLayout<_Float16>::row_len(p->nx) * sizeof(_Float16);
+    return rows * RecLayout<float>::row_len(p->nx) * sizeof(float);
 }
 
 

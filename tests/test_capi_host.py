@@ -114,10 +114,11 @@ def test_scratch_plan_and_caller_scratch_checks():
             cp = cgevap.make_params(w, prec, kernel)
             sizes[prec, kernel] = L.cge_scratch_bytes(C.byref(cp))
             assert sizes[prec, kernel] >= n * (4 + 8), (prec, kernel)
-    # the record form's 14 values per node (FP32 records, rows of 64 nodes: no padding here)
+    # the record form's 14 values per node (FP32 records, rows of 64 nodes: no padding here;
+    # half records come in chunks of 128 nodes, so each 64-node row is padded to 128)
     assert sizes["fp32s", "auto"] - sizes["fp32s", "split"] == 14 * 4 * n
     assert sizes["fp64", "auto"] - sizes["fp64", "split"] == 14 * 8 * n
-    assert sizes["fp16s", "auto"] == sizes["fp16s", "split"]
+    assert sizes["fp16s", "auto"] - sizes["fp16s", "split"] == 14 * 2 * (8 * 8 * 128)
     assert L.cge_scratch_bytes(C.byref(_params(nx=0))) == 0
     cp = cgevap.make_params(w, "fp32s")
     need = L.cge_scratch_bytes(C.byref(cp))

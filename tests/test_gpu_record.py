@@ -9,12 +9,15 @@ the rounding of the record and of the rebuilt populations:
   * FP32 storage: against the split form within 1e-6 of the population scale (the record's
     FP32 values and the FP32 rebuild of each pulled population, against the split form's
     FP32-stored populations), the same sites and sink total to 1e-9 (1e-7 with the soft
-    site rule, whose logistic weights amplify rounding differences of ||F|| by 1 / kappa).
-Shapes cover the z-marching pull of D3Q19 at FP32 storage (64 x 8 tiles) with ragged tiles,
-chunks of 1, 3, 5 and 32 planes (forced with cge_set_zchunk: on a 256-CU device the automatic
-choice gives these small grids one plane per chunk) with ragged last chunks, one and two
-planes and solid nodes, and the general pull: D2Q9, FP64, the |rho^N| < Gamma and soft site
-rules."""
+    site rule, whose logistic weights amplify rounding differences of ||F|| by 1 / kappa);
+  * FP16 storage: half records with stochastic rounding against the split form's half
+    populations within 5e-3, site-steps and sink totals within 1 %.
+Shapes cover the z-marching pull of D3Q19 at FP32 and FP16 storage (64 x 8 tiles) with
+ragged tiles, chunks of 1, 3, 5 and 32 planes (forced with cge_set_zchunk: on a 256-CU device
+the automatic choice gives these small grids one plane per chunk) with ragged last chunks, one
+and two planes and solid nodes, and the general pull: D2Q9, D3Q19 with an odd nx (the
+half-record z-march takes two nodes per lane and needs an even nx), FP64, the |rho^N| < Gamma
+and soft site rules."""
 import numpy as np
 import pytest
 
@@ -77,6 +80,7 @@ SPLIT_CASES = {
     "walls": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
     "walls_hemisphere": ("hemisphere3d", (40, 20, 70), dict(radius=8.0, phi=1e-3)),
     # general pull
+    "d3q19_odd_nx": ("sphere3d", (12, 10, 33), dict(radius=3.5, phi=1e-3)),
     "d2q9": ("drop2d", (1, 40, 52), dict(radius=11.0, phi=1e-3)),
     "soft": ("adjoint2d", (1, 48, 70), dict(radius=14.0, phi=1e-3, site_rule="soft",
                                             gamma=0.305, kappa=0.01)),
@@ -91,7 +95,7 @@ ZCHUNKS = {"zm_ragged": (0, 3, 32), "zm_aligned": (0, 3, 32), "walls": (0, 3, 32
 SPLIT_PARAMS = [(name, zc) for name in SPLIT_CASES for zc in ZCHUNKS.get(name, (0,))]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s", "fp16s"])
 @pytest.mark.parametrize("name,zc", SPLIT_PARAMS)
 def test_record_call_equals_split_steps(name, zc, precision):
     wl, shape, over = SPLIT_CASES[name]
@@ -106,12 +110,20 @@ def test_record_call_equals_split_steps(name, zc, precision):
         b.step(n)
         e = e_pop(a.populations().cpu().numpy(), b.populations().cpu().numpy(), Q, rho_in,
                   w["solid"])
-        tol = 1e-13 if precision == "fp64" else 1e-6
+        tol = {"fp64": 1e-13, "fp32s": 1e-6, "fp16s": 5e-3}[precision]
         assert e < tol, (n, e)
     oa, ob = a.observables(), b.observables()
     assert oa["step"] == ob["step"] == 13
     soft = w["params"]["site_rule"] == "soft"
-    if precision == "fp64":
+    if precision == "fp16s":
+        # half records and half populations round differently (stochastically, with other
+        # random bits), so a site decision near the threshold may differ: the sink totals
+        # agree to the share of one site-step
+        _flush(f"  e_pop {e:.2e}, site-steps {oa['site_steps']} / {ob['site_steps']}")
+        assert abs(oa["site_steps"] - ob["site_steps"]) <= 0.01 * ob["site_steps"] + 2
+        assert abs(oa["sink_total"] - ob["sink_total"]) <= (
+            0.01 * abs(ob["sink_total"]) + 2.0 * w["params"]["phi"] / w["params"]["sbar"])
+    elif precision == "fp64":
         if soft:  # the carried ||F||, rounded in a different order
             assert float((a.carry - b.carry).abs().max()) < 1e-12
         else:
@@ -131,16 +143,12 @@ def test_record_call_equals_split_steps(name, zc, precision):
 def test_automatic_choice_of_the_step_form():
     from paper_2412_14859_amd import cgevap
     w = case("sphere3d", (8, 8, 64), radius=3.0, phi=1e-3)
-    for precision, want in (("fp64", "k_pull_record"), ("fp32s", "k_pull_record"),
-                            ("fp16s", "k_finish")):
+    for precision in ("fp64", "fp32s", "fp16s"):  # D3Q19 at unit tau: the record form
         s = gpu_for(w, precision)
-        assert s.kernel_name() == want, precision
+        assert s.kernel_name() == "k_pull_record", precision
         s.close()
-    with pytest.raises(cgevap.CgeError) as e:  # FP32 records would not be FP16 storage
-        gpu_for(w, "fp16s", kernel="record")
-    assert e.value.status == cgevap.EUNSUPPORTED
     w9 = case("drop2d", (1, 40, 52), radius=11.0, phi=1e-3)
-    for precision in ("fp64", "fp32s"):  # D2Q9: the split step
+    for precision in ("fp64", "fp32s", "fp16s"):  # D2Q9: the split step
         s = gpu_for(w9, precision)
         assert s.kernel_name() == "k_finish", precision
         s.close()
@@ -152,16 +160,19 @@ def test_automatic_choice_of_the_step_form():
         gpu_for(w2, "fp32s", kernel="record")
 
 
-def test_z_marching_pull_against_the_oracle_fp32():
-    """The benchmark's kernel pair (the z-marching pull, FP32 records) against the FP64
-    oracle directly, in calls of several steps: with soft sites no site decision can flip
+@pytest.mark.parametrize("precision,tol", [("fp32s", 1e-5), ("fp16s", 5e-3)])
+def test_z_marching_pull_against_the_oracle(precision, tol):
+    """The benchmark's kernel pair (the z-marching pull, FP32 or half records) against the
+    FP64 oracle directly, in calls of several steps: with soft sites no site decision can flip
     between precisions, so FP32 storage stays within the 1e-5 bar without imposing the
-    oracle's masks.  The shape spans ragged tiles in x and y and several planes."""
+    oracle's masks, and half storage within 5e-3 (a few half-precision units of the largest
+    scaled population, as the split step's half populations).  The shape spans ragged tiles in
+    x and y and several planes."""
     w = case("sphere3d", (14, 16, 70), radius=5.0, phi=1e-3, site_rule="soft", kappa=0.01)
     Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
-    _flush("[record fp32s vs oracle] d3q19 soft 14x16x70")
+    _flush(f"[record {precision} vs oracle] d3q19 soft 14x16x70")
     ora = oracle_for(w)
-    sim = gpu_for(w, "fp32s", kernel="record")
+    sim = gpu_for(w, precision, kernel="record")
     sim.set_zchunk(5)  # 14 planes: chunks of 5, 5 and 4
     worst = 0.0
     for _ in range(3):
@@ -169,8 +180,8 @@ def test_z_marching_pull_against_the_oracle_fp32():
         ora.step(5)
         e = e_pop(sim.populations().cpu().numpy(), ora.populations(), Q, rho_in)
         worst = max(worst, e)
-        assert e < 1e-5, e
+        assert e < tol, e
     _flush(f"  worst e_pop {worst:.3e}")
     og, oo = sim.observables(), ora.observables()
-    assert abs(og["sink_total"] - oo["sink_total"]) <= 1e-5 * abs(oo["sink_total"])
+    assert abs(og["sink_total"] - oo["sink_total"]) <= tol * abs(oo["sink_total"])
     sim.close()
