@@ -49,10 +49,10 @@ constexpr int kFTX = 64;  // tile width in x: one wavefront per row
 // Tile rows per workgroup.  At general relaxation times a thread holds one pulled node's
 // moments and the 38 loads of a pull in flight, and the FP64 collision: 167 registers at FP32
 // storage with plane walls, three waves per SIMD (three workgroups per CU by their LDS).  The
-// 384 x 384 x 192 sessile drop runs in 2.52 ms per step.  Eight rows ran slower (fewer
-// workgroups per CU, which then wait on each other's barriers), and so did issuing a plane's
-// own pull one plane ahead of the previous plane's collision (2.77 ms: the loads held across
-// the collision take two waves per SIMD).
+// 384 x 384 x 192 sessile drop runs in 2.52 ms per step.  Six rows, whose halo ring adds
+// 38 % instead of 55 % to the pulls, ran in 3.10 ms (two workgroups per CU by their LDS) and
+// eight rows slower still; issuing a plane's own pull one plane ahead of the previous plane's
+// collision ran in 2.77 ms (the loads held across the collision take two waves per SIMD).
 constexpr int kFTY = 4;
 
 // Kinds of the z-planes under plane walls.
