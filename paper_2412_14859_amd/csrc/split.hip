@@ -327,7 +327,7 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const RecT<S>* __restrict
     }
 }
 
-// Pass 1 from records for D3Q19 with FP32 records: a block takes a 64 x TY tile of nodes
+// Pass 1 from records for D3Q19 (FP64, FP32 or half records): a block takes a 64 x TY tile of nodes
 // through zc consecutive planes (zm_chunk).  One plane of records (the tile and one node
 // around it) is staged in LDS at a time, in two buffers: while plane p is read, plane p + 1
 // is copied into the other buffer, one barrier per plane.  Each thread keeps the partial
@@ -339,16 +339,18 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const RecT<S>* __restrict
 // ring of four beside the records, and a direction whose source is solid takes the node's
 // own record (halfway bounce-back) while the node's own plane is staged.  Staging one plane
 // instead of three lets taller tiles fit (fewer halo rows per node) with more waves per CU.
-template <int TY>
+// Staged values are E: FP64 for FP64 records (two buffers then take 148 KB, one block per
+// CU), FP32 otherwise (half records are widened as they land).
+template <int TY, typename E = float>
 struct Zm {
     static constexpr int X = 64, W = X + 2, H = TY + 2;
     static constexpr int T = X * TY;                // threads
-    static constexpr int P = kRec * H * W;          // staged floats per buffer
+    static constexpr int P = kRec * H * W;          // staged values (type E) per buffer
     static constexpr int HaloSeg = 2 * kRec;        // 64-node segments of the two halo rows
     static constexpr int F = H * W;                 // staged flags per plane
     // blocks per CU as the LDS allows (two buffers of records, four of flags, the block
     // reduction)
-    static constexpr int LdsBytes = 2 * P * 4 + 4 * F + 256;
+    static constexpr int LdsBytes = 2 * P * (int)sizeof(E) + 4 * F + 256;
     static constexpr int PerCU = (160 * 1024) / LdsBytes < 2048 / T ? (160 * 1024) / LdsBytes
                                                                      : 2048 / T;
     static constexpr int Waves = PerCU * TY / 4;    // waves per SIMD
@@ -388,19 +390,19 @@ __device__ __forceinline__ M site_sink_ahead(const Phys<M>& P, const SiteRaw<S>&
     return w * (phi * P.inv_sbar);
 }
 
-// Partial moments of one node: delta rho, the colour sum and j in FP32, and the pulled rho^N
-// per weight class (ref_part) in the arithmetic type.  The FP32 sums take 5 to 9 FP32
-// rebuilds of FP32 record values and are stored as FP32 moments straight after, so they
-// add a few units in the last place before that rounding; the class sums of rho^N, which
-// ref_part weights by t_ref,k, stay in M, where FP32 rounding would repeat at every node and
-// step.
-template <typename M>
+// Partial moments of one node: delta rho, the colour sum and j in the rebuild's type E, and
+// the pulled rho^N per weight class (ref_part) in the arithmetic type.  With FP32 E the sums
+// take 5 to 9 FP32 rebuilds of FP32 record values and are stored as FP32 moments straight
+// after, so they add a few units in the last place before that rounding; the class sums of
+// rho^N, which ref_part weights by t_ref,k, stay in M, where FP32 rounding would repeat at
+// every node and step.
+template <typename M, typename E>
 struct PullSums {
-    float drho, dsum, j[3];
+    E drho, dsum, j[3];
     M rn[3];
     __device__ __forceinline__ void clear() {
-        drho = dsum = 0.0f;
-        j[0] = j[1] = j[2] = 0.0f;
+        drho = dsum = E(0);
+        j[0] = j[1] = j[2] = E(0);
         rn[0] = rn[1] = rn[2] = M(0);
     }
 };
@@ -416,21 +418,26 @@ constexpr CzList cz_list(int cz) {
     return l;
 }
 
+template <typename S, int TY>
+using ZmOf = Zm<TY, RecE<RecT<S>>>;
+
 template <typename S, typename M, bool WALLS, int TY>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(Zm<TY>::Waves, Zm<TY>::Waves))) void
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(ZmOf<S, TY>::Waves, ZmOf<S, TY>::Waves))) void
 k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
                  const void* __restrict__ carry, const void* __restrict__ phi_field,
-                 float* __restrict__ rhoN, float* __restrict__ mom, double* __restrict__ acc_sink,
-                 long long* __restrict__ acc_sites, Geo g, Phys<M> P, int zc) {
+                 MomT<S>* __restrict__ rhoN, MomT<S>* __restrict__ mom,
+                 double* __restrict__ acc_sink, long long* __restrict__ acc_sites, Geo g,
+                 Phys<M> P, int zc) {
     constexpr int Q = 19;
-    using R = RecT<S>;  // float, or half (then staged through registers, below)
+    using R = RecT<S>;  // double, float, or half (then staged through registers, below)
+    using E = RecE<R>;  // the staged values and the rebuild: double, or float
     constexpr bool kHalf = std::is_same<R, _Float16>::value;
     using L = RecLayout<R>;
-    using Z = Zm<TY>;
+    using Z = ZmOf<S, TY>;
     // the two record buffers (plane p in ring0 when p - z0 is odd) and the flags of plane p
     // in slot p & 3 of fring
-    __shared__ float ring0[Z::P];
-    __shared__ float ring1[Z::P];
+    __shared__ E ring0[Z::P];
+    __shared__ E ring1[Z::P];
     __shared__ uint8_t fring[WALLS ? 4 * Z::F : 1];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + Z::X * ty;
     // tiles in XCD-contiguous order: XCD k (blocks are dealt round-robin by id) takes a run of
@@ -456,6 +463,15 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
     // tid < 2 kRec H load the two halo columns x0 - 1 and x0 + 64 through a register.
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const uint32_t xin = L::in_row(wrapm(x0 + lane, g.nx)) * (uint32_t)sizeof(R);
+    // FP64 records: a 64-value row is two 256 B copies; in copy c lane l moves dword l & 1 of
+    // the value of node x0 + 32 c + l / 2
+    constexpr int kCopies = (int)sizeof(E) / 4 > 1 && !kHalf ? 2 : 1;
+    uint32_t xcp[kCopies];
+#pragma unroll
+    for (int c = 0; c < kCopies; ++c)
+        xcp[c] = kCopies == 1 ? xin
+                              : L::in_row(wrapm(x0 + 32 * c + (lane >> 1), g.nx)) *
+                                        (uint32_t)sizeof(R) + (uint32_t)(lane & 1) * 4u;
     const int hseg = tid >> 1, hside = tid & 1;
     const bool halo = tid < 2 * kRec * Z::H;
     const uint32_t hoff =
@@ -492,25 +508,31 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
     }
     __syncthreads();
     const long long fplane = (long long)g.nx * g.ny;
-    // start the copy of plane zp into dst; its halo columns come back in hb
-    auto issue_plane = [&](int zp, float* dst, float& hb) {
+    // start the copy of plane zp into dst; its halo columns come back in hb (a value's
+    // 256 B layout chunk holds 256 / sizeof(R) nodes, so values are 256 B apart)
+    auto issue_plane = [&](int zp, E* dst, E& hb) {
         const char* base = reinterpret_cast<const char*>(rec + (long long)wrapm(zp, g.nz) * plane);
         const char* own = base + row_own;
 #pragma unroll
         for (int sl = 0; sl < kRec; ++sl)
-            __builtin_amdgcn_global_load_lds(own + xin + sl * L::W * 4,
-                                             dst + (sl * Z::H + 1 + wave) * Z::W + 1, 4, 0, 0);
+#pragma unroll
+            for (int c = 0; c < kCopies; ++c)
+                __builtin_amdgcn_global_load_lds(own + xcp[c] + sl * 256,
+                                                 dst + (sl * Z::H + 1 + wave) * Z::W + 1 + 32 * c,
+                                                 4, 0, 0);
 #pragma unroll
         for (int m = 0; m < (Z::HaloSeg + TY - 1) / TY; ++m) {
             const int k = wave + TY * m;  // halo row segment: value k % kRec, row 0 or H - 1
             if (k < Z::HaloSeg) {
                 const int sl = k % kRec, hi = k / kRec;
-                __builtin_amdgcn_global_load_lds(
-                    base + (hi ? row_hi : row_lo) + sl * L::W * 4 + xin,
-                    dst + (sl * Z::H + (hi ? Z::H - 1 : 0)) * Z::W + 1, 4, 0, 0);
+#pragma unroll
+                for (int c = 0; c < kCopies; ++c)
+                    __builtin_amdgcn_global_load_lds(
+                        base + (hi ? row_hi : row_lo) + sl * 256 + xcp[c],
+                        dst + (sl * Z::H + (hi ? Z::H - 1 : 0)) * Z::W + 1 + 32 * c, 4, 0, 0);
             }
         }
-        if (halo) hb = ld_at(reinterpret_cast<const float*>(base), hoff);
+        if (halo) hb = ld_at(reinterpret_cast<const E*>(base), hoff);
     };
     // Half records: start the loads of plane zp into registers ...
     auto issue_half = [&](int zp, HalfRows& hr) {
@@ -531,8 +553,8 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
         if (halo) hr.col = ld_at(reinterpret_cast<const R*>(base), hoff);
     };
     // ... and put them into dst as floats, where issue_plane's copies land
-    auto land_half = [&](float* dst, const HalfRows& hr) {
-        auto put2 = [&](float* d, uint32_t w) {
+    auto land_half = [&](E* dst, const HalfRows& hr) {
+        auto put2 = [&](E* d, uint32_t w) {
             d[0] = static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)(w & 0xFFFFu)));
             d[1] = static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)));
         };
@@ -547,7 +569,7 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
                             ((k / (kRec / 2)) ? Z::H - 1 : 0)) * Z::W + 1 + 2 * pr_lane,
                      hr.halo[m]);
         }
-        if (halo) dst[hlds] = static_cast<float>(hr.col);
+        if (halo) dst[hlds] = static_cast<E>(hr.col);
     };
     auto load_flags = [&](int zp, uint8_t (&fb)[2]) {
         const uint8_t* fbase = flags + (long long)wrapm(zp, g.nz) * fplane;
@@ -571,7 +593,7 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
             issue_half(z0 - 1, hr);
             land_half(ring0, hr);
         } else {
-            float hb = 0.0f;
+            E hb = E(0);
             issue_plane(z0 - 1, ring0, hb);
             if (halo) ring0[hlds] = hb;
         }
@@ -592,15 +614,15 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
     // The record values direction i reads from its source (dir_slots); without walls they are
     // fetched one direction ahead of their use, so the LDS latency of one direction overlaps
     // the arithmetic of the previous one.
-    auto fetch = [&](int i, const float* src, float (&r)[kRec]) {
+    auto fetch = [&](int i, const E* src, E (&r)[kRec]) {
 #pragma unroll
         for (int sl = 0; sl < kRec; ++sl)
             if ((dir_slots<Q>(i) >> sl) & 1u) r[sl] = src[sl * Z::H * Z::W];
     };
     // direction i of a node from fetched record values (sgn -1: the node's own, bounce-back)
-    auto accum = [&](PullSums<M>& s, int i, const float (&r)[kRec], float sgn) {
-        float ar, dr, rr;
-        record_dir<Q, float>(i, sgn, [&](int sl) { return r[sl]; }, ar, dr, rr);
+    auto accum = [&](PullSums<M, E>& s, int i, const E (&r)[kRec], E sgn) {
+        E ar, dr, rr;
+        record_dir<Q, E>(i, sgn, [&](int sl) { return r[sl]; }, ar, dr, rr);
         s.drho += ar;
         s.dsum += dr;
         s.rn[norm2<Q>(i)] += static_cast<M>(rr);
@@ -614,9 +636,9 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
     };
     // The directions with c_z = CZ (the tag's value) into s: direction i from the record at
     // src_of(i) with sign sgn_of(i), skipped where take(i) is false.
-    auto stage = [&](PullSums<M>& s, auto cz_tag, auto src_of, auto sgn_of, auto take) {
+    auto stage = [&](PullSums<M, E>& s, auto cz_tag, auto src_of, auto sgn_of, auto take) {
         constexpr CzList D = cz_list(decltype(cz_tag)::value);
-        float r0[kRec], r1[kRec];
+        E r0[kRec], r1[kRec];
         if constexpr (WALLS) {  // no look-ahead: the flag ring leaves too few registers
 #pragma unroll
             for (int k = 0; k < D.n; ++k) {
@@ -638,19 +660,19 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
     using Level = std::integral_constant<int, 0>;
     using Up = std::integral_constant<int, 1>;
     auto at_of = [&](int i) { return (ty + 1 - Lat<Q>::cy[i]) * Z::W + (tx + 1 - Lat<Q>::cx[i]); };
-    PullSums<M> sa, sb;
+    PullSums<M, E> sa, sb;
     sa.clear();
     sb.clear();
     SiteRaw<S> site_fin{0.0, 0u, PhiT<S>(0)};
     double v[2] = {0.0, 0.0};
     // One plane: pl holds plane p, the copy of plane p + 1 goes to nxt; prev holds the partial
     // moments of node p - 1 and cur those of node p, and prev takes node p + 1's afterwards.
-    auto march = [&](int p, const float* pl, float* nxt, PullSums<M>& prev, PullSums<M>& cur) {
+    auto march = [&](int p, const E* pl, E* nxt, PullSums<M, E>& prev, PullSums<M, E>& cur) {
         const bool next = p < z1;
         const bool own = valid && p >= z0 && p < z1 && !solid(p, cen);
         SiteRaw<S> site_next{0.0, 0u, PhiT<S>(0)};
         if (own) site_ahead<S, M>(P, carry, phi_field, node(p), site_next);
-        float hb = 0.0f;
+        E hb = E(0);
         HalfRows hr;
         uint8_t fb[2] = {0, 0};
         if (next) {
@@ -659,7 +681,7 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
             if constexpr (WALLS) load_flags(p + 2, fb);
         }
         auto from_plane = [&](int i) { return pl + at_of(i); };
-        auto plus = [&](int i) { return 1.0f; };
+        auto plus = [&](int i) { return E(1); };
         auto fluid_src = [&](int i) { return !solid(p, at_of(i)); };
         // node p - 1: the directions with c_z = -1, then the node is complete
         if (p - 1 >= z0 && valid && !solid(p - 1, cen)) {
@@ -671,11 +693,11 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
             const long long n = node(p - 1);
             v[0] += static_cast<double>(s);
             v[1] += is_site(wgt) ? 1.0 : 0.0;
-            rhoN[n] = static_cast<float>((dsum - M(2) * s) / rho);
-            mom[n] = static_cast<float>(prev.drho);
-            mom[g.N + n] = static_cast<float>(prev.j[0]);
-            mom[2 * g.N + n] = static_cast<float>(prev.j[1]);
-            mom[3 * g.N + n] = static_cast<float>(prev.j[2]);
+            rhoN[n] = static_cast<MomT<S>>((dsum - M(2) * s) / rho);
+            mom[n] = static_cast<MomT<S>>(prev.drho);
+            mom[g.N + n] = static_cast<MomT<S>>(prev.j[0]);
+            mom[2 * g.N + n] = static_cast<MomT<S>>(prev.j[1]);
+            mom[3 * g.N + n] = static_cast<MomT<S>>(prev.j[2]);
         }
         // node p: the directions with c_z = 0 (from the node's own record where the source is
         // solid), then those with c_z = +-1 whose source is solid
@@ -683,16 +705,16 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
             auto own_or_src = [&](int i) {
                 return (i != 0 && solid(p, at_of(i))) ? pl + cen : pl + at_of(i);
             };
-            auto own_sgn = [&](int i) { return (i != 0 && solid(p, at_of(i))) ? -1.0f : 1.0f; };
+            auto own_sgn = [&](int i) { return (i != 0 && solid(p, at_of(i))) ? E(-1) : E(1); };
             auto all = [&](int i) { return true; };
             stage(cur, Level{}, own_or_src, own_sgn, all);
             if constexpr (WALLS) {
-                float r[kRec];
+                E r[kRec];
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
                     if (Lat<Q>::cz[i] == 0 || !solid(p - Lat<Q>::cz[i], at_of(i))) continue;
                     fetch(i, pl + cen, r);
-                    accum(cur, i, r, -1.0f);
+                    accum(cur, i, r, E(-1));
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -725,8 +747,9 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
 // Planes per z-chunk.  A chunk's blocks stage zc + 2 planes, and blocks run in rounds of
 // Zm::PerCU per CU, so the pass takes about rounds x (planes per chunk + 2) plane-times; the
 // chunk count that minimises this is taken.
+template <typename E>
 static int zm_chunk(const cge_ctx* c) {
-    using Z = Zm<kZmY>;
+    using Z = Zm<kZmY, E>;
     const Geo& g = c->g;
     if (c->zchunk > 0) return c->zchunk < g.nz ? c->zchunk : g.nz;
     const long long tiles = (long long)((g.nx + Z::X - 1) / Z::X) * ((g.ny + kZmY - 1) / kZmY);
@@ -857,12 +880,12 @@ static cge_status split_impl(cge_ctx* c, long long nsteps) {
 
 cge_status split_steps(cge_ctx* c, long long nsteps) { CGE_DISPATCH(c, split_impl, c, nsteps); }
 
-// The z-marching pass 1 serves D3Q19 with FP32 or half records (checked where it is
-// launched) when its blocks fit the per-block sink accumulators and a plane of records is
-// addressable with 32-bit offsets; half records also need an even nx (two nodes per lane).
+// The z-marching pass 1 serves D3Q19 (checked where it is launched) when its blocks fit the
+// per-block sink accumulators and a plane of records is addressable with 32-bit offsets; half
+// records also need an even nx (two nodes per lane).
 template <typename R>
 static bool zm_ok(const cge_ctx* c) {
-    const dim3 gz = zm_grid(c->g, zm_chunk(c));
+    const dim3 gz = zm_grid(c->g, zm_chunk<RecE<R>>(c));
     const long long blocks = (long long)gz.x * gz.y * gz.z;
     const long long plane = (long long)c->g.ny * RecLayout<R>::row_len(c->g.nx) * (long long)sizeof(R);
     return blocks <= c->acc_len && plane < (1ll << 31) &&
@@ -890,9 +913,9 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
                            c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
     else {
         bool marched = false;
-        if constexpr (Q == 19 && !std::is_same<RecT<S>, double>::value) {
+        if constexpr (Q == 19) {
             if (zm_ok<RecT<S>>(c)) {
-                const int zc = zm_chunk(c);
+                const int zc = zm_chunk<RecE<RecT<S>>>(c);
                 hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS, kZmY>), zm_grid(c->g, zc),
                                    dim3(Zm<kZmY>::X, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
                                    c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P,

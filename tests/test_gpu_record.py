@@ -12,12 +12,12 @@ the rounding of the record and of the rebuilt populations:
     site rule, whose logistic weights amplify rounding differences of ||F|| by 1 / kappa);
   * FP16 storage: half records with stochastic rounding against the split form's half
     populations within 5e-3, site-steps and sink totals within 1 %.
-Shapes cover the z-marching pull of D3Q19 at FP32 and FP16 storage (64 x 8 tiles) with
+Shapes cover the z-marching pull of D3Q19 at every storage precision (64 x 8 tiles) with
 ragged tiles, chunks of 1, 3, 5 and 32 planes (forced with cge_set_zchunk: on a 256-CU device
 the automatic choice gives these small grids one plane per chunk) with ragged last chunks, one
-and two planes and solid nodes, and the general pull: D2Q9, D3Q19 with an odd nx (the
-half-record z-march takes two nodes per lane and needs an even nx), FP64, the |rho^N| < Gamma
-and soft site rules."""
+and two planes and solid nodes, and the general pull: D2Q9, D3Q19 with an odd nx at FP16
+storage (the half-record z-march takes two nodes per lane and needs an even nx), the
+|rho^N| < Gamma and soft site rules."""
 import numpy as np
 import pytest
 
@@ -75,7 +75,7 @@ SPLIT_CASES = {
     "zm_aligned": ("sphere3d", (33, 8, 64), dict(radius=3.5, phi=1e-3)),
     "zm_one_plane": ("sphere3d", (1, 24, 64), dict(radius=6.0, phi=1e-3)),
     "zm_two_planes": ("sphere3d", (2, 20, 66), dict(radius=6.0, phi=1e-3)),
-    # with solid nodes (the z-marching pull at FP32 storage, the general one in FP64): the
+    # with solid nodes (the z-marching pull with walls at every storage precision): the
     # cavity ring, and a hemisphere on a wall with a flux field, ragged in x and z
     "walls": ("cap3d", (24, 32, 70), dict(radius=9.0, phi=1e-3)),
     "walls_hemisphere": ("hemisphere3d", (40, 20, 70), dict(radius=8.0, phi=1e-3)),
@@ -160,14 +160,14 @@ def test_automatic_choice_of_the_step_form():
         gpu_for(w2, "fp32s", kernel="record")
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32s", 1e-5), ("fp16s", 5e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32s", 1e-5), ("fp16s", 5e-3)])
 def test_z_marching_pull_against_the_oracle(precision, tol):
-    """The benchmark's kernel pair (the z-marching pull, FP32 or half records) against the
-    FP64 oracle directly, in calls of several steps: with soft sites no site decision can flip
-    between precisions, so FP32 storage stays within the 1e-5 bar without imposing the
-    oracle's masks, and half storage within 5e-3 (a few half-precision units of the largest
-    scaled population, as the split step's half populations).  The shape spans ragged tiles in
-    x and y and several planes."""
+    """The benchmark's kernel pair (the z-marching pull, FP64, FP32 or half records) against
+    the FP64 oracle directly, in calls of several steps: FP64 within the 1e-12 parity bar; with
+    soft sites no site decision can flip between precisions, so FP32 storage stays within the
+    1e-5 bar without imposing the oracle's masks, and half storage within 5e-3 (a few
+    half-precision units of the largest scaled population, as the split step's half
+    populations).  The shape spans ragged tiles in x and y and several planes."""
     w = case("sphere3d", (14, 16, 70), radius=5.0, phi=1e-3, site_rule="soft", kappa=0.01)
     Q, rho_in = w["params"]["Q"], w["params"]["rho_in"]
     _flush(f"[record {precision} vs oracle] d3q19 soft 14x16x70")
