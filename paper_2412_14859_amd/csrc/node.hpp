@@ -508,19 +508,20 @@ __device__ __forceinline__ void record_dir(int i, E sgn, Load&& L, E& a, E& dp, 
         dp = rn * a;
         return;
     }
+    // c.u and n.c from the non-zero components of c_i only (a sum started at zero costs an
+    // add per direction: 0 + x is not x for x = -0)
     E cu = E(0), nc = E(0);
-    if (Lat<Q>::cx[i]) {
-        cu += E(Lat<Q>::cx[i]) * L(kUx);
-        nc += E(Lat<Q>::cx[i]) * L(kNx);
-    }
-    if (Lat<Q>::cy[i]) {
-        cu += E(Lat<Q>::cy[i]) * L(kUy);
-        nc += E(Lat<Q>::cy[i]) * L(kNy);
-    }
-    if (Lat<Q>::cz[i]) {
-        cu += E(Lat<Q>::cz[i]) * L(kUz);
-        nc += E(Lat<Q>::cz[i]) * L(kNz);
-    }
+    bool any = false;
+    auto term = [&](int c, int su, int sn) {
+        if (c == 0) return;
+        const E tu = c > 0 ? L(su) : -L(su), tn = c > 0 ? L(sn) : -L(sn);
+        cu = any ? cu + tu : tu;
+        nc = any ? nc + tn : tn;
+        any = true;
+    };
+    term(Lat<Q>::cx[i], kUx, kNx);
+    term(Lat<Q>::cy[i], kUy, kNy);
+    term(Lat<Q>::cz[i], kUz, kNz);
     cu *= sgn;
     nc *= sgn;
     constexpr double h = weight<Q>(Q == 9 ? 5 : 7) / weight<Q>(1);  // W_2 / W_1

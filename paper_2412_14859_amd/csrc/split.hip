@@ -18,6 +18,21 @@
 
 namespace cge {
 
+// The moment record of node n between the two passes: rho^N and (delta rho, j), stored at
+// the record's precision T.  The stores are non-temporal: the next pass reads them after the
+// rest of this pass's traffic, and allocated normally in L2 they only displace the data
+// this pass re-reads (measured: the FP32 finish from records 0.304 -> 0.285 ms at 256^3).
+template <typename T, typename V, typename W>
+__device__ __forceinline__ void store_moments(T* __restrict__ rhoN, T* __restrict__ mom,
+                                              long long N, long long n, V rn, W drho,
+                                              const W (&j)[3]) {
+    __builtin_nontemporal_store(static_cast<T>(rn), rhoN + n);
+    __builtin_nontemporal_store(static_cast<T>(drho), mom + n);
+    __builtin_nontemporal_store(static_cast<T>(j[0]), mom + N + n);
+    __builtin_nontemporal_store(static_cast<T>(j[1]), mom + 2 * N + n);
+    __builtin_nontemporal_store(static_cast<T>(j[2]), mom + 3 * N + n);
+}
+
 // Pass 1: pull, sink, moments; FP64 sink bookkeeping per block.
 template <int Q, typename S, typename M, bool WALLS>
 __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
@@ -60,11 +75,7 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
         dsum -= M(2) * s;
         v[0] = static_cast<double>(s);
         v[1] = is_site(wgt) ? 1.0 : 0.0;
-        rhoN[n] = static_cast<MomT<S>>(dsum / rho);
-        mom[n] = static_cast<MomT<S>>(drho);
-        mom[g.N + n] = static_cast<MomT<S>>(j[0]);
-        mom[2 * g.N + n] = static_cast<MomT<S>>(j[1]);
-        mom[3 * g.N + n] = static_cast<MomT<S>>(j[2]);
+        store_moments(rhoN, mom, g.N, n, dsum / rho, drho, j);
     }
     const bool is_max[2] = {false, false};
     double out[2];
@@ -310,11 +321,7 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const RecT<S>* __restrict
         dsum -= M(2) * s;
         v[0] = static_cast<double>(s);
         v[1] = is_site(wgt) ? 1.0 : 0.0;
-        rhoN[n] = static_cast<MomT<S>>(dsum / rho);
-        mom[n] = static_cast<MomT<S>>(drho);
-        mom[g.N + n] = static_cast<MomT<S>>(j[0]);
-        mom[2 * g.N + n] = static_cast<MomT<S>>(j[1]);
-        mom[3 * g.N + n] = static_cast<MomT<S>>(j[2]);
+        store_moments(rhoN, mom, g.N, n, dsum / rho, drho, j);
     }
     const bool is_max[2] = {false, false};
     double out[2];
@@ -693,11 +700,7 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
             const long long n = node(p - 1);
             v[0] += static_cast<double>(s);
             v[1] += is_site(wgt) ? 1.0 : 0.0;
-            rhoN[n] = static_cast<MomT<S>>((dsum - M(2) * s) / rho);
-            mom[n] = static_cast<MomT<S>>(prev.drho);
-            mom[g.N + n] = static_cast<MomT<S>>(prev.j[0]);
-            mom[2 * g.N + n] = static_cast<MomT<S>>(prev.j[1]);
-            mom[3 * g.N + n] = static_cast<MomT<S>>(prev.j[2]);
+            store_moments(rhoN, mom, g.N, n, (dsum - M(2) * s) / rho, prev.drho, prev.j);
         }
         // node p: the directions with c_z = 0 (from the node's own record where the source is
         // solid), then those with c_z = +-1 whose source is solid
