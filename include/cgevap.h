@@ -67,8 +67,11 @@ typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } 
 /* Step implementation.
  *   TWOPASS: any lattice, geometry and relaxation times; writes the post-sink phase field to
  *            library scratch and pulls the populations twice.
- *   FUSED:   single pass, D3Q19 without solid nodes (CGE_EUNSUPPORTED at cge_create for
- *            D2Q9, at cge_bind with flags); recomputes the phase field of each tile's halo.
+ *   FUSED:   single pass, D3Q19, hard site rules, any relaxation times, no solid nodes or
+ *            solid nodes only as whole z-planes with fluid on one side (floors and lids;
+ *            CGE_EUNSUPPORTED at cge_create for D2Q9 or the SOFT rule, at cge_bind for other
+ *            solid nodes); recomputes the phase field of each tile's halo.  Where the 19
+ *            slots of one component exceed 4 GiB (32-bit buffer offsets) TWOPASS runs.
  *   SPLIT:   unit relaxation times (tau[0] == tau[1] == 1, else CGE_EUNSUPPORTED at
  *            cge_create), any lattice and geometry; the first pass writes the post-sink
  *            moments, the second finishes the step from them without re-reading populations.
@@ -293,7 +296,7 @@ cge_status cge_set_height_flux(cge_ctx* ctx, double phi_s, double K, double h_sc
  * adjoint returns CGE_EUNSUPPORTED while outlets are on. */
 cge_status cge_set_outlet(cge_ctx* ctx, int lo, int hi, double rho_out);
 
-/* Launch shape of the z-marching kernels (the record form's pull at FP32 and half records,
+/* Launch shape of the z-marching kernels (the record form's pull for D3Q19 at every precision,
  * the fused step): planes per z-chunk of a block's march.  0 (the default) chooses it from the grid
  * (and, for the record pull, the device's compute-unit count); planes > 0 takes that many
  * (at most nz).  Results do not depend on it beyond the grouping of the FP64 sink partials
