@@ -52,12 +52,18 @@ def kernel_sources(kernel):
 
 
 def sources_sha(kernel):
-    """Hash of a kernel's sources, to tell whether a stored counter summary still applies."""
+    """Hash of a kernel's sources, to tell whether a stored counter summary still applies.
+    Comments and blank lines are left out, so that an edit of the text alone keeps it."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for p in kernel_sources(kernel):
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
