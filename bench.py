@@ -553,18 +553,15 @@ def feature_costs(steps=200, precision="fp32s"):
     return {"workload": f"ms per step, 192^3, {precision}, {steps} steps", "costs": out}
 
 
-def c2_benchmark(steps=20000, phis=(1e-6, 1e-5, 1e-4), every=1000, oracle_steps=200):
+def c2_benchmark(steps=20000, phis=(1e-6, 1e-5, 1e-4), every=1000):
     """D2Q9 1024^2: a flat film at y = 512 between walls at y = 0 and 1023, and an ellipse
     200 x 120, each at phi = 1e-6, 1e-5, 1e-4, 20000 steps, in FP64 and in FP32 storage.  The
     FP32 run is compared with the FP64 run (film height and drop volume, site count); the FP64
-    run is checked against the FP64 oracle over its first 200 steps (all cores).  Both
-    population buffers fit in the 256 MB last-level cache (FP32: 75 MB each, FP64: 151 MB), so
-    the MLUPS are cache-resident, not an HBM roofline."""
-    import numpy as np
+    runs are checked against the FP64 oracle over their first 200 steps by
+    tests/test_gpu_configs.py.  Both population buffers fit in the 256 MB last-level cache
+    (FP32: 75 MB each, FP64: 151 MB), so the MLUPS are cache-resident, not an HBM roofline."""
     import torch
-    from oracle.oracle import Oracle  # the FP64 check of the GPU's FP64 run
     from paper_2412_14859_amd import analytic, cgevap, inputs
-    cores = len(os.sched_getaffinity(0))
     out = []
     for name in ("flat2d", "ellipse2d"):
         for phi in phis:
@@ -574,22 +571,7 @@ def c2_benchmark(steps=20000, phis=(1e-6, 1e-5, 1e-4), every=1000, oracle_steps=
             for prec in ("fp64", "fp32s"):
                 sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], solid=w["solid"],
                                         phi_field=w["phi_field"], precision=prec)
-                if prec == "fp64":
-                    ora = Oracle(p, solid=w["solid"])
-                    ora.set_threads(cores)
-                    ora.init_equilibrium(w["rho_r"], w["rho_b"])
-                    ora.step(oracle_steps)
-                    sim.step(oracle_steps)
-                    f_o = ora.populations()
-                    f_g = sim.populations().cpu().numpy()
-                    fl = w["solid"] == 0 if w["solid"] is not None else None
-                    d = np.abs(f_g - f_o)
-                    e_or = float((d[:, :, fl] if fl is not None else d).max())
-                    same_sites = ora.observables()["site_steps"] == sim.observables()["site_steps"]
-                    del ora, f_o, f_g, d
-                    done = oracle_steps
-                else:
-                    done = 0
+                done = 0
                 hist = []
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -604,15 +586,12 @@ def c2_benchmark(steps=20000, phis=(1e-6, 1e-5, 1e-4), every=1000, oracle_steps=
                     hist.append((done, ob["v_mass"], x, ob["site_steps"]))
                 torch.cuda.synchronize()
                 wall = time.perf_counter() - t0
-                runs[prec] = {"hist": hist, "mlups": round(p["shape"][1] * p["shape"][2]
-                                                            * (steps - (oracle_steps if prec == "fp64" else 0))
-                                                            / wall / 1e6, 1)}
+                runs[prec] = {"hist": hist,
+                              "mlups": round(p["shape"][1] * p["shape"][2] * steps / wall / 1e6, 1)}
                 sim.close()
             h64, h32 = runs["fp64"]["hist"], runs["fp32s"]["hist"]
             v_err = max(abs(a[1] - b[1]) / a[1] for a, b in zip(h64, h32))
             rec = {"case": name, "phi": phi, "steps": steps,
-                   "fp64_vs_oracle_200_steps": {"max_abs_population_diff": e_or,
-                                                "site_steps_equal": bool(same_sites)},
                    "v_mass_fp64_end": h64[-1][1], "v_mass_fp32s_end": h32[-1][1],
                    "volume_lost_fp64": h64[0][1] - h64[-1][1] if h64 else None,
                    "max_rel_volume_diff_fp32s_vs_fp64": v_err,
@@ -630,6 +609,111 @@ def c2_benchmark(steps=20000, phis=(1e-6, 1e-5, 1e-4), every=1000, oracle_steps=
     return {"workload": "D2Q9 1024^2 flat film (walls y=0,1023) and ellipse 200x120, sigma 4.44e-4, "
                         "beta 0.7, Gamma 0.305, Sbar 3, tau 1; FP32 storage against FP64; "
                         "cache-resident", "cases": out}
+
+
+# the oracle's observables on the 64^3 downscale of the 256^3 drop, written by
+# tests/golden/make_c3_downscale.py
+C3_FIXTURE = os.path.join(ROOT, "tests", "golden", "c3_downscale_64cube_oracle.txt")
+
+
+def read_c3_fixture():
+    rows, keys = [], None
+    with open(C3_FIXTURE) as f:
+        for line in f:
+            if line.startswith("# step "):
+                keys = line[2:].split()
+            elif line.strip() and not line.startswith("#"):
+                v = line.split()
+                rows.append({k: (int(x) if k in ("step", "site_steps", "n_sites") else float(x))
+                             for k, x in zip(keys, v)})
+    return rows
+
+
+def c3_benchmark(steps=10000, every=1000):
+    """The D3Q19 256^3 drop (R = 64, phi = 1e-5) over its 10000 steps at FP64, FP32 and FP16
+    storage: drop volume V = M_r / rho_r^in and the equivalent radius (3V / 4 pi)^(1/3) every
+    `every` steps, FP32 and FP16 against FP64, the linear radius law R0 - phi t / rho, and
+    MLUPS.  Then the 64^3 downscale (R = 16, centre half a node off the box centre) at the
+    three precisions against the FP64 oracle's observables stored in tests/golden (every 500
+    steps over 10000 steps)."""
+    import math
+    import torch
+    from paper_2412_14859_amd import cgevap, inputs
+
+    def radius(v):
+        return (3.0 * v / (4.0 * math.pi)) ** (1.0 / 3.0)
+
+    out = {"workload": "D3Q19 256^3 drop R=64, unit density ratio, tau 1, A=5e-4, beta 0.7, "
+                       f"phi 1e-5, Gamma 0.305, {steps} steps; downscale 64^3 R=16 against the "
+                       "FP64 oracle"}
+    w = inputs.workload("sphere3d")
+    p = w["params"]
+    N = 256 ** 3
+    full = {}
+    for prec in ("fp64", "fp32s", "fp16s"):
+        sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], precision=prec)
+        hist = [(0, sim.observables()["v_mass"])]
+        wall = 0.0
+        while hist[-1][0] < steps:
+            k = min(every, steps - hist[-1][0])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(k)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            hist.append((hist[-1][0] + k, sim.observables()["v_mass"]))
+        ob = sim.observables()
+        full[prec] = {"hist": hist, "mlups": round(N * steps / wall / 1e6, 1),
+                      "site_steps": ob["site_steps"], "sink_total": ob["sink_total"],
+                      "kernel": sim.kernel_name()}
+        sim.close()
+        torch.cuda.empty_cache()
+        print(f"c3 256^3 {prec}: {full[prec]['mlups']} MLUPS, V {hist[0][1]:.3f} -> "
+              f"{hist[-1][1]:.3f}", file=sys.stderr, flush=True)
+    h64 = full["fp64"]["hist"]
+    r0 = radius(h64[0][1])
+    phi = p["phi"]
+    res = {}
+    for prec, r in full.items():
+        h = r["hist"]
+        res[prec] = {
+            "kernel": r["kernel"], "mlups": r["mlups"],
+            "volume": [[s, round(v, 4)] for s, v in h],
+            "radius_end": radius(h[-1][1]),
+            "radius_drop": radius(h[0][1]) - radius(h[-1][1]),
+            "site_steps": r["site_steps"], "sink_total": r["sink_total"]}
+        if prec != "fp64":
+            res[prec]["max_rel_volume_diff_vs_fp64"] = max(abs(a[1] - b[1]) / a[1]
+                                                           for a, b in zip(h64, h))
+            res[prec]["max_abs_radius_diff_vs_fp64"] = max(abs(radius(a[1]) - radius(b[1]))
+                                                           for a, b in zip(h64, h))
+            res[prec]["rel_diff_of_volume_lost_vs_fp64"] = (
+                abs((h[0][1] - h[-1][1]) - (h64[0][1] - h64[-1][1])) / (h64[0][1] - h64[-1][1]))
+    res["radius_law"] = {"R0": r0, "law_drop_over_run": phi * steps / p["rho_in"][0],
+                         "fp64_drop_over_run": res["fp64"]["radius_drop"]}
+    out["full_256"] = res
+    # downscale against the oracle
+    rows = read_c3_fixture()
+    every_f = rows[1]["step"] - rows[0]["step"]
+    w4 = inputs.workload("sphere3d", shape=(64, 64, 64), radius=16.0, offset=(0.5, 0.5, 0.5))
+    small = {}
+    for prec in ("fp64", "fp32s", "fp16s"):
+        sim = cgevap.Simulation(w4["params"], w4["rho_r"], w4["rho_b"], precision=prec)
+        worst = 0.0
+        for r in rows:
+            if r["step"]:
+                sim.step(every_f)
+            ob = sim.observables()
+            worst = max(worst, abs(ob["v_mass"] - r["v_mass"]) / r["v_mass"])
+        ob = sim.observables()
+        small[prec] = {"max_rel_volume_error_vs_oracle": worst,
+                       "radius_error_end_vs_oracle": radius(ob["v_mass"]) - radius(rows[-1]["v_mass"]),
+                       "site_steps": ob["site_steps"], "site_steps_oracle": rows[-1]["site_steps"],
+                       "sink_total_rel_vs_oracle": (ob["sink_total"] - rows[-1]["sink_total"])
+                                                   / rows[-1]["sink_total"]}
+        sim.close()
+    out["downscale_64_vs_oracle"] = small
+    return out
 
 
 def c4_benchmark(steps=20000, every=2000, precision="fp32s"):
@@ -814,6 +898,10 @@ def main():
     ap.add_argument("--c2", action="store_true",
                     help="D2Q9 1024^2 film and ellipse over 20000 steps, FP32 storage against "
                          "FP64 (runs instead of the bench line)")
+    ap.add_argument("--c3", action="store_true",
+                    help="D3Q19 256^3 drop over 10000 steps at FP64, FP32 and FP16 storage, "
+                         "and its 64^3 downscale against the oracle's stored observables (runs "
+                         "instead of the bench line)")
     ap.add_argument("--c4", action="store_true",
                     help="D3Q19 384x384x192 sessile drop at density ratio 10 over 20000 steps "
                          "(runs instead of the bench line)")
@@ -833,6 +921,9 @@ def main():
         return
     if args.c2:
         print(json.dumps(c2_benchmark()), flush=True)
+        return
+    if args.c3:
+        print(json.dumps(c3_benchmark()), flush=True)
         return
     if args.c4:
         print(json.dumps(c4_benchmark(steps=args.steps if args.steps != 200 else 20000,

@@ -1,0 +1,85 @@
+"""The long benchmark configurations' FP64 references, pinned to the FP64 oracle:
+  * the D2Q9 1024^2 film and ellipse at phi = 1e-6, 1e-5, 1e-4 (the 20000-step comparison of
+    FP32 with FP64 storage in bench.py --c2 takes the GPU's FP64 run as its reference): the
+    FP64 run against the oracle over its first 200 steps, populations within 1e-12, the
+    same site-steps and the sink total within the rounding of its summation order (1e-10);
+  * the 64^3 downscale of the D3Q19 256^3 drop over 10000 steps (bench.py --c3) against the
+    oracle's observables stored by tests/golden/make_c3_downscale.py every 500 steps: FP64
+    drop volume within 1e-10 with the same site-steps, and the sink total equal to site-steps
+    x phi / Sbar (every term is that with a uniform flux and hard sites) to 1e-12; FP32
+    storage within the 0.1 % volume bar (measured 3.2e-4, growing linearly: the record form's
+    FP32 values shift red mass between the bulks by about 3e-8 of the volume per step); FP16
+    storage within 3e-3 (measured 2.1e-3: above the 0.1 % bar over this run, growing
+    linearly by 2e-7 of the volume per step)."""
+import os
+
+import pytest
+
+from tests.helpers import case, e_pop, gpu_for, oracle_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _flush(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("phi", [1e-6, 1e-5, 1e-4])
+@pytest.mark.parametrize("name", ["flat2d", "ellipse2d"])
+def test_c2_fp64_run_matches_the_oracle_over_200_steps(name, phi):
+    w = case(name, None, phi=phi)
+    _flush(f"[c2 fp64 vs oracle] {name} 1024^2 phi={phi} 200 steps")
+    ora = oracle_for(w)
+    ora.set_threads(min(16, len(os.sched_getaffinity(0))))
+    sim = gpu_for(w, "fp64")
+    for n in (100, 100):
+        sim.step(n)
+        ora.step(n)
+        _flush(f"  {n} steps done")
+    e = e_pop(sim.populations().cpu().numpy(), ora.populations(), 9, w["params"]["rho_in"],
+              w["solid"])
+    og, oo = sim.observables(), ora.observables()
+    _flush(f"  e_pop {e:.3e}, site-steps {og['site_steps']} / {oo['site_steps']}")
+    assert e < 1e-12
+    assert og["site_steps"] == oo["site_steps"]
+    # some 6e5 equal sink terms summed per block on the GPU and in node order by the oracle:
+    # the orders differ by up to n u = 7e-11 of the total (measured 6.5e-12); with a uniform
+    # flux and hard sites every term is phi / Sbar, so the total is site-steps x phi / Sbar
+    assert abs(og["sink_total"] - oo["sink_total"]) <= 1e-10 * abs(oo["sink_total"])
+    exact = og["site_steps"] * w["params"]["phi"] / w["params"]["sbar"]
+    assert abs(og["sink_total"] - exact) <= 1e-12 * exact
+    sim.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32s", 1e-3), ("fp16s", 3e-3)])
+def test_c3_downscale_against_the_oracle_over_10000_steps(precision, tol):
+    import bench
+    rows = bench.read_c3_fixture()
+    assert rows[0]["step"] == 0 and rows[-1]["step"] == 10000
+    every = rows[1]["step"] - rows[0]["step"]
+    w = case("sphere3d", (64, 64, 64), radius=16.0)  # centre half a node off, as stored
+    _flush(f"[c3 downscale {precision} vs oracle record] 64^3 R=16, 10000 steps")
+    sim = gpu_for(w, precision)
+    worst = 0.0
+    for r in rows:
+        if r["step"]:
+            sim.step(every)
+        ob = sim.observables()
+        worst = max(worst, abs(ob["v_mass"] - r["v_mass"]) / r["v_mass"])
+    ob = sim.observables()
+    lost = rows[0]["v_mass"] - rows[-1]["v_mass"]
+    _flush(f"  worst volume rel. error {worst:.3e} (volume lost {lost / rows[0]['v_mass']:.3e}); "
+           f"site-steps {ob['site_steps']} / {rows[-1]['site_steps']}, sink "
+           f"{ob['sink_total']:.10f} / {rows[-1]['sink_total']:.10f}")
+    assert lost > 0
+    assert worst < tol
+    if precision == "fp64":
+        assert ob["site_steps"] == rows[-1]["site_steps"]
+        # uniform flux, hard sites: every sink term is phi / Sbar, and the total is site-steps
+        # x phi / Sbar.  The GPU's per-block partials reach it to rounding; the oracle's sum in
+        # node and step order of 1e8 equal terms drifts by up to n u = 1.1e-8 of it (the stored
+        # value is 1.25e-9 low)
+        exact = ob["site_steps"] * w["params"]["phi"] / w["params"]["sbar"]
+        assert abs(ob["sink_total"] - exact) <= 1e-12 * exact
+        assert abs(rows[-1]["sink_total"] - exact) <= 1.1e-8 * exact
+    sim.close()
