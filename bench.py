@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor peak
 def algorithmic_bytes_per_node(Q, precision, walls=False, phi_field=False):
     """Populations read once and written once (2 components x Q), the site mask byte read
     and written, the flux field read when bound, the solid flag read when walls exist."""
-    elem = {"fp64": 8, "fp32s": 4, "fp16s": 2}[precision]
+    elem = {"fp64": 8, "fp32s": 4, "fp16s": 2, "fp16s64": 2}[precision]
     return 2 * Q * 2 * elem + 2 + (4 if phi_field else 0) + (1 if walls else 0)
 
 
@@ -76,7 +76,7 @@ def pass_bytes_per_node(kernel, Q, precision, walls=False, phi_field=False):
     k_collide) reads those, writes the state and the next site byte (k_collide also reads
     the populations again: its algorithmic bytes are a whole step's).  The phase field and
     the moments are stored like the state (FP64 next to FP64, else FP32)."""
-    elem = {"fp64": 8, "fp32s": 4, "fp16s": 2}[precision]
+    elem = {"fp64": 8, "fp32s": 4, "fp16s": 2, "fp16s64": 2}[precision]
     mom_e = 8 if precision == "fp64" else 4
     pops = 2 * Q * elem
     rec = 14 * elem
@@ -631,9 +631,9 @@ def read_c3_fixture():
 
 def c3_benchmark(steps=10000, every=1000):
     """The D3Q19 256^3 drop (R = 64, phi = 1e-5) over its 10000 steps at FP64, FP32 and FP16
-    storage: drop volume V = M_r / rho_r^in and the equivalent radius (3V / 4 pi)^(1/3) every
-    `every` steps, FP32 and FP16 against FP64, the linear radius law R0 - phi t / rho, and
-    MLUPS.  Then the 64^3 downscale (R = 16, centre half a node off the box centre) at the
+    storage (FP16 with FP32 arithmetic, and with FP64 arithmetic: "fp16s64"): drop volume
+    V = M_r / rho_r^in and the equivalent radius (3V / 4 pi)^(1/3) every `every` steps, each
+    against FP64, the linear radius law R0 - phi t / rho, and MLUPS.  Then the 64^3 downscale (R = 16, centre half a node off the box centre) at the
     three precisions against the FP64 oracle's observables stored in tests/golden (every 500
     steps over 10000 steps)."""
     import math
@@ -650,7 +650,7 @@ def c3_benchmark(steps=10000, every=1000):
     p = w["params"]
     N = 256 ** 3
     full = {}
-    for prec in ("fp64", "fp32s", "fp16s"):
+    for prec in ("fp64", "fp32s", "fp16s", "fp16s64"):
         sim = cgevap.Simulation(p, w["rho_r"], w["rho_b"], precision=prec)
         hist = [(0, sim.observables()["v_mass"])]
         wall = 0.0
@@ -697,7 +697,7 @@ def c3_benchmark(steps=10000, every=1000):
     every_f = rows[1]["step"] - rows[0]["step"]
     w4 = inputs.workload("sphere3d", shape=(64, 64, 64), radius=16.0, offset=(0.5, 0.5, 0.5))
     small = {}
-    for prec in ("fp64", "fp32s", "fp16s"):
+    for prec in ("fp64", "fp32s", "fp16s", "fp16s64"):
         sim = cgevap.Simulation(w4["params"], w4["rho_r"], w4["rho_b"], precision=prec)
         worst = 0.0
         for r in rows:
@@ -875,7 +875,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="fp32s", choices=["fp64", "fp32s", "fp16s"])
+    ap.add_argument("--precision", default="fp32s", choices=["fp64", "fp32s", "fp16s", "fp16s64"])
     ap.add_argument("--kernel", default="auto",
                     choices=["auto", "twopass", "fused", "split", "record"])
     ap.add_argument("--size", type=int, default=256, help="edge of the cubic box")
@@ -953,7 +953,7 @@ def main():
     main_leg = run_leg(w, args.precision, args.steps, args.warmup, args.kernel)
     legs = {}
     if not args.no_legs:
-        for prec in ("fp64", "fp16s"):
+        for prec in ("fp64", "fp16s", "fp16s64"):
             if prec != args.precision:
                 legs[prec] = run_leg(w, prec, args.steps, args.warmup, args.kernel)
         # drop volume after the same steps, against the FP64 run
@@ -983,6 +983,8 @@ def main():
                                 "stochastic rounding",
                ("fp32s", False): "fp32 shifted populations", ("fp64", False): "fp64 populations",
                ("fp16s", False): "fp16 shifted populations, stochastic rounding"}
+    storage[("fp16s64", True)] = storage[("fp16s", True)]
+    storage[("fp16s64", False)] = storage[("fp16s", False)]
     record = main_leg["kernel"] == "k_pull_record"
     arithmetic = {("fp32s", True): "pulled populations rebuilt from the FP32 records in FP32; "
                                    "moment sums, collision, perturbation and recolouring in FP64",
@@ -990,7 +992,10 @@ def main():
                   ("fp16s", True): "FP32 (pulled populations rebuilt from the half records in "
                                    "FP32)",
                   ("fp32s", False): "FP64 on FP32-stored values",
-                  ("fp64", False): "FP64", ("fp16s", False): "FP32 on FP16-stored values"}
+                  ("fp64", False): "FP64", ("fp16s", False): "FP32 on FP16-stored values",
+                  ("fp16s64", True): "pulled populations rebuilt from the half records in FP32; "
+                                     "moment sums, collision, perturbation and recolouring in FP64",
+                  ("fp16s64", False): "FP64 on FP16-stored values"}
     pop_bpn = main_leg["population_equivalent_bytes_per_node"]
     out = {
         "metric": "MLUPS + % HBM roofline, D3Q19 CG+evap FP32 vs FP64; adjoint/forward time",
@@ -1004,7 +1009,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         # the type the dominant kernel stores and rebuilds in (its moment sums are FP64)
-        "dtype": {"fp32s": "f32", "fp64": "f64", "fp16s": "f16"}[args.precision],
+        "dtype": {"fp32s": "f32", "fp64": "f64", "fp16s": "f16", "fp16s64": "f16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"D3Q19 {n}^3 periodic, spherical drop R={64 * n // 256}, "
                                "unit density ratio, tau=1, A=5e-4, beta=0.7, phi=1e-5, "

@@ -14,10 +14,11 @@ LIB_PATH = os.path.join(HERE, "libcgevap.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED, ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 ECHECKPOINT, ESCRATCH = -7, -8
-PRECISIONS = {"fp64": 0, "fp32s": 1, "fp16s": 2}
+# "fp16s64": half storage (CGE_FP16S) with FP64 arithmetic (cge_params.fp16_arith64)
+PRECISIONS = {"fp64": 0, "fp32s": 1, "fp16s": 2, "fp16s64": 2}
 KERNELS = {"auto": 0, "twopass": 1, "fused": 2, "split": 3, "record": 4}
 SITE_RULES = {"grad": 0, "phase": 1, "soft": 2}
-ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2}
+ELEM_BYTES = {"fp64": 8, "fp32s": 4, "fp16s": 2, "fp16s64": 2}
 
 # every symbol the header declares
 EXPORTS = ["cge_create", "cge_scratch_bytes", "cge_create_with_scratch", "cge_population_bytes", "cge_bind", "cge_init_equilibrium",
@@ -37,7 +38,7 @@ class CgeParams(C.Structure):
                 ("sbar", C.c_double), ("gamma", C.c_double), ("kappa", C.c_double),
                 ("site_rule", C.c_int),
                 ("kernel", C.c_int), ("seed", C.c_ulonglong),
-                ("recolor_fade", C.c_double)]
+                ("recolor_fade", C.c_double), ("fp16_arith64", C.c_int)]
 
 
 class CgeObs(C.Structure):
@@ -137,6 +138,7 @@ def make_params(params, precision="fp64", kernel="auto", seed=0):
     p.kernel = KERNELS[kernel]
     p.seed = seed
     p.recolor_fade = params.get("recolor_fade", 0.0)
+    p.fp16_arith64 = 1 if precision == "fp16s64" else 0
     return p
 
 

@@ -161,6 +161,8 @@ static const char* validate(const cge_params* p) {
     if (p->kernel < CGE_KERNEL_AUTO || p->kernel > CGE_KERNEL_RECORD) return "unknown kernel";
     if (!(is_fin(p->recolor_fade) && p->recolor_fade >= 0.0))
         return "recolor_fade must be finite and >= 0";
+    if (p->fp16_arith64 != 0 && !(p->fp16_arith64 == 1 && p->precision == CGE_FP16S))
+        return "fp16_arith64 must be 0, or 1 with CGE_FP16S";
     return nullptr;
 }
 
@@ -195,7 +197,8 @@ static ScratchPlan scratch_plan(const cge_params* p) {
     // records where the record form may run: selected, or chosen by AUTO (unit tau, D3Q19)
     const bool rec = unit && (p->kernel == CGE_KERNEL_RECORD ||
                               (p->kernel == CGE_KERNEL_AUTO && Q == 19));
-    const size_t mbytes = p->precision == CGE_FP16S ? 4 : 8;  // the widest use of the field
+    // the widest use of the field: the arithmetic type
+    const size_t mbytes = (p->precision == CGE_FP16S && !p->fp16_arith64) ? 4 : 8;
     const dim3 gr = node_grid(g);
     const size_t nblk = (size_t)gr.x * gr.y * gr.z;
     size_t off = 0;

@@ -184,8 +184,11 @@ Phys<M> phys(const cge_ctx* c);
                 return w_ ? FN<9, float, double, true>(__VA_ARGS__)                          \
                           : FN<9, float, double, false>(__VA_ARGS__);                        \
             case 92:                                                                        \
-                return w_ ? FN<9, _Float16, float, true>(__VA_ARGS__)                       \
-                          : FN<9, _Float16, float, false>(__VA_ARGS__);                     \
+                if ((c)->p.fp16_arith64)                                                    \
+                    return w_ ? FN<9, _Float16, double, true>(__VA_ARGS__)                   \
+                              : FN<9, _Float16, double, false>(__VA_ARGS__);                 \
+                return w_ ? FN<9, _Float16, float, true>(__VA_ARGS__)                        \
+                          : FN<9, _Float16, float, false>(__VA_ARGS__);                      \
             case 190:                                                                       \
                 return w_ ? FN<19, double, double, true>(__VA_ARGS__)                       \
                           : FN<19, double, double, false>(__VA_ARGS__);                     \
@@ -193,8 +196,11 @@ Phys<M> phys(const cge_ctx* c);
                 return w_ ? FN<19, float, double, true>(__VA_ARGS__)                         \
                           : FN<19, float, double, false>(__VA_ARGS__);                       \
             case 192:                                                                       \
-                return w_ ? FN<19, _Float16, float, true>(__VA_ARGS__)                      \
-                          : FN<19, _Float16, float, false>(__VA_ARGS__);                    \
+                if ((c)->p.fp16_arith64)                                                    \
+                    return w_ ? FN<19, _Float16, double, true>(__VA_ARGS__)                  \
+                              : FN<19, _Float16, double, false>(__VA_ARGS__);                \
+                return w_ ? FN<19, _Float16, float, true>(__VA_ARGS__)                       \
+                          : FN<19, _Float16, float, false>(__VA_ARGS__);                     \
             default:                                                                        \
                 return cge::fail((c), CGE_EUNSUPPORTED, "unsupported lattice/precision");   \
         }                                                                                   \

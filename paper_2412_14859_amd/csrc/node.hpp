@@ -93,6 +93,12 @@ template <>
 __device__ __forceinline__ _Float16 enc<_Float16, float>(float v, uint32_t bits) {
     return sr_half(v, bits);
 }
+// FP64 arithmetic into half storage: to FP32 by nearest (13 bits finer than half), then
+// stochastically to half
+template <>
+__device__ __forceinline__ _Float16 enc<_Float16, double>(double v, uint32_t bits) {
+    return sr_half(static_cast<float>(v), bits);
+}
 template <typename S, typename M>
 __device__ __forceinline__ void st(S* p, M v, uint32_t bits) {
     *p = enc<S, M>(v, bits);

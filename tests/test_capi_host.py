@@ -45,7 +45,10 @@ def _params(**over):
                                   dict(kernel=5), dict(kernel=-1),
                                   dict(site_rule=2, kappa=0.0), dict(site_rule=2, kappa=float("nan")),
                                   dict(sigma=-1.0), dict(phi=float("nan")),
-                                  dict(gamma=float("inf"))])
+                                  dict(gamma=float("inf")),
+                                  # FP64 arithmetic on half storage: 0 or 1, FP16S only
+                                  dict(fp16_arith64=1), dict(precision=1, fp16_arith64=1),
+                                  dict(precision=2, fp16_arith64=2)])
 def test_invalid_parameters_are_rejected_on_the_host(over):
     L = cgevap.lib()
     p = _params(**over)

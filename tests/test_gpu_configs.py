@@ -9,8 +9,9 @@
     x phi / Sbar (every term is that with a uniform flux and hard sites) to 1e-12; FP32
     storage within the 0.1 % volume bar (measured 3.2e-4, growing linearly: the record form's
     FP32 values shift red mass between the bulks by about 3e-8 of the volume per step); FP16
-    storage within 3e-3 (measured 2.1e-3: above the 0.1 % bar over this run, growing
-    linearly by 2e-7 of the volume per step)."""
+    storage with FP32 arithmetic within 3e-3 (measured 2.1e-3: above the 0.1 % bar over this
+    run, growing linearly by 2e-7 of the volume per step, from the FP32 arithmetic); FP16
+    storage with FP64 arithmetic within the 0.1 % bar (measured 2.8e-4, no trend)."""
 import os
 
 import pytest
@@ -51,7 +52,8 @@ def test_c2_fp64_run_matches_the_oracle_over_200_steps(name, phi):
     sim.close()
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32s", 1e-3), ("fp16s", 3e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32s", 1e-3), ("fp16s", 3e-3),
+                                           ("fp16s64", 1e-3)])
 def test_c3_downscale_against_the_oracle_over_10000_steps(precision, tol):
     import bench
     rows = bench.read_c3_fixture()
