@@ -40,7 +40,8 @@ PASS_KERNELS = ("k_moments", "k_finish", "k_finish_tile", "k_pull_record_zm", "k
 # source files of each kernel's launch (the record form's kernels live beside the split form's)
 KERNEL_FILE = {"k_moments": "split", "k_finish": "split", "k_finish_tile": "split",
                "k_pull_record_zm": "split", "k_pull_record": "split", "k_finish_record": "split",
-               "k_phase": "twopass", "k_collide": "twopass", "k_fused": "fused"}
+               "k_phase": "twopass", "k_collide": "twopass", "k_fused": "fused",
+               "k_adj_local_unit": "adjoint", "k_adj_gather": "adjoint", "k_adj_local": "adjoint"}
 
 
 def kernel_sources(kernel):
