@@ -62,7 +62,7 @@ static AdjWork adj_work(const cge_ctx* c, void* base, int parity, int nmu) {
 size_t adjoint_bytes(const cge_params* pr) {
     const long long N = (long long)pr->nx * pr->ny * pr->nz;
     const long long Q = pr->lattice;
-    const Geo g{pr->nx, pr->ny, pr->nz, N};
+    const Geo g{pr->nx, pr->ny, pr->nz, 0, N};
     const dim3 gr = node_grid(g);
     const long long nblk = (long long)gr.x * gr.y * gr.z;
     return (size_t)(2 * Q * N + 4 * N + 2 * N + 2 * N + 3 * N + nblk) * sizeof(double);

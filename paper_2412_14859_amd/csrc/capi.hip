@@ -192,7 +192,7 @@ static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
 static ScratchPlan scratch_plan(const cge_params* p) {
     ScratchPlan s;
     const int Q = p->lattice;
-    const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+    const Geo g{p->nx, p->ny, p->nz, 0, (long long)p->nx * p->ny * p->nz};
     const bool unit = p->tau[0] == 1.0 && p->tau[1] == 1.0;
     // records where the record form may run: selected, or chosen by AUTO (unit tau, D3Q19)
     const bool rec = unit && (p->kernel == CGE_KERNEL_RECORD ||
@@ -228,8 +228,16 @@ static cge_status create_ctx(const cge_params* params, void* hip_stream, void* s
     if (!c) return CGE_ENOMEM;
     c->p = *params;
     c->Q = params->lattice;
-    c->g = Geo{params->nx, params->ny, params->nz,
+    c->g = Geo{params->nx, params->ny, params->nz, 0,
                (long long)params->nx * params->ny * params->nz};
+    // non-temporal stores for each class of array a step writes that is too large to stay in
+    // the 256 MB last-level cache until it is read back (half of it taken as the bound): small
+    // grids keep their moments and populations cached between the kernels of a step
+    const size_t llc_half = 128ull << 20;
+    const size_t me = params->precision == CGE_FP64 ? 8 : 4;
+    if (2ull * c->Q * (size_t)c->g.N * elem_bytes(params->precision) > llc_half) c->g.nt |= kNtPop;
+    if (5ull * (size_t)c->g.N * me > llc_half) c->g.nt |= kNtMom;
+    if (record_bytes(params) > llc_half) c->g.nt |= kNtRec;
     c->stream = static_cast<hipStream_t>(hip_stream);
     if (hipGetDevice(&c->device) != hipSuccess ||
         hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) !=

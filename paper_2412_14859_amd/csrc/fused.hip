@@ -89,11 +89,12 @@ __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >
 __device__ __forceinline__ int wrapf(int v, int n) { return ((v % n) + n) % n; }
 
 // Loads and stores of one storage element through a buffer resource at byte offset
-// voff (per lane) + soff (uniform).  Stores are non-temporal (cache policy bit 1, as
-// __builtin_nontemporal_store gives the other step forms): the written populations are read
-// only by the next step, long after a plane's lines would have left L2, and left to allocate
-// normally they evict the ring rows that neighbouring tiles are about to re-read (the
-// 384 x 384 x 192 sessile drop: 2.54 -> 2.42 ms per step).
+// voff (per lane) + soff (uniform).  Stores of populations too large to stay in the
+// last-level cache (Geo::nt kNtPop) are non-temporal (cache policy bit 1, as
+// __builtin_nontemporal_store gives the other step forms): they are read only by the next
+// step, long after a plane's lines would have left L2, and left to allocate normally they
+// evict the ring rows that neighbouring tiles are about to re-read (the 384 x 384 x 192
+// sessile drop: 2.54 -> 2.42 ms per step).
 constexpr int kStoreNT = 2;
 template <typename S>
 struct Buf;
@@ -103,8 +104,11 @@ struct Buf<float> {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
     }
     static __device__ __forceinline__ void st(float x, __amdgpu_buffer_rsrc_t r, uint32_t v,
-                                              uint32_t s) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, kStoreNT);
+                                              uint32_t s, bool nt) {
+        if (nt)
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, kStoreNT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, 0);
     }
 };
 template <>
@@ -114,8 +118,11 @@ struct Buf<double> {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
     }
     static __device__ __forceinline__ void st(double x, __amdgpu_buffer_rsrc_t r, uint32_t v,
-                                              uint32_t s) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, v, s, kStoreNT);
+                                              uint32_t s, bool nt) {
+        if (nt)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, v, s, kStoreNT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, v, s, 0);
     }
 };
 template <>
@@ -125,8 +132,11 @@ struct Buf<_Float16> {
         return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
     }
     static __device__ __forceinline__ void st(_Float16 x, __amdgpu_buffer_rsrc_t r, uint32_t v,
-                                              uint32_t s) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), r, v, s, kStoreNT);
+                                              uint32_t s, bool nt) {
+        if (nt)
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), r, v, s, kStoreNT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, x), r, v, s, 0);
     }
 };
 
@@ -237,7 +247,7 @@ __device__ __forceinline__ void ring_at(int t, int d, int w, int h, int& rx, int
 }
 
 // PW: the solid flags are plane walls, described per plane by pkind.
-template <int Q, typename S, typename M, bool UNIT, bool PW>
+template <int Q, typename S, typename M, bool UNIT, bool PW, bool NTS>
 __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
     const S* __restrict__ src, S* __restrict__ dst, const uint8_t* __restrict__ cin,
     uint8_t* __restrict__ cout, const void* __restrict__ phi_field,
@@ -256,6 +266,7 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
 
     const int tid = threadIdx.x;
     const int lx = tid % kFTX, ly = tid / kFTX;
+    constexpr bool nt = NTS;
     const unsigned nb = gridDim.x, bid = blockIdx.x;
     const unsigned xq = nb / kXcds, xrem = nb % kXcds, xk = bid % kXcds;
     const long long b = (long long)(xk * xq + (xk < xrem ? xk : xrem) + bid / kXcds);
@@ -443,8 +454,8 @@ __global__ __launch_bounds__(kFTX* kFTY) void k_fused(
                     rN, u, F, P,
                     [&](int i, M a, M d) {
                         const uint32_t so = (uint32_t)i * slot_bytes + zo;
-                        Buf<S>::st(enc<S, M>(a, sr_bits(salt, g.N, n, 2 * i)), dft, vo, so);
-                        Buf<S>::st(enc<S, M>(d, sr_bits(salt, g.N, n, 2 * i + 1)), ddd, vo, so);
+                        Buf<S>::st(enc<S, M>(a, sr_bits(salt, g.N, n, 2 * i)), dft, vo, so, nt);
+                        Buf<S>::st(enc<S, M>(d, sr_bits(salt, g.N, n, 2 * i + 1)), ddd, vo, so, nt);
                     });
                 cout[n] = Fn > P.gamma ? 1 : 0;
             }
@@ -568,16 +579,19 @@ static cge_status fused_impl(cge_ctx* c, long long nsteps) {
             S* dst = static_cast<S*>(c->pop[1 - c->cur]);
             const uint64_t salt = mix64(seedmix + (uint64_t)c->step) * 0x100000001B3ull;
             timing_begin(c, "fused step");
-            if (unit)
-                hipLaunchKernelGGL((k_fused<Q, S, M, true, WALLS>), dim3((unsigned)fs.nb),
-                                   dim3(kFTX * kFTY), kbytes, c->stream, src, dst, mask[m],
-                                   mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites, c->g,
-                                   P, salt, fs);
-            else
-                hipLaunchKernelGGL((k_fused<Q, S, M, false, WALLS>), dim3((unsigned)fs.nb),
-                                   dim3(kFTX * kFTY), kbytes, c->stream, src, dst, mask[m],
-                                   mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites, c->g,
-                                   P, salt, fs);
+            by_policy(c->g.nt, kNtPop, [&](auto nts) {
+                constexpr bool NTS = decltype(nts)::value;
+                if (unit)
+                    hipLaunchKernelGGL((k_fused<Q, S, M, true, WALLS, NTS>), dim3((unsigned)fs.nb),
+                                       dim3(kFTX * kFTY), kbytes, c->stream, src, dst, mask[m],
+                                       mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites,
+                                       c->g, P, salt, fs);
+                else
+                    hipLaunchKernelGGL((k_fused<Q, S, M, false, WALLS, NTS>), dim3((unsigned)fs.nb),
+                                       dim3(kFTX * kFTY), kbytes, c->stream, src, dst, mask[m],
+                                       mask[1 - m], c->phi_field, pk, c->acc_sink, c->acc_sites,
+                                       c->g, P, salt, fs);
+            });
             timing_pass(c, "k_fused");
             timing_end(c);
             if (cge_status s = check(c, hipGetLastError(), "fused step launch")) return s;

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace cge {
 
@@ -102,8 +103,25 @@ __host__ __device__ __forceinline__ M recolor_fade_slope(M Fn, M inv_fade) {
     return (g > M(0) && g < M(1)) ? inv_fade : M(0);
 }
 
+// Store policy of the step kernels (Geo::nt): which of the arrays a pass writes for the next
+// pass go out with the non-temporal cache policy (kNtPop populations, kNtMom the moment
+// record between the two passes, kNtRec the post-collision records).  The kernels take their
+// bit as a template argument (by_policy picks the instance at launch): a uniform branch
+// around every store costs 3-10 % in the hot kernels.
+enum : int { kNtPop = 1, kNtMom = 2, kNtRec = 4 };
+
+// f(std::true_type) where bit is set in policy, else f(std::false_type)
+template <typename F>
+inline void by_policy(int policy, int bit, F&& f) {
+    if (policy & bit)
+        f(std::true_type{});
+    else
+        f(std::false_type{});
+}
+
 struct Geo {
     int nx, ny, nz;
+    int nt;  // store policy (kNt* bits), in the padding before N
     long long N;
 };
 

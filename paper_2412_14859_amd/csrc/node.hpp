@@ -103,10 +103,23 @@ template <typename S, typename M>
 __device__ __forceinline__ void st(S* p, M v, uint32_t bits) {
     *p = enc<S, M>(v, bits);
 }
-// The same with a streaming (non-temporal) hint: the value is not read again in this step.
-template <typename S, typename M>
+// The same with a streaming (non-temporal) hint where NT: the value is not read again in
+// this step.  The policy is a template argument: with a run-time flag the compiler merges
+// the two stores of the branch into one and drops the hint.
+template <bool NT, typename S, typename M>
 __device__ __forceinline__ void st_nt(S* p, M v, uint32_t bits) {
-    __builtin_nontemporal_store(enc<S, M>(v, bits), p);
+    if constexpr (NT)
+        __builtin_nontemporal_store(enc<S, M>(v, bits), p);
+    else
+        *p = enc<S, M>(v, bits);
+}
+// a value stored with the streaming hint where NT
+template <bool NT, typename T>
+__device__ __forceinline__ void st_pol(T* p, T v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
 
 // neighbour coordinates with periodic wrap

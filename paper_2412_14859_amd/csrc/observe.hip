@@ -279,7 +279,7 @@ static hipError_t noalloc_impl(const cge_params* p, const void* pop, const uint8
     cge_ctx tmp;  // host-side constants only: phys() reads the parameters and lattice
     tmp.p = *p;
     tmp.Q = Q;
-    const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+    const Geo g{p->nx, p->ny, p->nz, 0, (long long)p->nx * p->ny * p->nz};
     double* res = reinterpret_cast<double*>(base);
     double* part = reinterpret_cast<double*>(base + kNoallocRes);
     hipError_t e = obs_launch<Q, S, WALLS>(static_cast<const S*>(pop), flags, carry, part, res,
@@ -292,7 +292,7 @@ static hipError_t noalloc_impl(const cge_params* p, const void* pop, const uint8
 
 size_t noalloc_limit_bytes() { return kNoallocScratch - kNoallocRes; }
 size_t noalloc_need_bytes(const cge_params* p) {
-    const Geo g{p->nx, p->ny, p->nz, (long long)p->nx * p->ny * p->nz};
+    const Geo g{p->nx, p->ny, p->nz, 0, (long long)p->nx * p->ny * p->nz};
     return obs_scratch_bytes(g);
 }
 

@@ -19,22 +19,26 @@
 namespace cge {
 
 // The moment record of node n between the two passes: rho^N and (delta rho, j), stored at
-// the record's precision T.  The stores are non-temporal: the next pass reads them after the
-// rest of this pass's traffic, and allocated normally in L2 they only displace the data
-// this pass re-reads (measured: the FP32 finish from records 0.304 -> 0.285 ms at 256^3).
-template <typename T, typename V, typename W>
+// the record's precision T.  Where the record is too large to stay in the last-level cache
+// (Geo::nt kNtMom) the stores are non-temporal: the next pass reads them after the rest of
+// this pass's traffic, and allocated normally they only displace the data this pass
+// re-reads (measured: the FP32 finish from records 0.304 -> 0.285 ms at 256^3).  A record
+// that fits stays cached for the next pass (non-temporal, the 1024^2 D2Q9 split step ran
+// 20 % slower).
+template <bool NTS, typename T, typename V, typename W>
 __device__ __forceinline__ void store_moments(T* __restrict__ rhoN, T* __restrict__ mom,
-                                              long long N, long long n, V rn, W drho,
+                                              const Geo& g, long long n, V rn, W drho,
                                               const W (&j)[3]) {
-    __builtin_nontemporal_store(static_cast<T>(rn), rhoN + n);
-    __builtin_nontemporal_store(static_cast<T>(drho), mom + n);
-    __builtin_nontemporal_store(static_cast<T>(j[0]), mom + N + n);
-    __builtin_nontemporal_store(static_cast<T>(j[1]), mom + 2 * N + n);
-    __builtin_nontemporal_store(static_cast<T>(j[2]), mom + 3 * N + n);
+    const long long N = g.N;
+    st_pol<NTS>(rhoN + n, static_cast<T>(rn));
+    st_pol<NTS>(mom + n, static_cast<T>(drho));
+    st_pol<NTS>(mom + N + n, static_cast<T>(j[0]));
+    st_pol<NTS>(mom + 2 * N + n, static_cast<T>(j[1]));
+    st_pol<NTS>(mom + 3 * N + n, static_cast<T>(j[2]));
 }
 
 // Pass 1: pull, sink, moments; FP64 sink bookkeeping per block.
-template <int Q, typename S, typename M, bool WALLS>
+template <int Q, typename S, typename M, bool WALLS, bool NTS>
 __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
                                                    const uint8_t* __restrict__ flags,
                                                    const void* __restrict__ carry,
@@ -75,7 +79,7 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
         dsum -= M(2) * s;
         v[0] = static_cast<double>(s);
         v[1] = is_site(wgt) ? 1.0 : 0.0;
-        store_moments(rhoN, mom, g.N, n, dsum / rho, drho, j);
+        store_moments<NTS>(rhoN, mom, g, n, dsum / rho, drho, j);
     }
     const bool is_max[2] = {false, false};
     double out[2];
@@ -91,7 +95,7 @@ __global__ __launch_bounds__(kTPBX) void k_moments(const S* __restrict__ src,
 // Pass 2: gradient, equilibrium, perturbation, recolouring, store, next site mask.
 // At least 5 waves per SIMD (the register budget allows it without spills): more stores in
 // flight.
-template <int Q, typename S, typename M, bool WALLS>
+template <int Q, typename S, typename M, bool WALLS, bool NTS>
 __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_finish(S* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
                                                   void* __restrict__ carry,
@@ -140,9 +144,9 @@ __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) v
                                      [&](int i, M a, M d) {
                                          S* pa = uniform_ptr(dst + (long long)i * g.N + row);
                                          S* pd = uniform_ptr(dst + (long long)(Q + i) * g.N + row);
-                                         st_nt(reinterpret_cast<S*>(reinterpret_cast<char*>(pa) + xb), a,
+                                         st_nt<NTS>(reinterpret_cast<S*>(reinterpret_cast<char*>(pa) + xb), a,
                                                sr_bits(salt, g.N, n, 2 * i));
-                                         st_nt(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
+                                         st_nt<NTS>(reinterpret_cast<S*>(reinterpret_cast<char*>(pd) + xb), d,
                                                sr_bits(salt, g.N, n, 2 * i + 1));
                                      });
     carry_store(P, carry, n, Fn);
@@ -160,7 +164,7 @@ constexpr int kTileX = 64, kTileY = 4;
 
 __device__ __forceinline__ int wrapm(int v, int n) { return ((v % n) + n) % n; }
 
-template <typename S, typename M>
+template <typename S, typename M, bool NTS>
 __global__ __launch_bounds__(kTileX* kTileY) __attribute__((amdgpu_waves_per_eu(5, 8))) void
 k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const MomT<S>* __restrict__ rhoN,
               const MomT<S>* __restrict__ mom, Geo g, Phys<M> P, uint64_t salt) {
@@ -199,8 +203,8 @@ k_finish_tile(S* __restrict__ dst, void* __restrict__ carry, const MomT<S>* __re
                     static_cast<M>(mom[3 * g.N + n]) * inv_rho};
     const M Fn = collide<Q, M, true>([](int) { return M(0); }, drho, rho, tile[1][1 + ty][1 + tx],
                                      u, F, P, [&](int i, M a, M d) {
-                                         st_nt(dst + (long long)i * g.N + n, a, sr_bits(salt, g.N, n, 2 * i));
-                                         st_nt(dst + (long long)(Q + i) * g.N + n, d,
+                                         st_nt<NTS>(dst + (long long)i * g.N + n, a, sr_bits(salt, g.N, n, 2 * i));
+                                         st_nt<NTS>(dst + (long long)(Q + i) * g.N + n, d,
                                                sr_bits(salt, g.N, n, 2 * i + 1));
                                      });
     carry_store(P, carry, n, Fn);
@@ -250,7 +254,7 @@ __device__ __forceinline__ M ref_part(const Phys<M>& P, const M (&rn)[3]) {
 // Pass 1 from records: pull (Eq. Stream) with every population rebuilt from the record of
 // x - c_i (of x itself, opposite direction, where x - c_i is solid), then the sink and the
 // moments exactly as k_moments.
-template <int Q, typename S, typename M, bool WALLS>
+template <int Q, typename S, typename M, bool WALLS, bool NTS>
 __global__ __launch_bounds__(kTPBX) void k_pull_record(const RecT<S>* __restrict__ rec,
                                                        const uint8_t* __restrict__ flags,
                                                        const void* __restrict__ carry,
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(kTPBX) void k_pull_record(const RecT<S>* __restrict
         dsum -= M(2) * s;
         v[0] = static_cast<double>(s);
         v[1] = is_site(wgt) ? 1.0 : 0.0;
-        store_moments(rhoN, mom, g.N, n, dsum / rho, drho, j);
+        store_moments<NTS>(rhoN, mom, g, n, dsum / rho, drho, j);
     }
     const bool is_max[2] = {false, false};
     double out[2];
@@ -428,7 +432,7 @@ constexpr CzList cz_list(int cz) {
 template <typename S, int TY>
 using ZmOf = Zm<TY, RecE<RecT<S>>>;
 
-template <typename S, typename M, bool WALLS, int TY>
+template <typename S, typename M, bool WALLS, int TY, bool NTS>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(ZmOf<S, TY>::Waves, ZmOf<S, TY>::Waves))) void
 k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
                  const void* __restrict__ carry, const void* __restrict__ phi_field,
@@ -700,7 +704,7 @@ k_pull_record_zm(const RecT<S>* __restrict__ rec, const uint8_t* __restrict__ fl
             const long long n = node(p - 1);
             v[0] += static_cast<double>(s);
             v[1] += is_site(wgt) ? 1.0 : 0.0;
-            store_moments(rhoN, mom, g.N, n, (dsum - M(2) * s) / rho, prev.drho, prev.j);
+            store_moments<NTS>(rhoN, mom, g, n, (dsum - M(2) * s) / rho, prev.drho, prev.j);
         }
         // node p: the directions with c_z = 0 (from the node's own record where the source is
         // solid), then those with c_z = +-1 whose source is solid
@@ -778,7 +782,7 @@ static dim3 zm_grid(const Geo& g, int zc) {
 
 // Pass 2 to records: gradient and moments as k_finish, then the node's record instead of its
 // populations, and the next site data.
-template <int Q, typename S, typename M, bool WALLS>
+template <int Q, typename S, typename M, bool WALLS, bool NTS>
 __global__ __launch_bounds__(kTPBX) __attribute__((amdgpu_waves_per_eu(5, 8))) void
 k_finish_record(RecT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
                 void* __restrict__ carry, const MomT<S>* __restrict__ rhoN,
@@ -823,7 +827,7 @@ k_finish_record(RecT<S>* __restrict__ rec, const uint8_t* __restrict__ flags,
     for (int sl = 0; sl < kRec; ++sl) {
         if (Q == 9 && (sl == kUz || sl == kNz)) continue;  // no z component in 2D
         // half records round stochastically, like half populations
-        __builtin_nontemporal_store(enc<R, M>(rv[sl], sr_bits(salt, g.N, n, sl)), at + sl * L::W);
+        st_pol<NTS>(at + sl * L::W, enc<R, M>(rv[sl], sr_bits(salt, g.N, n, sl)));
     }
     carry_store(P, carry, n, Fn);
 }
@@ -849,19 +853,26 @@ static cge_status split_one(cge_ctx* c, const void* carry_in, void* carry_out, v
     S* dst = static_cast<S*>(c->pop[1 - c->cur]);
     const uint64_t salt = mix64(mix64(c->p.seed) + (uint64_t)c->step) * 0x100000001B3ull;
     timing_begin(c, "split step");
-    hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
-                       carry_in, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
+    by_policy(c->g.nt, kNtMom, [&](auto nts) {
+        hipLaunchKernelGGL((k_moments<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0, c->stream,
+                           src, c->flags, carry_in, c->phi_field, rhoN, mom, c->acc_sink,
+                           c->acc_sites, c->g, P);
+    });
     if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
     timing_pass(c, "k_moments");
     if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
         const dim3 tb(kTileX, kTileY, 1);
         const dim3 tg((c->g.nx + kTileX - 1) / kTileX, (c->g.ny + kTileY - 1) / kTileY, c->g.nz);
-        hipLaunchKernelGGL((k_finish_tile<S, M>), tg, tb, 0, c->stream, dst, carry_out, rhoN, mom,
-                           c->g, P, salt);
+        by_policy(c->g.nt, kNtPop, [&](auto nts) {
+            hipLaunchKernelGGL((k_finish_tile<S, M, decltype(nts)::value>), tg, tb, 0, c->stream,
+                               dst, carry_out, rhoN, mom, c->g, P, salt);
+        });
         timing_pass(c, "k_finish_tile");
     } else {
-        hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
-                           carry_out, rhoN, mom, c->g, P, salt);
+        by_policy(c->g.nt, kNtPop, [&](auto nts) {
+            hipLaunchKernelGGL((k_finish<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0,
+                               c->stream, dst, c->flags, carry_out, rhoN, mom, c->g, P, salt);
+        });
         timing_pass(c, "k_finish");
     }
     timing_end(c);
@@ -912,43 +923,56 @@ static cge_status record_one(cge_ctx* c, bool first, bool last) {
                           : (last ? "record step (to populations)" : "record step"));
     const char* pass1 = "k_moments";
     if (first)
-        hipLaunchKernelGGL((k_moments<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, c->flags,
-                           c->carry, c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P);
+        by_policy(c->g.nt, kNtMom, [&](auto nts) {
+            hipLaunchKernelGGL((k_moments<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0,
+                               c->stream, src, c->flags, c->carry, c->phi_field, rhoN, mom,
+                               c->acc_sink, c->acc_sites, c->g, P);
+        });
     else {
         bool marched = false;
         if constexpr (Q == 19) {
             if (zm_ok<RecT<S>>(c)) {
                 const int zc = zm_chunk<RecE<RecT<S>>>(c);
-                hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS, kZmY>), zm_grid(c->g, zc),
-                                   dim3(Zm<kZmY>::X, kZmY, 1), 0, c->stream, rec, c->flags, c->carry,
-                                   c->phi_field, rhoN, mom, c->acc_sink, c->acc_sites, c->g, P,
-                                   zc);
+                by_policy(c->g.nt, kNtMom, [&](auto nts) {
+                    hipLaunchKernelGGL((k_pull_record_zm<S, M, WALLS, kZmY, decltype(nts)::value>),
+                                       zm_grid(c->g, zc), dim3(Zm<kZmY>::X, kZmY, 1), 0, c->stream,
+                                       rec, c->flags, c->carry, c->phi_field, rhoN, mom,
+                                       c->acc_sink, c->acc_sites, c->g, P, zc);
+                });
                 marched = true;
                 pass1 = "k_pull_record_zm";
             }
         }
         if (!marched) {
-            hipLaunchKernelGGL((k_pull_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec,
-                               c->flags, c->carry, c->phi_field, rhoN, mom, c->acc_sink,
-                               c->acc_sites, c->g, P);
+            by_policy(c->g.nt, kNtMom, [&](auto nts) {
+                hipLaunchKernelGGL((k_pull_record<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0,
+                                   c->stream, rec, c->flags, c->carry, c->phi_field, rhoN, mom,
+                                   c->acc_sink, c->acc_sites, c->g, P);
+            });
             pass1 = "k_pull_record";
         }
     }
     if (WALLS) hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
     timing_pass(c, pass1);
     if (!last) {
-        hipLaunchKernelGGL((k_finish_record<Q, S, M, WALLS>), gr, bl, 0, c->stream, rec, c->flags,
-                           c->carry, rhoN, mom, c->g, P, salt);
+        by_policy(c->g.nt, kNtRec, [&](auto nts) {
+            hipLaunchKernelGGL((k_finish_record<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0,
+                               c->stream, rec, c->flags, c->carry, rhoN, mom, c->g, P, salt);
+        });
         timing_pass(c, "k_finish_record");
     } else if constexpr (Q == 19 && !WALLS && std::is_same<S, double>::value) {
         const dim3 tb(kTileX, kTileY, 1);
         const dim3 tg((c->g.nx + kTileX - 1) / kTileX, (c->g.ny + kTileY - 1) / kTileY, c->g.nz);
-        hipLaunchKernelGGL((k_finish_tile<S, M>), tg, tb, 0, c->stream, dst, c->carry, rhoN, mom,
-                           c->g, P, salt);
+        by_policy(c->g.nt, kNtPop, [&](auto nts) {
+            hipLaunchKernelGGL((k_finish_tile<S, M, decltype(nts)::value>), tg, tb, 0, c->stream,
+                               dst, c->carry, rhoN, mom, c->g, P, salt);
+        });
         timing_pass(c, "k_finish_tile");
     } else {
-        hipLaunchKernelGGL((k_finish<Q, S, M, WALLS>), gr, bl, 0, c->stream, dst, c->flags,
-                           c->carry, rhoN, mom, c->g, P, salt);
+        by_policy(c->g.nt, kNtPop, [&](auto nts) {
+            hipLaunchKernelGGL((k_finish<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0,
+                               c->stream, dst, c->flags, c->carry, rhoN, mom, c->g, P, salt);
+        });
         timing_pass(c, "k_finish");
     }
     timing_end(c);

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kTPBX) void k_carry(const uint8_t* __restrict__ fla
 }
 
 // Pass 2: the full step at one node.
-template <int Q, typename S, typename M, bool WALLS>
+template <int Q, typename S, typename M, bool WALLS, bool NTS>
 __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S* __restrict__ dst,
                                                    const uint8_t* __restrict__ flags,
                                                    void* __restrict__ carry,
@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kTPBX) void k_collide(const S* __restrict__ src, S*
         gradient<Q>(rhoN, g, b, x, y, z, F);
         const M Fn = collide<Q>([&](int i) { return ft[i]; }, drho, rho, rN, u, F, P,
                                 [&](int i, M a, M d) {
-                                    st_nt(dst + (long long)i * g.N + n, a, sr_bits(salt, g.N, n, 2 * i));
-                                    st_nt(dst + (long long)(Q + i) * g.N + n, d,
+                                    st_nt<NTS>(dst + (long long)i * g.N + n, a, sr_bits(salt, g.N, n, 2 * i));
+                                    st_nt<NTS>(dst + (long long)(Q + i) * g.N + n, d,
                                           sr_bits(salt, g.N, n, 2 * i + 1));
                                 });
         carry_store<M>(P, carry, n, Fn);
@@ -121,9 +121,11 @@ static cge_status twopass_impl(cge_ctx* c, long long nsteps) {
         if (WALLS)
             hipLaunchKernelGGL((k_wet<Q, MomT<S>>), gr, bl, 0, c->stream, c->flags, rhoN, c->g);
         timing_pass(c, "k_phase");
-        hipLaunchKernelGGL((k_collide<Q, S, M, WALLS>), gr, bl, 0, c->stream, src, dst, c->flags,
-                           c->carry, c->phi_field, rhoN, c->acc_sink, c->acc_sites, c->g, P,
-                           salt);
+        by_policy(c->g.nt, kNtPop, [&](auto nts) {
+            hipLaunchKernelGGL((k_collide<Q, S, M, WALLS, decltype(nts)::value>), gr, bl, 0,
+                               c->stream, src, dst, c->flags, c->carry, c->phi_field, rhoN,
+                               c->acc_sink, c->acc_sites, c->g, P, salt);
+        });
         timing_pass(c, "k_collide");
         timing_end(c);
         if (cge_status s = check(c, hipGetLastError(), "step kernel launch")) return s;
