@@ -106,8 +106,8 @@ __host__ __device__ __forceinline__ M recolor_fade_slope(M Fn, M inv_fade) {
 // Store policy of the step kernels (Geo::nt): which of the arrays a pass writes for the next
 // pass go out with the non-temporal cache policy (kNtPop populations, kNtMom the moment
 // record between the two passes, kNtRec the post-collision records).  The kernels take their
-// bit as a template argument (by_policy picks the instance at launch): a uniform branch
-// around every store costs 3-10 % in the hot kernels.
+// bit as a template argument (by_policy picks the instance at launch): given a run-time
+// flag, the compiler merged the two stores of each branch into one plain store.
 enum : int { kNtPop = 1, kNtMom = 2, kNtRec = 4 };
 
 // f(std::true_type) where bit is set in policy, else f(std::false_type)
