@@ -89,8 +89,8 @@ typedef enum { CGE_SITE_GRAD_GT = 0, CGE_SITE_PHASE_LT = 1, CGE_SITE_SOFT = 2 } 
  *            library scratch in that type (rows padded to 256 B), allocated at cge_create for
  *            RECORD, and for AUTO where AUTO selects it.
  *   AUTO:    at unit relaxation times RECORD for D3Q19 and SPLIT for D2Q9 (where the record
- *            pull has no LDS-staged form and is no faster); otherwise FUSED where supported,
- *            else TWOPASS.
+ *            pull has no LDS-staged form and is no faster); otherwise FUSED where supported
+ *            at FP32 or FP16 storage (at FP64 it is about three times slower), else TWOPASS.
  * All give the same results up to rounding. */
 typedef enum {
     CGE_KERNEL_AUTO = 0,

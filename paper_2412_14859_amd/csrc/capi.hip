@@ -338,8 +338,12 @@ cge_status cge_bind(cge_ctx* c, void* pop_a, void* pop_b, unsigned char* carry,
         case CGE_KERNEL_SPLIT: c->kernel = CGE_KERNEL_SPLIT; break;
         case CGE_KERNEL_RECORD: c->kernel = CGE_KERNEL_RECORD; break;
         default:
+            // the fused step only below FP64: at FP64 its per-thread population stash takes
+            // most of a CU's LDS, and it ran about three times slower than the two-pass step
+            // (256 x 256 x 128 sessile drop: 4.22 against 1.47 ms per step)
             c->kernel = split_supported(c) ? (c->rec ? CGE_KERNEL_RECORD : CGE_KERNEL_SPLIT)
-                               : (fused_supported(c) ? CGE_KERNEL_FUSED : CGE_KERNEL_TWOPASS);
+                        : (fused_supported(c) && c->p.precision != CGE_FP64 ? CGE_KERNEL_FUSED
+                                                                             : CGE_KERNEL_TWOPASS);
     }
     c->bound = true;
     return CGE_OK;
